@@ -1,0 +1,214 @@
+/*
+ * ri.h - C ABI of libri, an MI355X (gfx950) implementation of the
+ * resolution-of-the-identity Hartree-Fock hot path: RI J/K Fock builds and
+ * the RI-HF analytic gradient (Stocks, Palethorpe, Barca, "Multi-GPU RI-HF
+ * Energies and Analytic Gradients", arXiv 2407.19614).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Basis functions are normalised primitive s-Gaussians
+ *   phi(r) = (2a/pi)^{3/4} exp(-a |r - A|^2); auxiliary functions likewise.
+ *   One function per shell.
+ * - All device pointers are allocated and owned by the caller; the library
+ *   never allocates device memory and keeps no global state.  Scratch memory
+ *   comes from `ws` (device, >= 256-byte aligned) of `ws_bytes` bytes, sized
+ *   by ri_workspace_bytes().  Calls that take a `hipStream_t` enqueue all
+ *   their work on that stream; only calls that return host scalars
+ *   synchronise that stream.
+ * - Matrices are row-major FP64 unless stated.  N = number of orbital basis
+ *   functions, n_aux = number of auxiliary functions, n_occ = number of doubly
+ *   occupied orbitals.
+ * - Sign of exchange: K = +sum_P X^P X^P^T (positive semidefinite) with
+ *   X^P = B^P C_occ; the Fock matrix is F = h + J - K.  The paper's exchange
+ *   term (eq. k) is -K.
+ * - Factor convention (eq. symmetric_ri / eq. biap): A = L L^T with L lower
+ *   triangular, B^P = sum_Q [L^{-1}]_PQ (mu nu|Q).  The paper's A^L is L^{-T}.
+ * - Errors: every entry point returns an ri_status; no exception crosses the
+ *   ABI, nothing is printed and nothing aborts.  On RI_E_HIP the HIP error
+ *   text is available from ri_last_hip_error().
+ */
+#ifndef RI_H
+#define RI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RI_OK = 0,
+    RI_E_ARG = 1,          /* NULL pointer, negative or inconsistent size     */
+    RI_E_NOT_PD = 2,       /* metric or overlap not positive definite         */
+    RI_E_NO_CONV = 3,      /* SCF did not converge within max_iter            */
+    RI_E_WORKSPACE = 4,    /* ws_bytes smaller than ri_workspace_bytes()      */
+    RI_E_CAPACITY = 5,     /* pair capacity too small (count is returned)     */
+    RI_E_HIP = 6,          /* a HIP runtime call failed                       */
+    RI_E_UNSUPPORTED = 7   /* option not supported (e.g. unknown precision)   */
+} ri_status;
+
+/* Storage precision of the packed B tensor and arithmetic of the X / K
+ * contractions (project extension; FP64 is the paper's precision). */
+typedef enum {
+    RI_FP64 = 0,     /* B in FP64, FP64 MFMA                                  */
+    RI_FP32 = 1,     /* B in FP32, FP32 MFMA, FP32 accumulation per P-chunk,  */
+                     /* FP64 across chunks                                    */
+    RI_BF16X3 = 2    /* B split as hi + lo bfloat16; products hi*hi + hi*lo + */
+                     /* lo*hi on BF16 MFMA with FP32 accumulation per chunk,  */
+                     /* FP64 across chunks                                    */
+} ri_precision;
+
+/* Molecular system.  The struct lives in host memory; every array is a
+ * device pointer.  Positions in bohr. */
+typedef struct {
+    int32_t n_centres;
+    int32_t n_fn;                 /* N                                       */
+    int32_t n_aux;                /* N_aux                                   */
+    int32_t n_occ;                /* doubly occupied orbitals                */
+    const double* xyz;            /* [n_centres][3]                          */
+    const double* Z;              /* [n_centres] nuclear charges             */
+    const int32_t* fn_centre;     /* [N] centre index of each function       */
+    const double* fn_exp;         /* [N] exponent of each function           */
+    const int32_t* aux_centre;    /* [N_aux]                                 */
+    const double* aux_exp;        /* [N_aux]                                 */
+} ri_system;
+
+/* Packed B tensor geometry.  B^P is symmetric in (mu, nu) (the paper's
+ * Symmetry-utilisation section) and is stored as the lower triangle of
+ * 64 x 64 tiles: tile (I, J), I >= J, has index I(I+1)/2 + J and holds
+ * B^P[64I + r][64J + c] at offset r*64 + c; entries beyond N are zero.
+ * Layout [n_aux][n_tiles][64*64] of the storage type (double, float, or for
+ * RI_BF16X3 two planes of uint16 bfloat16 words: the hi plane for all P
+ * followed by the lo plane).  ri_packed_b_bytes() returns the size. */
+#define RI_TILE 64
+size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec);
+
+/* ri_build_3c - Schwarz screening of orbital pairs and the three-centre
+ * integrals (mu nu|P) over the significant pairs.
+ * Paper: definitions of the two- and three-centre ERIs (Notation section);
+ * basis-function pair screening (Basis-function pair sparsity section): a
+ * pair is dropped when (mu nu|mu nu) <= tau; Algorithm 1, three-centre ERI
+ * computation for each auxiliary batch.
+ *   pairs   [cap][2] int32 (device, out): significant pairs (mu, nu), mu >= nu,
+ *           ordered by mu, then nu.
+ *   cap     capacity of `pairs` (and the column count T was sized for).
+ *   n_pairs (host, out): number of significant pairs.  If it exceeds cap the
+ *           call returns RI_E_CAPACITY and writes nothing else.
+ *   T       [n_aux][n_pairs] (device, out; row stride n_pairs), or NULL to
+ *           only screen.
+ * Synchronises `stream` once to read the pair count.
+ * Workspace: ri_workspace_bytes(RI_OP_BUILD_3C, ...). */
+int32_t ri_build_3c(const ri_system* sys, double tau, int32_t* pairs, int64_t cap,
+                    int64_t* n_pairs, double* T, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* ri_metric_factor - the Coulomb metric A_PQ = (P|Q), its Cholesky factor
+ * A = L L^T (FP64), the fitted tensor on compressed pairs
+ * Bc = L^{-1} T (overwrites T in place), and the packed ("decompressed")
+ * B tensor in precision `prec`.
+ * Paper: eq. symmetric_ri and eq. biap (Cholesky of the metric, B formation);
+ * Algorithm 1 lines forming B and decompressing it once when memory allows.
+ *   T_inout [n_aux][n_pairs] in: (mu nu|P); out: Bc.
+ *   L       [n_aux][n_aux] out: lower factor (upper triangle zeroed).
+ *   Linv    [n_aux][n_aux] out: L^{-1} (lower).
+ *   B       packed B (see above), out; may be NULL to skip packing.
+ *   bad_pivot (host, out): -1, or the first auxiliary index whose pivot is
+ *           not positive (then RI_E_NOT_PD is returned).
+ * Synchronises `stream` once (pivot check). */
+int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
+                         double* T_inout, double* L, double* Linv, void* B, int32_t prec,
+                         int64_t* bad_pivot, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ri_fock_jk - one RI Fock build: Coulomb J and exchange K for the density
+ * D = 2 C_occ C_occ^T.
+ * Paper: eq. j_ri (gamma_P = sum B^P_mu_nu D_mu_nu, J = sum_P gamma_P B^P),
+ * eq. k_ri_2 and eq. tp (X^P = B^P C_occ, K = sum_P X^P X^P^T), Algorithm 1
+ * Fock-build loop, symmetric GEMM for the lower triangle of K (Symmetry
+ * utilisation section).
+ *   B       packed B in precision `prec` (from ri_metric_factor).
+ *   Bc      [n_aux][n_pairs] FP64 fitted tensor on compressed pairs, and
+ *   pairs   [n_pairs][2]: gamma and J are formed from these in FP64 for
+ *           every precision.
+ *   C_occ   [N][n_occ] row-major.
+ *   J, K    [N][N] out, full symmetric.
+ *   gamma   [n_aux] out (may be NULL).
+ * Asynchronous: no host synchronisation. */
+int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
+                   const double* Bc, const int32_t* pairs, int64_t n_pairs,
+                   const double* C_occ, double* J, double* K, double* gamma,
+                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+typedef struct {
+    int32_t max_iter;      /* default 100                                       */
+    int32_t diis_n;        /* DIIS subspace size, 1..8 (default 6)              */
+    double tol_E;          /* |E_k - E_{k-1}| threshold (default 1e-10)         */
+    double tol_err;        /* max |F D S - S D F| threshold (default 1e-8)      */
+    int32_t guess_kind;    /* 0 core Hamiltonian, 1 C_occ given in `guess`      */
+} ri_scf_opts;
+
+typedef struct {
+    double E_total, E_nuc, E_1e, E_J, E_K;
+    int32_t n_iter, converged;
+    double last_dE, max_err;
+} ri_scf_result;
+
+/* ri_energy - closed-shell RI-HF SCF.
+ * Paper: Roothaan equations (Energy formulation section), Fock build
+ * (eq. fock_build with the RI J/K of ri_fock_jk), DIIS and a new set of
+ * occupied orbitals each iteration (Algorithm 1, SCF loop).
+ * The occupied space of each extrapolated Fock matrix (the n_occ lowest
+ * orbitals of F C = S C eps) is obtained as the spectral projector by
+ * trace-correcting purification, all on the GPU.
+ *   guess     [N][n_occ] device C_occ when opts->guess_kind == 1, else NULL.
+ *   C_occ     [N][n_occ] out: orthonormal (C^T S C = 1) occupied orbitals
+ *             spanning the converged occupied space (not canonical).
+ *   F_out     [N][N] out: Fock matrix built from C_occ.
+ *   D_out     [N][N] out (may be NULL): D = 2 C_occ C_occ^T.
+ *   res       (host, out).
+ * Returns RI_E_NO_CONV (with `res` filled) when max_iter is reached.
+ * Synchronises the stream once per iteration. */
+int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const double* Bc,
+                  const int32_t* pairs, int64_t n_pairs, const ri_scf_opts* opts,
+                  const double* guess, double* C_occ, double* F_out, double* D_out,
+                  ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ri_gradient - analytic RI-HF nuclear gradient at a converged SCF.
+ * Paper: eq. hf_gradient and eq. rihf_gradient with the Coulomb (L^P) and
+ * exchange (X_ij^P) coefficients of the Gradient-formulation section,
+ * Algorithm 2.  With D = 2 C C^T:
+ *   c = L^{-T} gamma, Xi^P_ij = [L^{-T} B_ij]_P, B^P_ij = (C^T B^P C)_ij,
+ *   Y^P = c_P D - 2 C Xi^P C^T,  Z = c c^T - 2 sum_ij Xi_ij Xi_ij^T,
+ *   W = (1/2) D F D (= 2 C eps C^T at convergence),
+ *   g = sum D h' - sum W S' + sum Y (mu nu|P)' - 1/2 sum Z (P|Q)' + E_nn'.
+ *   B, prec, Bc, pairs, Linv as returned by ri_metric_factor.
+ *   C_occ, F  converged orbitals and Fock matrix from ri_energy.
+ *   grad     [n_centres][3] out, Eh/bohr, including nuclear repulsion.
+ * Asynchronous. */
+int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
+                    const void* B, int32_t prec, const double* Bc, const double* Linv,
+                    const double* C_occ, const double* F, double* grad,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Operation codes for ri_workspace_bytes. */
+enum { RI_OP_BUILD_3C = 0, RI_OP_METRIC = 1, RI_OP_FOCK = 2, RI_OP_ENERGY = 3,
+       RI_OP_GRADIENT = 4 };
+
+/* Bytes of workspace an operation needs (0 on invalid arguments). */
+size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ,
+                          int64_t n_pairs, int32_t prec);
+
+/* Human-readable text for a status code. */
+const char* ri_status_str(int32_t status);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char* ri_last_hip_error(void);
+
+/* Library version string. */
+const char* ri_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RI_H */

@@ -1,0 +1,9 @@
+"""MI355X-native RI-HF hot path (arXiv 2407.19614): Python binding of libri.
+
+Every step of the computation runs in the HIP kernels of ``libri.so``; this
+package only marshals arguments (PyTorch supplies device memory and streams).
+Importing it does not load the library; the first call does, and raises if
+the library has not been built.
+"""
+from .binding import (FP64, FP32, BF16X3, RIError, RIProblem, lib, load_library,  # noqa: F401
+                      ri_status_str, workspace_bytes, packed_b_bytes)

@@ -1,0 +1,244 @@
+"""ctypes binding of libri's C ABI (include/ri.h) with torch device buffers.
+
+Argument marshalling only: sizes, pointers and the current HIP stream go to
+the library; no arithmetic of the method happens here.  There is no CPU
+fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p, c_char_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libri.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+OP_BUILD_3C, OP_METRIC, OP_FOCK, OP_ENERGY, OP_GRADIENT = range(5)
+STATUS = {0: "RI_OK", 1: "RI_E_ARG", 2: "RI_E_NOT_PD", 3: "RI_E_NO_CONV", 4: "RI_E_WORKSPACE",
+          5: "RI_E_CAPACITY", 6: "RI_E_HIP", 7: "RI_E_UNSUPPORTED"}
+
+
+class RIError(RuntimeError):
+    def __init__(self, code, where, extra=""):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({ri_status_str(code)}){extra}")
+
+
+class RISystem(ctypes.Structure):
+    _fields_ = [("n_centres", c_int32), ("n_fn", c_int32), ("n_aux", c_int32), ("n_occ", c_int32),
+                ("xyz", c_void_p), ("Z", c_void_p), ("fn_centre", c_void_p), ("fn_exp", c_void_p),
+                ("aux_centre", c_void_p), ("aux_exp", c_void_p)]
+
+
+class SCFOpts(ctypes.Structure):
+    _fields_ = [("max_iter", c_int32), ("diis_n", c_int32), ("tol_E", c_double), ("tol_err", c_double),
+                ("guess_kind", c_int32)]
+
+
+class SCFResult(ctypes.Structure):
+    _fields_ = [("E_total", c_double), ("E_nuc", c_double), ("E_1e", c_double), ("E_J", c_double),
+                ("E_K", c_double), ("n_iter", c_int32), ("converged", c_int32), ("last_dE", c_double),
+                ("max_err", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+_SIGS = {
+    "ri_version": (c_char_p, []),
+    "ri_status_str": (c_char_p, [c_int32]),
+    "ri_last_hip_error": (c_char_p, []),
+    "ri_packed_b_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "ri_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, c_int32, c_int64, c_int32]),
+    "ri_build_3c": (c_int32, [POINTER(RISystem), c_double, c_void_p, c_int64, POINTER(c_int64), c_void_p,
+                              c_void_p, c_size_t, c_void_p]),
+    "ri_metric_factor": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_int32, POINTER(c_int64), c_void_p, c_size_t, c_void_p]),
+    "ri_fock_jk": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p,
+                             c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ri_energy": (c_int32, [POINTER(RISystem), c_void_p, c_int32, c_void_p, c_void_p, c_int64, POINTER(SCFOpts),
+                            c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SCFResult), c_void_p, c_size_t,
+                            c_void_p]),
+    "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libri.so once; raise if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2407_19614_amd.build`")
+        lib_ = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib_, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib_
+    return _LIB
+
+
+def lib():
+    return load_library()
+
+
+def ri_status_str(code: int) -> str:
+    return lib().ri_status_str(int(code)).decode()
+
+
+def workspace_bytes(op, N, n_aux, n_occ, n_pairs, prec=FP64) -> int:
+    return int(lib().ri_workspace_bytes(op, N, n_aux, n_occ, n_pairs, prec))
+
+
+def packed_b_bytes(N, n_aux, prec=FP64) -> int:
+    return int(lib().ri_packed_b_bytes(N, n_aux, prec))
+
+
+def _check(code, where):
+    if code != 0:
+        extra = ""
+        if code == 6:
+            extra = ": " + lib().ri_last_hip_error().decode()
+        raise RIError(code, where, extra)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class RIProblem:
+    """Device-resident state of one molecular system.
+
+    Holds the system arrays, pair list, fitted tensors and workspace as torch
+    tensors on the current HIP device, and calls the five entry points.
+    """
+
+    def __init__(self, system, device="cuda", prec=FP64):
+        import torch
+        self.torch = torch
+        self.system = system
+        self.device = torch.device(device)
+        self.prec = prec
+        dev = self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        i32 = dict(dtype=torch.int32, device=dev)
+        self.xyz = torch.tensor(np.ascontiguousarray(system.xyz), **f64)
+        self.Z = torch.tensor(np.ascontiguousarray(system.Z), **f64)
+        self.fn_centre = torch.tensor(np.ascontiguousarray(system.fn_centre, dtype=np.int32), **i32)
+        self.fn_exp = torch.tensor(np.ascontiguousarray(system.fn_exp), **f64)
+        self.aux_centre = torch.tensor(np.ascontiguousarray(system.aux_centre, dtype=np.int32), **i32)
+        self.aux_exp = torch.tensor(np.ascontiguousarray(system.aux_exp), **f64)
+        self.N, self.n_aux, self.n_occ = system.N, system.n_aux, system.n_occ
+        self.c_sys = RISystem(system.n_centres, self.N, self.n_aux, self.n_occ,
+                              self.xyz.data_ptr(), self.Z.data_ptr(), self.fn_centre.data_ptr(),
+                              self.fn_exp.data_ptr(), self.aux_centre.data_ptr(), self.aux_exp.data_ptr())
+        self._ws = None
+        self.pairs = self.T = self.L = self.Linv = self.B = None
+        self.n_pairs = None
+
+    # -- helpers
+    def stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = self.torch.empty(max(int(nbytes), 256), dtype=self.torch.uint8, device=self.device)
+        return self._ws
+
+    def _ws_for(self, op, prec=None):
+        prec = self.prec if prec is None else prec
+        nb = workspace_bytes(op, self.N, self.n_aux, self.n_occ, max(self.n_pairs or 0, 0), prec)
+        if nb == 0:
+            raise RIError(1, "ri_workspace_bytes")
+        return self.workspace(nb), nb
+
+    # -- entry points
+    def build_3c(self, tau=None):
+        torch = self.torch
+        tau = self.system.tau if tau is None else tau
+        ws = self.workspace(workspace_bytes(OP_BUILD_3C, self.N, self.n_aux, self.n_occ, 0, FP64))
+        n = c_int64(0)
+        dummy = torch.empty(2, dtype=torch.int32, device=self.device)
+        code = lib().ri_build_3c(ctypes.byref(self.c_sys), float(tau), _ptr(dummy), 0, ctypes.byref(n), None,
+                                 _ptr(ws), ws.numel(), self.stream())
+        if code not in (0, 5):
+            _check(code, "ri_build_3c")
+        self.n_pairs = int(n.value)
+        self.pairs = torch.empty((max(self.n_pairs, 1), 2), dtype=torch.int32, device=self.device)
+        self.T = torch.empty((self.n_aux, max(self.n_pairs, 1)), dtype=torch.float64, device=self.device)
+        code = lib().ri_build_3c(ctypes.byref(self.c_sys), float(tau), _ptr(self.pairs), self.pairs.shape[0],
+                                 ctypes.byref(n), _ptr(self.T), _ptr(ws), ws.numel(), self.stream())
+        _check(code, "ri_build_3c")
+        return self.n_pairs
+
+    def metric_factor(self, prec=None, pack=True):
+        torch = self.torch
+        prec = self.prec if prec is None else prec
+        self.prec = prec
+        self.L = torch.empty((self.n_aux, self.n_aux), dtype=torch.float64, device=self.device)
+        self.Linv = torch.empty_like(self.L)
+        self.B = None
+        if pack:
+            self.B = torch.empty(packed_b_bytes(self.N, self.n_aux, prec), dtype=torch.uint8, device=self.device)
+        ws, nb = self._ws_for(OP_METRIC, prec)
+        bad = c_int64(-1)
+        code = lib().ri_metric_factor(ctypes.byref(self.c_sys), _ptr(self.pairs), self.n_pairs, _ptr(self.T),
+                                      _ptr(self.L), _ptr(self.Linv), _ptr(self.B), prec, ctypes.byref(bad),
+                                      _ptr(ws), nb, self.stream())
+        _check(code, "ri_metric_factor", ) if code != 2 else None
+        if code == 2:
+            raise RIError(code, "ri_metric_factor", f": pivot {bad.value}")
+        return self
+
+    @property
+    def Bc(self):
+        return self.T
+
+    def fock_jk(self, C_occ, J=None, K=None, gamma=None):
+        torch = self.torch
+        C_occ = C_occ.contiguous()
+        J = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device) if J is None else J
+        K = torch.empty_like(J) if K is None else K
+        gamma = torch.empty(self.n_aux, dtype=torch.float64, device=self.device) if gamma is None else gamma
+        ws, nb = self._ws_for(OP_FOCK)
+        code = lib().ri_fock_jk(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.prec, _ptr(self.T),
+                                _ptr(self.pairs), self.n_pairs, _ptr(C_occ), _ptr(J), _ptr(K), _ptr(gamma),
+                                _ptr(ws), nb, self.stream())
+        _check(code, "ri_fock_jk")
+        return J, K, gamma
+
+    def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True):
+        torch = self.torch
+        opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, 0 if guess is None else 1)
+        C = torch.empty((self.N, self.n_occ), dtype=torch.float64, device=self.device)
+        F = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
+        D = torch.empty_like(F)
+        res = SCFResult()
+        ws, nb = self._ws_for(OP_ENERGY)
+        g = None if guess is None else guess.contiguous()
+        code = lib().ri_energy(ctypes.byref(self.c_sys), _ptr(self.B), self.prec, _ptr(self.T), _ptr(self.pairs),
+                               self.n_pairs, ctypes.byref(opts), _ptr(g), _ptr(C), _ptr(F), _ptr(D),
+                               ctypes.byref(res), _ptr(ws), nb, self.stream())
+        if code == 3 and not raise_on_noconv:
+            return res.as_dict(), C, F, D
+        _check(code, "ri_energy")
+        self.C_occ, self.F, self.D = C, F, D
+        return res.as_dict(), C, F, D
+
+    def gradient(self, C_occ=None, F=None):
+        torch = self.torch
+        C_occ = self.C_occ if C_occ is None else C_occ
+        F = self.F if F is None else F
+        g = torch.empty((self.system.n_centres, 3), dtype=torch.float64, device=self.device)
+        ws, nb = self._ws_for(OP_GRADIENT)
+        code = lib().ri_gradient(ctypes.byref(self.c_sys), _ptr(self.pairs), self.n_pairs, _ptr(self.B), self.prec,
+                                 _ptr(self.T), _ptr(self.Linv), _ptr(C_occ), _ptr(F), _ptr(g), _ptr(ws), nb,
+                                 self.stream())
+        _check(code, "ri_gradient")
+        return g

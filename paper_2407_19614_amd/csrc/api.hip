@@ -1,0 +1,390 @@
+// C-ABI entry points of libri: argument checks, workspace carving and the
+// sequencing of kernels on the caller's stream.
+#include "kernels.h"
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_hip_err;
+
+int32_t hip_status(hipError_t e) {
+    if (e == hipSuccess) return RI_OK;
+    g_hip_err = hipGetErrorString(e);
+    return RI_E_HIP;
+}
+
+#define HIPC(x)                                          \
+    do {                                                 \
+        hipError_t _e = (x);                             \
+        if (_e != hipSuccess) return hip_status(_e);     \
+    } while (0)
+
+// Bump allocator over the caller's workspace.  In dry mode it only counts
+// bytes, so ri_workspace_bytes() and the entry points share one layout.
+struct Arena {
+    char* base;
+    size_t cap;
+    size_t off = 0;
+    bool dry;
+    template <class T>
+    T* take(int64_t n) {
+        size_t b = ((size_t)(n < 0 ? 0 : n) * sizeof(T) + 255) & ~(size_t)255;
+        size_t o = off;
+        off += b;
+        return dry ? nullptr : (T*)(base + o);
+    }
+    bool ok() const { return dry || off <= cap; }
+};
+
+bool valid_sys(const ri_system* s) {
+    return s && s->n_centres > 0 && s->n_fn > 0 && s->n_aux > 0 && s->n_occ > 0 && s->n_occ <= s->n_fn &&
+           s->xyz && s->Z && s->fn_centre && s->fn_exp && s->aux_centre && s->aux_exp;
+}
+
+size_t elem_size(int prec) { return prec == RI_FP64 ? 8 : (prec == RI_FP32 ? 4 : 2); }
+
+// ---------------------------------------------------------------- layouts
+struct BuildWS { int32_t* counts; int64_t* offsets; };
+BuildWS carve_build(Arena& a, int N) { return {a.take<int32_t>(N), a.take<int64_t>(N + 1)}; }
+
+constexpr int64_t BC_CHUNK = 8192;
+struct MetricWS { double* dinv; int* bad; int32_t* map; double* tmp; };
+MetricWS carve_metric(Arena& a, int N, int n_aux, int64_t n_pairs) {
+    MetricWS w;
+    w.dinv = a.take<double>((int64_t)((n_aux + 63) / 64) * 4096);
+    w.bad = a.take<int>(1);
+    w.map = a.take<int32_t>((int64_t)N * N);
+    w.tmp = a.take<double>((int64_t)n_aux * std::min<int64_t>(std::max<int64_t>(n_pairs, 1), BC_CHUNK));
+    return w;
+}
+
+struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* gamma; int ks, js; };
+FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec) {
+    FockWS w;
+    const int Npad = ri::n_tiles_1d(N) * 64;
+    w.ks = ri::k_split_count(N, n_aux, n_occ);
+    w.js = ri::j_split_count(n_aux);
+    w.Xt = a.take<char>((int64_t)n_aux * n_occ * Npad * (int64_t)(prec == RI_FP64 ? 8 : 4));
+    w.part = a.take<double>((int64_t)w.ks * Npad * Npad);
+    w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
+    w.jpart = a.take<double>((int64_t)w.js * std::max<int64_t>(n_pairs, 1));
+    w.gamma = a.take<double>(n_aux);
+    return w;
+}
+
+struct EnergyWS {
+    double *S, *H, *Ls, *LinvS, *J, *K, *F, *D, *T1, *T2, *E, *Fx, *X, *X2;
+    double *dF[8], *dE[8];
+    double *Bmat, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal;
+    int* bad;
+    FockWS fock;
+};
+EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec, int diis_n) {
+    EnergyWS w;
+    const int64_t n2 = (int64_t)N * N;
+    double** mats[] = {&w.S, &w.H, &w.Ls, &w.LinvS, &w.J, &w.K, &w.F, &w.D, &w.T1, &w.T2, &w.E, &w.Fx, &w.X, &w.X2};
+    for (double** m : mats) *m = a.take<double>(n2);
+    for (int i = 0; i < 8; ++i) {
+        w.dF[i] = i < diis_n ? a.take<double>(n2) : nullptr;
+        w.dE[i] = i < diis_n ? a.take<double>(n2) : nullptr;
+    }
+    w.Bmat = a.take<double>(64);
+    w.coef = a.take<double>(8);
+    w.row = a.take<double>(8);
+    w.Y = a.take<double>((int64_t)N * n_occ);
+    w.Cp = a.take<double>((int64_t)N * n_occ);
+    w.R = a.take<double>((int64_t)N * n_occ);
+    w.Mo = a.take<double>((int64_t)n_occ * n_occ);
+    w.LinvM = a.take<double>((int64_t)n_occ * n_occ);
+    w.dinvS = a.take<double>((int64_t)((N + 63) / 64) * 4096);
+    w.dinvM = a.take<double>((int64_t)((n_occ + 63) / 64) * 4096);
+    w.scal = a.take<double>(32);
+    w.bad = a.take<int>(2);
+    w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
+    return w;
+}
+
+int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const double* Bc, const int32_t* pairs,
+                  int64_t n_pairs, const double* C, double* J, double* K, double* gamma, const FockWS& w,
+                  hipStream_t st) {
+    double* g = gamma ? gamma : w.gamma;
+    HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, st));
+    HIPC(ri::x_transform(B, prec, N, n_aux, n_occ, C, w.Xt, st));
+    HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
+    return RI_OK;
+}
+
+// Occupied orbitals of the Fock matrix Fx (the n_occ lowest solutions of
+// F C = S C eps): projector by TC2 purification in the basis orthonormalised
+// by L_S^{-1}, then an orthonormal basis of its range by two passes of
+// projection and Cholesky QR, mapped back by L_S^{-T}.
+int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool have_prev, double* C_out,
+                       hipStream_t st) {
+    const int64_t n2 = (int64_t)N * N;
+    HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.LinvS, N, 0, Fx, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
+    HIPC(ri::gemm_f64(false, true, N, N, N, 1.0, w.T1, N, 0, w.LinvS, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
+    HIPC(ri::gershgorin(w.T2, N, w.scal + 16, st));
+    HIPC(ri::tc2_init(w.T2, w.scal + 16, N, w.X, st));
+    double idem = 1.0;
+    int it = 0, extra = -1;
+    const int max_it = 200;
+    while (it < max_it) {
+        HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.X, N, 0, w.X, N, 0, 0.0, w.X2, N, 0, 1, 0, 0, st));
+        HIPC(ri::traces(w.X, w.X2, N, w.scal + 20, st));
+        HIPC(ri::tc2_update(w.X, w.X2, w.scal + 20, n_occ, n2, st));
+        ++it;
+        if (extra > 0) {
+            if (--extra == 0) break;
+            continue;
+        }
+        if (it % 4 == 0) {
+            HIPC(hipMemcpyAsync(&idem, w.scal + 22, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            if (std::fabs(idem) < 1e-11 * std::max(1, n_occ)) extra = 3;
+        }
+    }
+    if (extra != 0) return RI_E_NO_CONV;
+    if (!have_prev) HIPC(ri::hash_matrix(w.Cp, (int64_t)N * n_occ, 0x5eed1234u, st));
+    for (int pass = 0; pass < 2; ++pass) {
+        HIPC(ri::gemm_f64(false, false, N, n_occ, N, 1.0, w.X, N, 0, w.Cp, n_occ, 0, 0.0, w.Y, n_occ, 0, 1, 0, 0, st));
+        HIPC(ri::gemm_f64(true, false, n_occ, n_occ, N, 1.0, w.Y, n_occ, 0, w.Y, n_occ, 0, 0.0, w.Mo, n_occ, 0, 1, 0,
+                          0, st));
+        HIPC(ri::cholesky_inv(w.Mo, n_occ, n_occ, w.LinvM, n_occ, w.dinvM, w.bad + 1, st));
+        HIPC(ri::gemm_f64(false, true, N, n_occ, n_occ, 1.0, w.Y, n_occ, 0, w.LinvM, n_occ, 0, 0.0, w.Cp, n_occ, 0,
+                          1, 0, 0, st));
+    }
+    HIPC(ri::gemm_f64(true, false, N, n_occ, N, 1.0, w.LinvS, N, 0, w.Cp, n_occ, 0, 0.0, C_out, n_occ, 0, 1, 2, 0,
+                      st));
+    return RI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ri_version(void) { return "libri 0.1 (gfx950)"; }
+
+const char* ri_last_hip_error(void) { return g_hip_err.c_str(); }
+
+const char* ri_status_str(int32_t s) {
+    switch (s) {
+        case RI_OK: return "ok";
+        case RI_E_ARG: return "invalid argument";
+        case RI_E_NOT_PD: return "matrix not positive definite";
+        case RI_E_NO_CONV: return "iteration did not converge";
+        case RI_E_WORKSPACE: return "workspace too small";
+        case RI_E_CAPACITY: return "pair capacity too small";
+        case RI_E_HIP: return "HIP runtime error";
+        case RI_E_UNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec) {
+    if (N <= 0 || n_aux <= 0 || prec < 0 || prec > 2) return 0;
+    return (size_t)n_aux * ri::tile_elems(N) * elem_size(prec) * (prec == RI_BF16X3 ? 2 : 1);
+}
+
+size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, int64_t n_pairs, int32_t prec) {
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_pairs < 0 || prec < 0 || prec > 2) return 0;
+    Arena a{nullptr, 0, 0, true};
+    switch (op) {
+        case RI_OP_BUILD_3C: carve_build(a, N); break;
+        case RI_OP_METRIC: carve_metric(a, N, n_aux, n_pairs); break;
+        case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec); break;
+        case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8); break;
+        case RI_OP_GRADIENT: return 0;
+        default: return 0;
+    }
+    return a.off + 256;
+}
+
+int32_t ri_build_3c(const ri_system* sys, double tau, int32_t* pairs, int64_t cap, int64_t* n_pairs, double* T,
+                    void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!valid_sys(sys) || !pairs || !n_pairs || cap < 0 || !ws || !(tau >= 0.0)) return RI_E_ARG;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    BuildWS w = carve_build(a, sys->n_fn);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    HIPC(ri::screen_pairs(sys, tau, w.counts, w.offsets, st));
+    int64_t np = 0;
+    HIPC(hipMemcpyAsync(&np, w.offsets + sys->n_fn, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    *n_pairs = np;
+    if (np > cap) return RI_E_CAPACITY;
+    HIPC(ri::write_pairs(sys, tau, w.offsets, pairs, st));
+    if (T) HIPC(ri::eri3(sys, pairs, np, T, st));
+    return RI_OK;
+}
+
+int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, double* T, double* L,
+                         double* Linv, void* B, int32_t prec, int64_t* bad_pivot, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+    if (!valid_sys(sys) || n_pairs < 0 || (n_pairs > 0 && (!pairs || !T)) || !L || !Linv || !bad_pivot || !ws)
+        return RI_E_ARG;
+    if (prec < 0 || prec > 2) return RI_E_UNSUPPORTED;
+    if (B && prec == RI_BF16X3) return RI_E_UNSUPPORTED;
+    const int na = sys->n_aux, N = sys->n_fn;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    MetricWS w = carve_metric(a, N, na, n_pairs);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    *bad_pivot = -1;
+    HIPC(ri::metric(sys, L, st));
+    HIPC(ri::fill_i32(w.bad, INT_MAX, 1, st));
+    HIPC(ri::cholesky_inv(L, na, na, Linv, na, w.dinv, w.bad, st));
+    int bad = INT_MAX;
+    HIPC(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (bad != INT_MAX) {
+        *bad_pivot = bad;
+        return RI_E_NOT_PD;
+    }
+    // Bc = L^{-1} T, by column chunks through the workspace.
+    for (int64_t c0 = 0; c0 < n_pairs; c0 += BC_CHUNK) {
+        const int64_t nc = std::min<int64_t>(BC_CHUNK, n_pairs - c0);
+        HIPC(ri::gemm_f64(false, false, na, (int)nc, na, 1.0, Linv, na, 0, T + c0, n_pairs, 0, 0.0, w.tmp, nc, 0, 1,
+                          1, 0, st));
+        HIPC(hipMemcpy2DAsync(T + c0, n_pairs * sizeof(double), w.tmp, nc * sizeof(double), nc * sizeof(double), na,
+                              hipMemcpyDeviceToDevice, st));
+    }
+    if (B) {
+        HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
+        HIPC(ri::pack_b(T, n_pairs, w.map, N, na, B, prec, st));
+    }
+    return RI_OK;
+}
+
+int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec, const double* Bc,
+                   const int32_t* pairs, int64_t n_pairs, const double* C, double* J, double* K, double* gamma,
+                   void* ws, size_t ws_bytes, hipStream_t st) {
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
+        (n_pairs > 0 && (!Bc || !pairs)))
+        return RI_E_ARG;
+    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st);
+}
+
+int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const double* Bc, const int32_t* pairs,
+                  int64_t n_pairs, const ri_scf_opts* opts, const double* guess, double* C_occ, double* F_out,
+                  double* D_out, ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!valid_sys(sys) || !B || !opts || !C_occ || !F_out || !res || !ws || n_pairs < 0 ||
+        (n_pairs > 0 && (!Bc || !pairs)))
+        return RI_E_ARG;
+    if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0))
+        return RI_E_ARG;
+    if (opts->guess_kind == 1 && !guess) return RI_E_ARG;
+    if (opts->guess_kind != 0 && opts->guess_kind != 1) return RI_E_UNSUPPORTED;
+    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
+    const int64_t n2 = (int64_t)N * N;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    EnergyWS w = carve_energy(a, N, na, no, n_pairs, prec, 8);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    std::memset(res, 0, sizeof(*res));
+
+    HIPC(ri::one_electron(sys, w.S, w.H, st));
+    HIPC(ri::nuclear_repulsion(sys, w.scal + 8, st));
+    HIPC(ri::copy(w.Ls, w.S, n2, st));
+    HIPC(ri::fill_i32(w.bad, INT_MAX, 2, st));
+    HIPC(ri::cholesky_inv(w.Ls, N, N, w.LinvS, N, w.dinvS, w.bad, st));
+    int bad = INT_MAX;
+    HIPC(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (bad != INT_MAX) return RI_E_NOT_PD;
+
+    int32_t rc;
+    if (opts->guess_kind == 0) {
+        rc = occupied_space(w.H, N, no, w, false, C_occ, st);
+        if (rc) return rc;
+    } else {
+        HIPC(ri::copy(C_occ, guess, (int64_t)N * no, st));
+        // the guess in the orthonormal frame, C' = L_S^T C, seeds the subspace passes
+        HIPC(ri::gemm_f64(true, false, N, no, N, 1.0, w.Ls, N, 0, C_occ, no, 0, 0.0, w.Cp, no, 0, 1, 2, 0, st));
+    }
+
+    std::vector<int> slots;
+    double Bh[8][8] = {};   // DIIS inner products <e_i, e_j>, indexed by ring slot
+    int pushes = 0;
+    double E_old = 0.0, host[8];
+    bool converged = false;
+    int it = 0;
+    for (it = 1; it <= opts->max_iter; ++it) {
+        rc = fock_impl(N, na, no, B, prec, Bc, pairs, n_pairs, C_occ, w.J, w.K, nullptr, w.fock, st);
+        if (rc) return rc;
+        HIPC(ri::fock_assemble(w.H, w.J, w.K, w.F, n2, st));
+        HIPC(ri::gemm_f64(false, true, N, N, no, 2.0, C_occ, no, 0, C_occ, no, 0, 0.0, w.D, N, 0, 1, 0, 0, st));
+        HIPC(ri::energy_terms(w.D, w.H, w.J, w.K, n2, w.scal + 8, w.scal, st));
+        HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.F, N, 0, w.D, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
+        HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.T1, N, 0, w.S, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
+        HIPC(ri::commutator(w.T2, w.E, N, st));
+        HIPC(ri::max_abs(w.E, n2, w.scal + 5, st));
+        HIPC(hipMemcpyAsync(host, w.scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        res->E_total = host[0];
+        res->E_nuc = host[1];
+        res->E_1e = host[2];
+        res->E_J = host[3];
+        res->E_K = host[4];
+        res->max_err = host[5];
+        res->n_iter = it;
+        if (it > 1) {
+            res->last_dE = host[0] - E_old;
+            if (std::fabs(host[0] - E_old) < opts->tol_E && host[5] < opts->tol_err) {
+                converged = true;
+                break;
+            }
+        }
+        E_old = host[0];
+        // DIIS: store (F, e) in the ring, update the B matrix row, extrapolate.
+        const int s = pushes % dn;
+        ++pushes;
+        HIPC(ri::copy(w.dF[s], w.F, n2, st));
+        HIPC(ri::copy(w.dE[s], w.E, n2, st));
+        for (size_t k = 0; k < slots.size(); ++k)
+            if (slots[k] == s) { slots.erase(slots.begin() + k); break; }
+        slots.push_back(s);
+        const int m = (int)slots.size();
+        {
+            const double* es[8];
+            for (int k = 0; k < m; ++k) es[k] = w.dE[slots[k]];
+            HIPC(ri::diis_dots(es, m, w.dE[s], w.row, n2, st));
+            double row[8];
+            HIPC(hipMemcpyAsync(row, w.row, m * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            for (int k = 0; k < m; ++k) { Bh[s][slots[k]] = row[k]; Bh[slots[k]][s] = row[k]; }
+        }
+        const double* Fx = w.F;
+        if (m >= 2) {
+            const double* fs[8];
+            for (int k = 0; k < m; ++k) fs[k] = w.dF[slots[k]];
+            double Bm[64];
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) Bm[i * 8 + j] = Bh[slots[i]][slots[j]];
+            HIPC(hipMemcpyAsync(w.Bmat, Bm, sizeof(Bm), hipMemcpyHostToDevice, st));
+            HIPC(ri::diis_solve(w.Bmat, m, 8, w.coef, st));
+            HIPC(ri::diis_combine(fs, w.coef, m, w.Fx, n2, st));
+            Fx = w.Fx;
+        }
+        rc = occupied_space(Fx, N, no, w, true, C_occ, st);
+        if (rc) return rc;
+    }
+    HIPC(ri::copy(F_out, w.F, n2, st));
+    if (D_out) HIPC(ri::copy(D_out, w.D, n2, st));
+    HIPC(hipStreamSynchronize(st));
+    res->converged = converged ? 1 : 0;
+    return converged ? RI_OK : RI_E_NO_CONV;
+}
+
+int32_t ri_gradient(const ri_system*, const int32_t*, int64_t, const void*, int32_t, const double*, const double*,
+                    const double*, const double*, double*, void*, size_t, hipStream_t) {
+    return RI_E_UNSUPPORTED;
+}
+
+}  // extern "C"

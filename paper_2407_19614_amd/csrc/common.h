@@ -1,0 +1,90 @@
+// Internal declarations shared by the libri HIP sources (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/ri.h"
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+#define RI_PI 3.14159265358979323846
+
+// v_mfma_f64_16x16x4_f64: D(16x16) += A(16x4) B(4x16).
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16]; it receives
+// D[4*r + l/16][l%16] in element r of the result.
+__device__ __forceinline__ d4_t mfma_f64(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double norm_s(double a) {
+    // (2a/pi)^{3/4}
+    return pow(2.0 * a / RI_PI, 0.75);
+}
+
+// Boys function F0(t) = int_0^1 exp(-t u^2) du.
+__device__ __forceinline__ double boys_f0(double t) {
+    if (t < 1e-4) {
+        // 1 - t/3 + t^2/10 - t^3/42 + t^4/216
+        return 1.0 + t * (-1.0 / 3.0 + t * (1.0 / 10.0 + t * (-1.0 / 42.0 + t * (1.0 / 216.0))));
+    }
+    double s = sqrt(t);
+    return 0.88622692545275801365 * erf(s) / s;   // sqrt(pi)/2
+}
+
+// Boys function F1(t) = int_0^1 u^2 exp(-t u^2) du.  For t < 1 the series
+// F1 = exp(-t) sum_k (2t)^k / (3*5*...*(2k+3)) (all terms positive);
+// otherwise the downward relation F1 = (F0 - exp(-t)) / (2t).
+__device__ __forceinline__ double boys_f1(double t) {
+    double e = exp(-t);
+    if (t < 1.0) {
+        double term = 1.0 / 3.0, sum = term;
+        double x = 2.0 * t;
+        #pragma unroll 1
+        for (int k = 1; k < 40; ++k) {
+            term *= x / (2.0 * k + 3.0);
+            sum += term;
+            if (term < 1e-17 * sum) break;
+        }
+        return e * sum;
+    }
+    return (boys_f0(t) - e) / (2.0 * t);
+}
+
+// ------------------------------------------------------------ launch helpers
+namespace ri {
+
+// GEMM C = alpha op(A) op(B) + beta C over a batch (row-major, FP64 MFMA).
+// tri: 0 general; 1 op(A) lower triangular; 2 op(A) upper triangular.
+// lowerC: skip 64x64 tiles of C strictly above the diagonal.
+hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha,
+                    const double* A, int64_t lda, int64_t sA,
+                    const double* B, int64_t ldb, int64_t sB, double beta,
+                    double* C, int64_t ldc, int64_t sC, int batch, int tri, int lowerC,
+                    hipStream_t s);
+
+// In-place Cholesky A = L L^T (lower; upper triangle zeroed) of an n x n
+// matrix, plus Linv = L^{-1} when Linv != nullptr.  dwork >= ceil(n/64)*4096
+// doubles.  The first non-positive pivot index is atomically min-ed into
+// *d_bad (device int, caller initialises it to INT_MAX).
+hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi,
+                        double* dwork, int* d_bad, hipStream_t s);
+
+hipError_t fill(double* p, double v, int64_t n, hipStream_t s);
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t set_identity(double* p, int n, int64_t ld, hipStream_t s);
+// out[k] = sum_i x[i] * y[i] for one pair of vectors, accumulated as
+// out[slot] (single block per call, deterministic).
+hipError_t dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
+hipError_t max_abs(const double* x, int64_t n, double* out, hipStream_t s);
+hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s); // y = a x + b y
+hipError_t copy(double* dst, const double* src, int64_t n, hipStream_t s);
+
+}  // namespace ri
+
+#define RI_TRY(expr)                                   \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return _e;               \
+    } while (0)

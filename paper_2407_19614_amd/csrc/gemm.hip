@@ -1,0 +1,303 @@
+// FP64 MFMA GEMM and the dense linear algebra built on it: blocked Cholesky
+// with non-positive pivot detection and the triangular inverse.
+#include "common.h"
+#include <climits>
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 1;
+
+// 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a 32 x 32
+// block of C as 2 x 2 MFMA 16x16 tiles.  Tiles of A and B are staged through
+// LDS in k-major order so that the 16 lanes reading one fragment row touch
+// consecutive addresses.  Global loads for the next k-slice are issued before
+// the MFMAs of the current one.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
+    const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int tri, int lowerC) {
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (lowerC && n0 > m0 + BM - 1) return;
+    A += (int64_t)blockIdx.z * sA;
+    B += (int64_t)blockIdx.z * sB;
+    C += (int64_t)blockIdx.z * sC;
+    __shared__ double As[BK][LDP];
+    __shared__ double Bs[BK][LDP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+    int kbeg = 0, kend = K;
+    if (tri == 1) kend = min(K, m0 + BM);
+    if (tri == 2) kbeg = (m0 / BK) * BK;
+
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int m, k;
+            if (!TA) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            else     { m = tid & 63; k = (tid >> 6) + 4 * r; }
+            int gm = m0 + m, gk = k0 + k;
+            double v = 0.0;
+            if (gm < M && gk < kend)
+                v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+            ra[r] = v;
+            int n, kb;
+            if (!TB) { n = tid & 63; kb = (tid >> 6) + 4 * r; }
+            else     { kb = tid & 15; n = (tid >> 4) + 16 * r; }
+            int gn = n0 + n, gkb = k0 + kb;
+            double w = 0.0;
+            if (gn < N && gkb < kend)
+                w = TB ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn];
+            rb[r] = w;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int m, k;
+            if (!TA) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            else     { m = tid & 63; k = (tid >> 6) + 4 * r; }
+            As[k][m] = ra[r];
+            int n, kb;
+            if (!TB) { n = tid & 63; kb = (tid >> 6) + 4 * r; }
+            else     { kb = tid & 15; n = (tid >> 4) + 16 * r; }
+            Bs[kb][n] = rb[r];
+        }
+    };
+
+    d4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int li = lane & 15, lk = lane >> 4;
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a0 = As[kk + lk][wm + li], a1 = As[kk + lk][wm + 16 + li];
+            double b0 = Bs[kk + lk][wn + li], b1 = Bs[kk + lk][wn + 16 + li];
+            acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+            acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+            acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+            acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
+                if (gm < M && gn < N) {
+                    double* c = C + (int64_t)gm * ldc + gn;
+                    double v = alpha * acc[i][j][r];
+                    *c = (beta == 0.0) ? v : v + beta * *c;
+                }
+            }
+}
+
+// Factor one 64x64 diagonal block in place (lower Cholesky) and write the
+// inverse of its factor to Dinv (64x64, lower, identity padding beyond n).
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int n, int64_t lda, int kb,
+                                                         double* Dinv, int* bad) {
+    __shared__ double L[64][65];
+    const int t = threadIdx.x, o = kb * 64, nb = min(64, n - o);
+    for (int c = 0; c < 64; ++c)
+        L[t][c] = (t < nb && c < nb) ? A[(int64_t)(o + t) * lda + o + c] : (t == c ? 1.0 : 0.0);
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (t == j) {
+            double d = L[j][j];
+            if (!(d > 0.0)) {
+                atomicMin(bad, o + j);
+                d = 1.0;
+            }
+            L[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        if (t > j && t < nb) L[t][j] /= L[j][j];
+        __syncthreads();
+        if (t > j && t < nb)
+            for (int c = j + 1; c <= t; ++c) L[t][c] -= L[t][j] * L[c][j];
+        __syncthreads();
+    }
+    for (int c = 0; c < 64; ++c)
+        if (t < nb && c < nb) A[(int64_t)(o + t) * lda + o + c] = (c <= t) ? L[t][c] : 0.0;
+    // column t of L^{-1} by forward substitution
+    double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = 0.0;
+    for (int i = 0; i < 64; ++i) {
+        double s = (i == t) ? 1.0 : 0.0;
+        for (int k = t; k < i; ++k) s -= L[i][k] * x[k];
+        x[i] = (i >= t) ? s / L[i][i] : 0.0;
+    }
+    for (int i = 0; i < 64; ++i) Dinv[i * 64 + t] = x[i];
+}
+
+__global__ void zero_upper_kernel(double* A, int n, int64_t lda) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * n) return;
+    int r = i / n, c = i % n;
+    if (c > r) A[(int64_t)r * lda + c] = 0.0;
+}
+
+__global__ void fill_kernel(double* p, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void identity_kernel(double* p, int n, int64_t ld) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * n) return;
+    int r = i / n, c = i % n;
+    p[(int64_t)r * ld + c] = (r == c) ? 1.0 : 0.0;
+}
+__global__ void axpby_kernel(double* y, const double* x, double a, double b, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + b * y[i];
+}
+
+__device__ double block_sum(double v) {
+    __shared__ double sh[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    return r;
+}
+__device__ double block_max(double v) {
+    __shared__ double sh[16];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o));
+    int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void dot_kernel(const double* x, const double* y, int64_t n,
+                                                    double* out) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * y[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+__global__ __launch_bounds__(1024) void maxabs_kernel(const double* x, int64_t n, double* out) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s = fmax(s, fabs(x[i]));
+    s = block_max(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+inline unsigned nblk(int64_t n, int b = 256) {
+    int64_t g = (n + b - 1) / b;
+    return (unsigned)(g > 65535 * 16 ? 65535 * 16 : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+namespace ri {
+
+hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+                    int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
+                    double beta, double* C, int64_t ldc, int64_t sC, int batch, int tri,
+                    int lowerC, hipStream_t s) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+    if (!ta && !tb)
+        gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC);
+    else if (!ta && tb)
+        gemm_f64_kernel<false, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC);
+    else if (ta && !tb)
+        gemm_f64_kernel<true, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC);
+    else
+        gemm_f64_kernel<true, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC);
+    return hipGetLastError();
+}
+
+hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi, double* dwork,
+                        int* d_bad, hipStream_t s) {
+    const int nb = (n + 63) / 64;
+    for (int k = 0; k < nb; ++k) {
+        const int o = k * 64, w = min(64, n - o), rest = n - o - w;
+        potrf_diag_kernel<<<1, 64, 0, s>>>(A, n, lda, k, dwork + (int64_t)k * 4096, d_bad);
+        RI_TRY(hipGetLastError());
+        if (rest > 0) {
+            double* panel = A + (int64_t)(o + w) * lda + o;
+            // panel <- panel * Dinv^T  (rows below the diagonal block)
+            RI_TRY(gemm_f64(false, true, rest, w, w, 1.0, panel, lda, 0, dwork + (int64_t)k * 4096, 64, 0,
+                            0.0, panel, lda, 0, 1, 0, 0, s));
+            // trailing lower update
+            double* trail = A + (int64_t)(o + w) * lda + o + w;
+            RI_TRY(gemm_f64(false, true, rest, rest, w, -1.0, panel, lda, 0, panel, lda, 0, 1.0, trail,
+                            lda, 0, 1, 0, 1, s));
+        }
+    }
+    zero_upper_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(A, n, lda);
+    RI_TRY(hipGetLastError());
+    if (!Linv) return hipSuccess;
+    // Solve L X = I by blocks: X_k = Dinv_k (I_k - L_{k,<k} X_{<k}).
+    identity_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(Linv, n, ldi);
+    RI_TRY(hipGetLastError());
+    for (int k = 0; k < nb; ++k) {
+        const int o = k * 64, w = min(64, n - o), rest = n - o - w, cols = o + w;
+        double* Xk = Linv + (int64_t)o * ldi;
+        RI_TRY(gemm_f64(false, false, w, cols, w, 1.0, dwork + (int64_t)k * 4096, 64, 0, Xk, ldi, 0, 0.0,
+                        Xk, ldi, 0, 1, 0, 0, s));
+        if (rest > 0)
+            RI_TRY(gemm_f64(false, false, rest, cols, w, -1.0, A + (int64_t)(o + w) * lda + o, lda, 0, Xk,
+                            ldi, 0, 1.0, Linv + (int64_t)(o + w) * ldi, ldi, 0, 1, 0, 0, s));
+    }
+    return hipSuccess;
+}
+
+hipError_t fill(double* p, double v, int64_t n, hipStream_t s) {
+    fill_kernel<<<nblk(n), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    fill_i32_kernel<<<nblk(n), 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}
+hipError_t set_identity(double* p, int n, int64_t ld, hipStream_t s) {
+    identity_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(p, n, ld);
+    return hipGetLastError();
+}
+hipError_t dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
+    dot_kernel<<<1, 1024, 0, s>>>(x, y, n, out);
+    return hipGetLastError();
+}
+hipError_t max_abs(const double* x, int64_t n, double* out, hipStream_t s) {
+    maxabs_kernel<<<1, 1024, 0, s>>>(x, n, out);
+    return hipGetLastError();
+}
+hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
+    axpby_kernel<<<nblk(n), 256, 0, s>>>(y, x, a, b, n);
+    return hipGetLastError();
+}
+hipError_t copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+    return hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace ri

@@ -1,0 +1,54 @@
+// Launchers of the method's kernels (integrals, Fock build, SCF, gradient).
+#pragma once
+#include "common.h"
+
+namespace ri {
+
+// ---- integrals
+hipError_t screen_pairs(const ri_system* s, double tau, int32_t* counts, int64_t* offsets, hipStream_t st);
+hipError_t write_pairs(const ri_system* s, double tau, const int64_t* offsets, int32_t* pairs, hipStream_t st);
+hipError_t eri3(const ri_system* s, const int32_t* pairs, int64_t n_pairs, double* T, hipStream_t st);
+hipError_t metric(const ri_system* s, double* A, hipStream_t st);
+hipError_t one_electron(const ri_system* s, double* S, double* H, hipStream_t st);
+hipError_t nuclear_repulsion(const ri_system* s, double* out, hipStream_t st);
+
+// ---- packed B geometry
+inline int n_tiles_1d(int N) { return (N + 63) / 64; }
+inline int64_t n_tiles(int N) { int t = n_tiles_1d(N); return (int64_t)t * (t + 1) / 2; }
+inline int64_t tile_elems(int N) { return n_tiles(N) * 4096; }
+
+hipError_t pair_map(const int32_t* pairs, int64_t n_pairs, int N, int32_t* map, hipStream_t st);
+hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, int n_aux, void* B,
+                  int prec, hipStream_t st);
+
+// ---- Fock build pieces
+// Xt[P][i][mu] (row stride Npad = 64 * tiles) = (B^P C_occ)^T
+hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C,
+                       void* Xt, hipStream_t st);
+// K = sum_P X^P X^P^T from Xt; part = workspace of n_split * Npad^2 doubles.
+hipError_t k_syrk(const void* Xt, int prec, int N, int n_aux, int n_occ, double* part, int n_split,
+                  double* K, hipStream_t st);
+int k_split_count(int N, int n_aux, int n_occ);
+// gamma and J from the compressed FP64 tensor.
+hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
+                   int n_occ, const double* C, double* dpair, double* gamma, double* jpart,
+                   int n_jsplit, double* J, hipStream_t st);
+int j_split_count(int n_aux);
+
+}  // namespace ri
+
+namespace ri {
+// ---- SCF helpers (scf.hip)
+hipError_t fock_assemble(const double* h, const double* J, const double* K, double* F, int64_t n, hipStream_t st);
+hipError_t commutator(const double* M, double* e, int N, hipStream_t st);   // e = M - M^T
+hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, hipStream_t st);
+hipError_t diis_solve(const double* Bmat, int m, int ld, double* coef, hipStream_t st);
+hipError_t diis_combine(const double* const* Fs, const double* coef, int m, double* out, int64_t n, hipStream_t st);
+hipError_t gershgorin(const double* F, int N, double* bounds, hipStream_t st);
+hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st);
+hipError_t traces(const double* X, const double* X2, int N, double* tr, hipStream_t st);
+hipError_t tc2_update(double* X, const double* X2, const double* tr, int n_occ, int64_t n, hipStream_t st);
+hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st);
+hipError_t energy_terms(const double* D, const double* h, const double* J, const double* K, int64_t n,
+                        const double* enuc, double* out, hipStream_t st);
+}  // namespace ri

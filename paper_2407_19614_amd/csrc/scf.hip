@@ -1,0 +1,231 @@
+// SCF helpers on the GPU: Fock assembly, the DIIS error F D S - S D F and
+// extrapolation (Pulay), spectral bounds and trace-correcting purification
+// (Niklasson's TC2) giving the projector onto the n_occ lowest orbitals of an
+// orthogonalised Fock matrix, and the energy terms.
+#include "kernels.h"
+
+namespace {
+
+inline unsigned nb(int64_t n) { int64_t g = (n + 255) / 256; return (unsigned)(g > 1048576 ? 1048576 : g); }
+
+__global__ void fock_kernel(const double* h, const double* J, const double* K, double* F, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        F[i] = h[i] + J[i] - K[i];
+}
+
+__global__ void comm_kernel(const double* M, double* e, int N) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= N) return;
+    e[(int64_t)r * N + c] = M[(int64_t)r * N + c] - M[(int64_t)c * N + r];
+}
+
+struct Ptrs { const double* p[8]; };
+
+__global__ __launch_bounds__(256) void multi_dot_kernel(Ptrs es, const double* enew, double* row, int64_t n) {
+    const double* x = es.p[blockIdx.x];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i] * enew[i];
+    __shared__ double sh[4];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) row[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Solve [B -1; -1 0] [c; l] = [0; -1] by Gaussian elimination with partial
+// pivoting (one thread; m <= 8).
+__global__ void diis_solve_kernel(const double* Bm, int m, int ld, double* coef) {
+    if (threadIdx.x != 0) return;
+    double a[9][10];
+    const int n = m + 1;
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < m; ++j) a[i][j] = Bm[i * ld + j];
+        a[i][m] = -1.0;
+        a[i][n] = 0.0;
+    }
+    for (int j = 0; j < m; ++j) a[m][j] = -1.0;
+    a[m][m] = 0.0;
+    a[m][n] = -1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        if (piv != c)
+            for (int k = 0; k <= n; ++k) { double t = a[c][k]; a[c][k] = a[piv][k]; a[piv][k] = t; }
+        double d = a[c][c];
+        if (d == 0.0) d = 1e-300;
+        for (int r = c + 1; r < n; ++r) {
+            double f = a[r][c] / d;
+            for (int k = c; k <= n; ++k) a[r][k] -= f * a[c][k];
+        }
+    }
+    double x[9];
+    for (int r = n - 1; r >= 0; --r) {
+        double s = a[r][n];
+        for (int k = r + 1; k < n; ++k) s -= a[r][k] * x[k];
+        x[r] = s / (a[r][r] == 0.0 ? 1e-300 : a[r][r]);
+    }
+    for (int i = 0; i < m; ++i) coef[i] = x[i];
+}
+
+__global__ void combine_kernel(Ptrs Fs, const double* coef, int m, double* out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += coef[k] * Fs.p[k][i];
+        out[i] = s;
+    }
+}
+
+__global__ __launch_bounds__(1024) void gersh_kernel(const double* F, int N, double* bounds) {
+    double lo = 1e300, hi = -1e300;
+    for (int r = threadIdx.x; r < N; r += 1024) {
+        const double* row = F + (int64_t)r * N;
+        double off = 0.0;
+        for (int c = 0; c < N; ++c)
+            if (c != r) off += fabs(row[c]);
+        lo = fmin(lo, row[r] - off);
+        hi = fmax(hi, row[r] + off);
+    }
+    __shared__ double sl[16], sh[16];
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_down(lo, o));
+        hi = fmax(hi, __shfl_down(hi, o));
+    }
+    if ((threadIdx.x & 63) == 0) { sl[threadIdx.x >> 6] = lo; sh[threadIdx.x >> 6] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 16; ++i) { lo = fmin(lo, sl[i]); hi = fmax(hi, sh[i]); }
+        lo = fmin(lo, sl[0]);
+        hi = fmax(hi, sh[0]);
+        bounds[0] = lo;
+        bounds[1] = hi;
+    }
+}
+
+// X0 = (hi I - F) / (hi - lo): spectrum mapped into [0, 1], reversed.
+__global__ void tc2_init_kernel(const double* F, const double* bounds, int N, double* X) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= N) return;
+    double lo = bounds[0], hi = bounds[1], s = 1.0 / (hi - lo);
+    int64_t i = (int64_t)r * N + c;
+    X[i] = ((r == c ? hi : 0.0) - F[i]) * s;
+}
+
+__global__ __launch_bounds__(1024) void traces_kernel(const double* X, const double* X2, int N, double* tr) {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < N; i += 1024) {
+        a += X[(int64_t)i * N + i];
+        b += X2[(int64_t)i * N + i];
+    }
+    __shared__ double sa[16], sb[16];
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_down(a, o); b += __shfl_down(b, o); }
+    if ((threadIdx.x & 63) == 0) { sa[threadIdx.x >> 6] = a; sb[threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0.0; b = 0.0;
+        for (int i = 0; i < 16; ++i) { a += sa[i]; b += sb[i]; }
+        tr[0] = a;
+        tr[1] = b;
+        tr[2] = a - b;   // idempotency measure tr(X - X^2)
+    }
+}
+
+// TC2 step: X <- X^2 if that moves the trace closer to n_occ, else 2X - X^2.
+__global__ void tc2_update_kernel(double* X, const double* X2, const double* tr, int n_occ, int64_t n) {
+    const double t1 = tr[0], t2 = tr[1];
+    const bool sq = fabs(t2 - n_occ) < fabs(2.0 * t1 - t2 - n_occ);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        X[i] = sq ? X2[i] : 2.0 * X[i] - X2[i];
+}
+
+// Counter-based pseudo-random values in [-1, 1) (a 32-bit integer hash of
+// the element index); any full-rank block serves as a subspace start.
+__global__ void hash_kernel(double* R, int64_t n, uint32_t seed) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+        x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+        R[i] = (double)x * (2.0 / 4294967296.0) - 1.0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void energy_kernel(const double* D, const double* h, const double* J,
+                                                       const double* K, int64_t n, const double* enuc,
+                                                       double* out) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        double d = D[i];
+        a += d * h[i];
+        b += d * J[i];
+        c += d * K[i];
+    }
+    __shared__ double s[3][16];
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_down(a, o); b += __shfl_down(b, o); c += __shfl_down(c, o); }
+    if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; s[2][threadIdx.x >> 6] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = c = 0.0;
+        for (int i = 0; i < 16; ++i) { a += s[0][i]; b += s[1][i]; c += s[2][i]; }
+        double en = *enuc;
+        out[0] = a + 0.5 * b - 0.5 * c + en;   // E_total
+        out[1] = en;
+        out[2] = a;                            // E_1e
+        out[3] = 0.5 * b;                      // E_J
+        out[4] = -0.5 * c;                     // E_K
+    }
+}
+
+}  // namespace
+
+namespace ri {
+
+hipError_t fock_assemble(const double* h, const double* J, const double* K, double* F, int64_t n, hipStream_t st) {
+    fock_kernel<<<nb(n), 256, 0, st>>>(h, J, K, F, n);
+    return hipGetLastError();
+}
+hipError_t commutator(const double* M, double* e, int N, hipStream_t st) {
+    comm_kernel<<<dim3((N + 255) / 256, N), 256, 0, st>>>(M, e, N);
+    return hipGetLastError();
+}
+hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, hipStream_t st) {
+    Ptrs p{};
+    for (int i = 0; i < m; ++i) p.p[i] = es[i];
+    multi_dot_kernel<<<m, 256, 0, st>>>(p, enew, row, n);
+    return hipGetLastError();
+}
+hipError_t diis_solve(const double* Bmat, int m, int ld, double* coef, hipStream_t st) {
+    diis_solve_kernel<<<1, 64, 0, st>>>(Bmat, m, ld, coef);
+    return hipGetLastError();
+}
+hipError_t diis_combine(const double* const* Fs, const double* coef, int m, double* out, int64_t n, hipStream_t st) {
+    Ptrs p{};
+    for (int i = 0; i < m; ++i) p.p[i] = Fs[i];
+    combine_kernel<<<nb(n), 256, 0, st>>>(p, coef, m, out, n);
+    return hipGetLastError();
+}
+hipError_t gershgorin(const double* F, int N, double* bounds, hipStream_t st) {
+    gersh_kernel<<<1, 1024, 0, st>>>(F, N, bounds);
+    return hipGetLastError();
+}
+hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st) {
+    tc2_init_kernel<<<dim3((N + 255) / 256, N), 256, 0, st>>>(F, bounds, N, X);
+    return hipGetLastError();
+}
+hipError_t traces(const double* X, const double* X2, int N, double* tr, hipStream_t st) {
+    traces_kernel<<<1, 1024, 0, st>>>(X, X2, N, tr);
+    return hipGetLastError();
+}
+hipError_t tc2_update(double* X, const double* X2, const double* tr, int n_occ, int64_t n, hipStream_t st) {
+    tc2_update_kernel<<<nb(n), 256, 0, st>>>(X, X2, tr, n_occ, n);
+    return hipGetLastError();
+}
+hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st) {
+    hash_kernel<<<nb(n), 256, 0, st>>>(R, n, seed);
+    return hipGetLastError();
+}
+hipError_t energy_terms(const double* D, const double* h, const double* J, const double* K, int64_t n,
+                        const double* enuc, double* out, hipStream_t st) {
+    energy_kernel<<<1, 1024, 0, st>>>(D, h, J, K, n, enuc, out);
+    return hipGetLastError();
+}
+
+}  // namespace ri

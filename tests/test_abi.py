@@ -1,0 +1,73 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes its workspaces, and rejects bad arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2407_19614_amd as P
+from paper_2407_19614_amd import binding as Bd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "ri.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ri_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    names = header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(Bd.EXPORTED)
+
+
+def test_status_strings_and_version():
+    assert P.ri_status_str(0) == "ok"
+    assert "positive definite" in P.ri_status_str(2)
+    assert P.lib().ri_version().startswith(b"libri")
+
+
+def test_workspace_and_packed_sizes():
+    # packed tiles: 16 x 17 / 2 tiles of 64 x 64 per auxiliary function at N=1000
+    assert P.packed_b_bytes(1000, 3000, P.FP64) == 3000 * 136 * 4096 * 8
+    assert P.packed_b_bytes(1000, 3000, P.FP32) == 3000 * 136 * 4096 * 4
+    assert P.packed_b_bytes(1000, 3000, P.BF16X3) == 3000 * 136 * 4096 * 2 * 2
+    for op in range(4):
+        assert P.workspace_bytes(op, 32, 80, 8, 528, P.FP64) > 0
+    assert P.workspace_bytes(0, 0, 80, 8, 528, P.FP64) == 0
+    assert P.workspace_bytes(2, 32, 80, 8, -1, P.FP64) == 0
+    # the Fock workspace holds X^T (n_aux * n_occ * Npad doubles)
+    assert P.workspace_bytes(2, 1000, 3000, 100, 68799, P.FP64) >= 3000 * 100 * 1024 * 8
+
+
+def test_bad_arguments_rejected_before_device_work():
+    lib = P.lib()
+    n = ctypes.c_int64(0)
+    assert lib.ri_build_3c(None, 0.0, None, 0, ctypes.byref(n), None, None, 0, None) == 1
+    s = Bd.RISystem(0, 0, 0, 0, None, None, None, None, None, None)
+    assert lib.ri_build_3c(ctypes.byref(s), 0.0, None, 0, ctypes.byref(n), None, None, 0, None) == 1
+    assert lib.ri_fock_jk(0, 10, 2, None, 0, None, None, 0, None, None, None, None, None, 0, None) == 1
+    assert lib.ri_fock_jk(10, 10, 20, None, 0, None, None, 0, None, None, None, None, None, 0, None) == 1
+    bad = ctypes.c_int64(0)
+    assert lib.ri_metric_factor(ctypes.byref(s), None, 0, None, None, None, None, 0, ctypes.byref(bad), None, 0,
+                                None) == 1
+    opts = Bd.SCFOpts(0, 6, 1e-10, 1e-8, 0)
+    res = Bd.SCFResult()
+    assert lib.ri_energy(ctypes.byref(s), None, 0, None, None, 0, ctypes.byref(opts), None, None, None, None,
+                         ctypes.byref(res), None, 0, None) == 1
+
+
+def test_product_path_has_no_oracle_import():
+    pkg = os.path.join(ROOT, "paper_2407_19614_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f

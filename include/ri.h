@@ -140,6 +140,18 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
                    const double* C_occ, double* J, double* K, double* gamma,
                    void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ri_fock_jk_timed - ri_fock_jk with phase events, for measurement.
+ * Same computation and arguments as ri_fock_jk (paper: eq. j_ri, eq. k_ri_2,
+ * eq. tp, Algorithm 1 Fock-build loop); additionally records, on `stream`,
+ *   events[0] before the gamma/J contraction, events[1] before the exchange
+ *   half-transform X^P = B^P C_occ, events[2] before the K = sum X X^T SYRK
+ *   and its reduction, events[3] after the last kernel.
+ * events: four events created by the caller (host array). */
+int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
+                         const double* Bc, const int32_t* pairs, int64_t n_pairs,
+                         const double* C_occ, double* J, double* K, double* gamma,
+                         void* ws, size_t ws_bytes, hipStream_t stream, hipEvent_t* events);
+
 typedef struct {
     int32_t max_iter;      /* default 100                                       */
     int32_t diis_n;        /* DIIS subspace size, 1..8 (default 6)              */

@@ -72,12 +72,12 @@ def analytic_gradient(sys, res, ri: RIData | None = None, parts=False):
     g3 = np.zeros_like(sys.xyz)
     mu, nu = ri.mu, ri.nu
     Dp = D[mu, nu]
-    dA, dB = ints.eri3_derivs_pairs(sys, mu, nu)
     for P in range(na):
+        dA, dB = ints.eri3_derivs_pairs(sys, mu, nu, [P])
         V = Co @ Xi[P] @ Co.T
         Y = (c[P] * Dp - 2.0 * V[mu, nu]) * ri.w
-        cA = Y[:, None] * dA[P]
-        cB = Y[:, None] * dB[P]
+        cA = Y[:, None] * dA[0]
+        cB = Y[:, None] * dB[0]
         _scatter(g3, fc[mu], cA)
         _scatter(g3, fc[nu], cB)
         g3[sys.aux_centre[P]] -= cA.sum(0) + cB.sum(0)

@@ -208,8 +208,9 @@ def nuclear_derivs(sys):
     return dA, dB, dC
 
 
-def eri3_derivs_pairs(sys, mu_idx, nu_idx):
-    """d(mu nu|P)/dA and /dB for the listed pairs: [N_aux, n_pairs, 3] each.
+def eri3_derivs_pairs(sys, mu_idx, nu_idx, aux_idx=None):
+    """d(mu nu|P)/dA and /dB for the listed pairs: [n_P, n_pairs, 3] each,
+    over the auxiliary functions aux_idx (default: all).
     The derivative w.r.t. the auxiliary centre is -(dA + dB)."""
     A = sys.xyz[sys.fn_centre[mu_idx]]
     B = sys.xyz[sys.fn_centre[nu_idx]]
@@ -219,8 +220,9 @@ def eri3_derivs_pairs(sys, mu_idx, nu_idx):
     P = (a[:, None] * A + b[:, None] * B) / p[:, None]
     m = a * b / p
     K = np.exp(-m * ((A - B) ** 2).sum(-1)) * norm(a) * norm(b)
-    R = sys.xyz[sys.aux_centre]
-    al = sys.aux_exp
+    aux_idx = np.arange(sys.n_aux) if aux_idx is None else np.asarray(aux_idx)
+    R = sys.xyz[sys.aux_centre[aux_idx]]
+    al = sys.aux_exp[aux_idx]
     dA = np.empty((al.size, p.size, 3))
     dB = np.empty((al.size, p.size, 3))
     for k in range(al.size):

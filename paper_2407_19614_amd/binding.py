@@ -60,6 +60,9 @@ _SIGS = {
                                    c_int32, POINTER(c_int64), c_void_p, c_size_t, c_void_p]),
     "ri_fock_jk": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p,
                              c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ri_fock_jk_timed": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                                   ctypes.POINTER(c_void_p)]),
     "ri_energy": (c_int32, [POINTER(RISystem), c_void_p, c_int32, c_void_p, c_void_p, c_int64, POINTER(SCFOpts),
                             c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SCFResult), c_void_p, c_size_t,
                             c_void_p]),
@@ -212,6 +215,17 @@ class RIProblem:
                                 _ptr(ws), nb, self.stream())
         _check(code, "ri_fock_jk")
         return J, K, gamma
+
+    def fock_jk_timed(self, C_occ, J, K, gamma, events):
+        """ri_fock_jk with four torch.cuda.Event objects recorded by the
+        library at its phase boundaries (gamma/J, X, K, end)."""
+        C_occ = C_occ.contiguous()
+        ws, nb = self._ws_for(OP_FOCK)
+        arr = (c_void_p * 4)(*[ctypes.c_void_p(e.cuda_event) for e in events])
+        code = lib().ri_fock_jk_timed(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.prec, _ptr(self.T),
+                                      _ptr(self.pairs), self.n_pairs, _ptr(C_occ), _ptr(J), _ptr(K), _ptr(gamma),
+                                      _ptr(ws), nb, self.stream(), arr)
+        _check(code, "ri_fock_jk_timed")
 
     def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True):
         torch = self.torch

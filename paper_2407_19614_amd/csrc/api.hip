@@ -109,13 +109,38 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     return w;
 }
 
+struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part; void* Xt; };
+GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec) {
+    GradWS w;
+    const int Npad = ri::n_tiles_1d(N) * 64;
+    const int64_t n2 = (int64_t)N * N, o2 = (int64_t)n_occ * n_occ;
+    w.D = a.take<double>(n2);
+    w.W = a.take<double>(n2);
+    w.T1 = a.take<double>(n2);
+    w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
+    w.gamma = a.take<double>(n_aux);
+    w.c = a.take<double>(n_aux);
+    w.Bij = a.take<double>((int64_t)n_aux * o2);
+    w.Xi = a.take<double>((int64_t)n_aux * o2);
+    w.Zx = a.take<double>((int64_t)n_aux * n_aux);
+    w.part = a.take<double>((int64_t)(3 * ri::GRAD_BLOCKS + 1) * 3 * std::max(n_centres, 1));
+    // X^T for B_ij, reused afterwards for U^P = C Xi^P ([n_aux][N][n_occ])
+    w.Xt = a.take<char>((int64_t)n_aux * n_occ * Npad * (int64_t)(prec == RI_FP64 ? 8 : 4) + 8);
+    (void)prec;
+    return w;
+}
+
 int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const double* C, double* J, double* K, double* gamma, const FockWS& w,
-                  hipStream_t st) {
+                  hipStream_t st, hipEvent_t* ev = nullptr) {
     double* g = gamma ? gamma : w.gamma;
+    if (ev) HIPC(hipEventRecord(ev[0], st));
     HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, st));
+    if (ev) HIPC(hipEventRecord(ev[1], st));
     HIPC(ri::x_transform(B, prec, N, n_aux, n_occ, C, w.Xt, st));
+    if (ev) HIPC(hipEventRecord(ev[2], st));
     HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
+    if (ev) HIPC(hipEventRecord(ev[3], st));
     return RI_OK;
 }
 
@@ -198,7 +223,7 @@ size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, i
         case RI_OP_METRIC: carve_metric(a, N, n_aux, n_pairs); break;
         case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec); break;
         case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8); break;
-        case RI_OP_GRADIENT: return 0;
+        case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec); break;
         default: return 0;
     }
     return a.off + 256;
@@ -269,6 +294,20 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
     FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
     if (!a.ok()) return RI_E_WORKSPACE;
     return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st);
+}
+
+int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec, const double* Bc,
+                         const int32_t* pairs, int64_t n_pairs, const double* C, double* J, double* K,
+                         double* gamma, void* ws, size_t ws_bytes, hipStream_t st, hipEvent_t* events) {
+    if (!events || !events[0] || !events[1] || !events[2] || !events[3]) return RI_E_ARG;
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
+        (n_pairs > 0 && (!Bc || !pairs)))
+        return RI_E_ARG;
+    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st, events);
 }
 
 int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const double* Bc, const int32_t* pairs,
@@ -382,9 +421,46 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
     return converged ? RI_OK : RI_E_NO_CONV;
 }
 
-int32_t ri_gradient(const ri_system*, const int32_t*, int64_t, const void*, int32_t, const double*, const double*,
-                    const double*, const double*, double*, void*, size_t, hipStream_t) {
-    return RI_E_UNSUPPORTED;
+int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, const void* B, int32_t prec,
+                    const double* Bc, const double* Linv, const double* C, const double* F, double* grad, void* ws,
+                    size_t ws_bytes, hipStream_t st) {
+    if (!valid_sys(sys) || !B || !Linv || !C || !F || !grad || !ws || n_pairs < 0 || (n_pairs > 0 && (!Bc || !pairs)))
+        return RI_E_ARG;
+    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    if (sys->n_centres > 2048) return RI_E_UNSUPPORTED;
+    const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, nc = sys->n_centres;
+    const int Npad = ri::n_tiles_1d(N) * 64;
+    const int64_t o2 = (int64_t)no * no;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    GradWS w = carve_grad(a, N, na, no, n_pairs, 2048, prec);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    // D = 2 C C^T, W = 1/2 D F D
+    HIPC(ri::gemm_f64(false, true, N, N, no, 2.0, C, no, 0, C, no, 0, 0.0, w.D, N, 0, 1, 0, 0, st));
+    HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, F, N, 0, w.D, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
+    HIPC(ri::gemm_f64(false, false, N, N, N, 0.5, w.D, N, 0, w.T1, N, 0, 0.0, w.W, N, 0, 1, 0, 0, st));
+    // gamma = L^{-1} d and c = L^{-T} gamma = A^{-1} d
+    HIPC(ri::gamma_only(Bc, pairs, n_pairs, na, no, C, w.dpair, w.gamma, st));
+    HIPC(ri::gemm_f64(true, false, na, 1, na, 1.0, Linv, na, 0, w.gamma, 1, 0, 0.0, w.c, 1, 0, 1, 2, 0, st));
+    // B_ij^P = (C^T B^P C)_ij from X^P = B^P C
+    HIPC(ri::x_transform(B, prec, N, na, no, C, w.Xt, st));
+    HIPC(ri::gemm_f64(false, false, no, no, N, 1.0, (const double*)w.Xt, Npad, (int64_t)no * Npad, C, no, 0, 0.0,
+                      w.Bij, no, o2, na, 0, 0, st));
+    // Xi = L^{-T} B_ij  (columns ij)
+    HIPC(ri::gemm_f64(true, false, na, (int)o2, na, 1.0, Linv, na, 0, w.Bij, o2, 0, 0.0, w.Xi, o2, 0, 1, 2, 0, st));
+    // Zx = -2 sum_ij Xi_ij Xi_ij^T (lower tiles); Z = c c^T + Zx inside the contraction
+    HIPC(ri::gemm_f64(false, true, na, na, (int)o2, -2.0, w.Xi, o2, 0, w.Xi, o2, 0, 0.0, w.Zx, na, 0, 1, 0, 1, st));
+    // U^P = C Xi^P  (stored over the X buffer)
+    double* U = (double*)w.Xt;
+    HIPC(ri::gemm_f64(false, false, N, no, no, 1.0, C, no, 0, w.Xi, no, o2, 0.0, U, no, (int64_t)N * no, na, 0, 0,
+                      st));
+    const int GB = ri::GRAD_BLOCKS;
+    const int64_t rowlen = 3 * (int64_t)nc;
+    HIPC(ri::grad_one_electron(sys, w.D, w.W, w.part, st));
+    HIPC(ri::grad_metric(sys, w.Zx, w.c, w.part + GB * rowlen, st));
+    HIPC(ri::grad_three_centre(sys, pairs, n_pairs, U, C, no, w.D, w.c, w.part + 2 * GB * rowlen, st));
+    HIPC(ri::grad_nuclear(sys, w.part + 3 * GB * rowlen, st));
+    HIPC(ri::grad_reduce(w.part, 3 * GB + 1, nc, grad, st));
+    return RI_OK;
 }
 
 }  // extern "C"

@@ -52,3 +52,19 @@ hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st);
 hipError_t energy_terms(const double* D, const double* h, const double* J, const double* K, int64_t n,
                         const double* enuc, double* out, hipStream_t st);
 }  // namespace ri
+
+namespace ri {
+// ---- gradient (grad.hip).  Each contribution kernel runs on a fixed grid of
+// GRAD_BLOCKS blocks and writes one partial gradient row [n_centres*3] per
+// block into `part` (rows [row0, row0 + GRAD_BLOCKS)); grad_reduce sums rows.
+constexpr int GRAD_BLOCKS = 1024;
+hipError_t grad_one_electron(const ri_system* s, const double* D, const double* W, double* part, hipStream_t st);
+hipError_t grad_metric(const ri_system* s, const double* Z, const double* c, double* part, hipStream_t st);
+hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n_pairs, const double* U,
+                             const double* C, int n_occ, const double* D, const double* c, double* part,
+                             hipStream_t st);
+hipError_t grad_nuclear(const ri_system* s, double* part, hipStream_t st);
+hipError_t grad_reduce(const double* part, int rows, int n_centres, double* grad, hipStream_t st);
+hipError_t gamma_only(const double* Bc, const int32_t* pairs, int64_t n_pairs, int n_aux, int n_occ,
+                      const double* C, double* dpair, double* gamma, hipStream_t st);
+}  // namespace ri

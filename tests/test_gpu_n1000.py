@@ -1,0 +1,82 @@
+"""GPU parity at the N=1000 workload (the benchmark's configuration):
+100 He-like centres, N=1000, N_aux=3000, n_occ=100, tau=1e-12.
+
+Reference values come from tests/golden/n1000_oracle.json, written by
+tests/golden/make_golden.py from the CPU oracle; sampled three-centre rows
+are recomputed by the oracle here."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrals as I
+from tests.gpu_common import need_gpu, problem, to_np, dev
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "n1000_oracle.json")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    need_gpu()
+    if not os.path.exists(GOLD):
+        pytest.skip("golden file missing")
+    ref = json.load(open(GOLD))
+    s = synth.config_system("n1000")
+    print("case: n1000 build_3c + metric_factor", flush=True)
+    import paper_2407_19614_amd as P
+    pr = P.RIProblem(s)
+    pr.build_3c()
+    T_rows_idx = np.random.default_rng(5).choice(s.n_aux, 12, replace=False)
+    T_rows = to_np(pr.T[T_rows_idx])
+    pairs = to_np(pr.pairs)
+    pr.metric_factor(P.FP64)
+    return s, ref, pr, T_rows_idx, T_rows, pairs
+
+
+def test_pairs_and_sampled_three_centre(setup):
+    s, ref, pr, idx, T_rows, pairs = setup
+    assert pr.n_pairs == ref["n_pairs"]
+    assert int(pairs[:, 0].sum()) == ref["pair_mu_sum"] and int(pairs[:, 1].sum()) == ref["pair_nu_sum"]
+    assert np.all(pairs[:, 0] >= pairs[:, 1])
+    sub = synth.System(s.xyz, s.Z, s.fn_centre, s.fn_exp, s.aux_centre[idx], s.aux_exp[idx], s.n_occ, s.tau)
+    Tref = I.eri3_pairs(sub, pairs[:, 0].astype(np.int64), pairs[:, 1].astype(np.int64))
+    err = np.abs(T_rows - Tref)
+    assert np.all(err <= 1e-14 * np.abs(Tref).max() + 4e-16 * np.abs(Tref)), err.max()
+
+
+def test_fock_jk_sampled_rows(setup):
+    s, ref, pr, *_ = setup
+    print("case: n1000 fock_jk", flush=True)
+    C = synth.random_coeffs(s.N, s.n_occ, seed=ref["jk_seed"])
+    J, K, _ = pr.fock_jk(dev(C))
+    J, K = to_np(J), to_np(K)
+    rows = ref["rows"]
+    dJ = np.abs(J[rows] - np.array(ref["J_rows"])).max()
+    dK = np.abs(K[rows] - np.array(ref["K_rows"])).max()
+    print(f"max|dJ|={dJ:.2e} max|dK|={dK:.2e}", flush=True)
+    assert dJ < 1e-10 and dK < 1e-10
+    assert abs(np.trace(J) - ref["J_trace"]) < 1e-8 and abs(np.trace(K) - ref["K_trace"]) < 1e-8
+    assert np.abs(K - K.T).max() == 0.0 and np.abs(J - J.T).max() == 0.0
+    w = np.linalg.eigvalsh(K)
+    assert w.min() > -1e-12 * w.max()
+
+
+def test_energy_and_gradient(setup):
+    s, ref, pr, *_ = setup
+    print("case: n1000 energy", flush=True)
+    res, C, F, D = pr.energy(tol_E=1e-12, tol_err=1e-9)
+    dE = abs(res["E_total"] - ref["E_total"])
+    print(f"E={res['E_total']:.12f} ref={ref['E_total']:.12f} |dE|={dE:.2e} iters={res['n_iter']}", flush=True)
+    assert res["converged"] and dE < 1e-10
+    Cn = to_np(C)
+    Sm = I.overlap(s)
+    assert np.abs(Cn.T @ Sm @ Cn - np.eye(s.n_occ)).max() < 1e-10
+    print("case: n1000 gradient", flush=True)
+    g = to_np(pr.gradient())
+    dg = np.abs(g - np.array(ref["gradient"])).max()
+    print(f"max|dg|={dg:.2e}", flush=True)
+    assert dg < 1e-8
+    assert np.abs(g.sum(0)).max() < 1e-9

@@ -82,3 +82,18 @@ def test_energy_matches_oracle(tiny):
     C = to_np(C)
     Sm = I.overlap(s)
     assert np.abs(C.T @ Sm @ C - np.eye(s.n_occ)).max() < 1e-12
+
+
+def test_gradient_matches_oracle_and_fd(tiny):
+    s, ri = tiny
+    from oracle import gradient as G
+    print("case: tiny gradient", flush=True)
+    ref = S.run_scf(s, ri, tol_E=1e-12, tol_e=1e-10)
+    gref = G.analytic_gradient(s, ref, ri)
+    pr = problem(s)
+    res, C, F, D = pr.energy(tol_E=1e-12, tol_err=1e-10)
+    g = to_np(pr.gradient())
+    assert np.abs(g - gref).max() < 1e-8, np.abs(g - gref).max()
+    assert np.abs(g.sum(0)).max() < 1e-10
+    fd = G.fd_gradient(s, ref, atoms=[2])
+    assert np.abs(g[2] - fd[2]).max() < 1e-7

@@ -34,6 +34,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-pipeline", action="store_true", help="skip SCF/gradient phase timings")
     ap.add_argument("--calib", action="store_true", help="also run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--quick", action="store_true",
+                    help="profiling mode: seeded random occupied orbitals instead of the converged SCF "
+                         "(same shapes and kernels), no pipeline, no CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -61,7 +64,12 @@ def main():
 
     timed("build_3c_s", pr.build_3c)
     timed("metric_factor_s", lambda: pr.metric_factor(P.FP64))
-    res, C, F, D = timed("scf_s", lambda: pr.energy(tol_E=1e-10, tol_err=1e-8))
+    if args.quick:
+        args.no_pipeline = args.no_cpu = True
+        C = torch.tensor(synth.random_coeffs(s.N, s.n_occ, seed=0), dtype=torch.float64, device=dev)
+        res = {"E_total": None, "n_iter": 0, "converged": 0}
+    else:
+        res, C, F, D = timed("scf_s", lambda: pr.energy(tol_E=1e-10, tol_err=1e-8))
     if not args.no_pipeline:
         g = timed("gradient_s", pr.gradient)
     phases = {k: round(v, 4) for k, v in phases.items()}
@@ -115,7 +123,7 @@ def main():
         "scf": {"E_total": res["E_total"], "n_iter": res["n_iter"], "converged": res["converged"]},
     }
     gold = os.path.join(ROOT, "tests", "golden", "n1000_oracle.json")
-    if os.path.exists(gold):
+    if os.path.exists(gold) and not args.quick:
         ref = json.load(open(gold))
         out["scf"]["abs_dE_vs_oracle"] = abs(res["E_total"] - ref["E_total"])
         if not args.no_pipeline:

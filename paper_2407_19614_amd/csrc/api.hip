@@ -66,10 +66,10 @@ MetricWS carve_metric(Arena& a, int N, int n_aux, int64_t n_pairs) {
 struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* gamma; int ks, js; };
 FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec) {
     FockWS w;
-    const int Npad = ri::n_tiles_1d(N) * 64;
+    const int Npad = ri::xt_ld(N);
     w.ks = ri::k_split_count(N, n_aux, n_occ);
     w.js = ri::j_split_count(n_aux);
-    w.Xt = a.take<char>((int64_t)n_aux * n_occ * Npad * (int64_t)(prec == RI_FP64 ? 8 : 4));
+    w.Xt = a.take<char>(ri::xt_rows(n_aux, n_occ) * Npad * (int64_t)(prec == RI_FP64 ? 8 : 4));
     w.part = a.take<double>((int64_t)w.ks * Npad * Npad);
     w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
     w.jpart = a.take<double>((int64_t)w.js * std::max<int64_t>(n_pairs, 1));
@@ -112,7 +112,7 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
 struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part; void* Xt; };
 GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec) {
     GradWS w;
-    const int Npad = ri::n_tiles_1d(N) * 64;
+    const int Npad = ri::xt_ld(N);
     const int64_t n2 = (int64_t)N * N, o2 = (int64_t)n_occ * n_occ;
     w.D = a.take<double>(n2);
     w.W = a.take<double>(n2);
@@ -429,7 +429,7 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     if (prec != RI_FP64) return RI_E_UNSUPPORTED;
     if (sys->n_centres > 2048) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, nc = sys->n_centres;
-    const int Npad = ri::n_tiles_1d(N) * 64;
+    const int Npad = ri::xt_ld(N);
     const int64_t o2 = (int64_t)no * no;
     Arena a{(char*)ws, ws_bytes, 0, false};
     GradWS w = carve_grad(a, N, na, no, n_pairs, 2048, prec);

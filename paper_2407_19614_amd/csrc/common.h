@@ -18,6 +18,15 @@ __device__ __forceinline__ d4_t mfma_f64(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This bijection maps the hardware order onto a logical order in which
+// each XCD receives one contiguous run of logical workgroup ids, so that
+// neighbouring logical work (sharing operands) shares an L2.
+__device__ __forceinline__ int xcd_remap(int L, int W) {
+    const int q = W >> 3, r = W & 7, x = L & 7, s = L >> 3;
+    return x * q + min(x, r) + s;
+}
+
 __device__ __forceinline__ double norm_s(double a) {
     // (2a/pi)^{3/4}
     return pow(2.0 * a / RI_PI, 0.75);

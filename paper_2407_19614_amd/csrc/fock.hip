@@ -5,6 +5,8 @@
 // the compressed (significant-pair) tensor.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace {
 
 __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
@@ -42,58 +44,173 @@ __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_p
     }
 }
 
-// X^T for one (row-block I, auxiliary P): Xt[P][i][64I + m] = sum_nu C[nu][i] B^P[64I+m][nu].
-// MFMA rows = occupied index i (MT tiles of 16), columns = mu (4 waves x 16).
+// X^T for (row-block I, auxiliary pair P0, P0+1): each wave owns one P and
+// 32 columns mu (2 MFMA column tiles) over all MT occupied row tiles, so the
+// staged C_occ slice serves both P.  Next-slice global loads are held in
+// registers while the current slice is multiplied.
 template <int MT>
-__global__ __launch_bounds__(256) void x_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
-                                                    const double* __restrict__ C, int N, int n_occ,
-                                                    double* __restrict__ Xt, int Npad) {
-    const int I = blockIdx.x, P = blockIdx.y, i0 = blockIdx.z * 128;
-    const double* Bp = B + (int64_t)P * ntl * 4096;
+__global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
+                                                     const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                                     double* __restrict__ Xt, int Npad) {
+    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int I = L % gridDim.x, P0 = 2 * (L / gridDim.x), i0 = blockIdx.z * 128;
     constexpr int W = MT * 16;
+    __shared__ double Bs[2][16][65];
     __shared__ double Cs[16][W + 1];
-    __shared__ double Bs[16][65];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-    d4_t acc[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m] = d4_t{0.0, 0.0, 0.0, 0.0};
-    for (int J = 0; J < nt; ++J) {
+    const int ps = wave >> 1, h = wave & 1;
+    const bool has1 = P0 + 1 < n_aux;
+    const double* Bp0 = B + (int64_t)P0 * ntl * 4096;
+    const double* Bp1 = B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096;
+    double rb[8], rc[MT];
+    auto load = [&](int J, int k0) {
         const bool lower = J <= I;
-        const double* tp = Bp + (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
-        for (int k0 = 0; k0 < 64; k0 += 16) {
-            __syncthreads();
+        const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (lower) {
-                    int k = tid & 15, m = (tid >> 4) + 16 * r;
-                    Bs[k][m] = tp[m * 64 + k0 + k];
-                } else {
-                    int m = tid & 63, k = (tid >> 6) + 4 * r;
-                    Bs[k][m] = tp[(k0 + k) * 64 + m];
-                }
-            }
-            for (int e = tid; e < 16 * W; e += 256) {
-                int k = e / W, i = e % W;
-                int nu = 64 * J + k0 + k, gi = i0 + i;
-                Cs[k][i] = (nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
-            }
-            __syncthreads();
+        for (int r = 0; r < 4; ++r) {
+            int off;
+            if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
+            else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
+            rb[r] = Bp0[toff + off];
+            rb[4 + r] = has1 ? Bp1[toff + off] : 0.0;
+        }
 #pragma unroll
-            for (int kk = 0; kk < 16; kk += 4) {
-                double b = Bs[kk + lk][wave * 16 + li];
+        for (int r = 0; r < MT; ++r) {
+            int e = tid + 256 * r, k = e / W, i = e % W;
+            int nu = 64 * J + k0 + k, gi = i0 + i;
+            rc[r] = (nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
+        }
+    };
+    auto store = [&](int J) {
+        const bool lower = J <= I;
 #pragma unroll
-                for (int m = 0; m < MT; ++m) acc[m] = mfma_f64(Cs[kk + lk][m * 16 + li], b, acc[m]);
+        for (int r = 0; r < 4; ++r) {
+            int k, m;
+            if (lower) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            else       { m = tid & 63; k = (tid >> 6) + 4 * r; }
+            Bs[0][k][m] = rb[r];
+            Bs[1][k][m] = rb[4 + r];
+        }
+#pragma unroll
+        for (int r = 0; r < MT; ++r) {
+            int e = tid + 256 * r;
+            Cs[e / W][e % W] = rc[r];
+        }
+    };
+    d4_t acc[MT][2];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) { acc[m][0] = d4_t{0, 0, 0, 0}; acc[m][1] = d4_t{0, 0, 0, 0}; }
+    const int nsl = nt * 4;
+    load(0, 0);
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int J = sl >> 2;
+        __syncthreads();
+        store(J);
+        __syncthreads();
+        if (sl + 1 < nsl) load((sl + 1) >> 2, ((sl + 1) & 3) * 16);
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            double b0 = Bs[ps][kk + lk][h * 32 + li], b1 = Bs[ps][kk + lk][h * 32 + 16 + li];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                double a = Cs[kk + lk][m * 16 + li];
+                acc[m][0] = mfma_f64(a, b0, acc[m][0]);
+                acc[m][1] = mfma_f64(a, b1, acc[m][1]);
             }
         }
     }
-    const int mu = 64 * I + wave * 16 + li;
+    const int P = P0 + ps;
+    if (P >= n_aux) return;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int i = i0 + m * 16 + 4 * r + lk;
-            if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + mu] = acc[m][r];
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int i = i0 + m * 16 + 4 * r + lk;
+                if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = acc[m][n][r];
+            }
+}
+
+// Exchange SYRK, K_part[z] = sum over rows r of split z of Xt[r][m] Xt[r][n],
+// for the lower 128 x 128 tiles only.  Rows of Xt are streamed through an
+// S-stage LDS ring filled by direct global->LDS loads (global_load_lds, 16 B
+// per lane: one wave moves one 1 KB tile row per instruction), so several
+// k-steps of loads are in flight without staging registers.  One barrier per
+// k-step.  Row r is (P, i) flattened; the buffer carries >= 16 zero rows past
+// the last real row, so split ends and the pipeline's look-ahead loads stay
+// in bounds and contribute nothing.
+typedef __attribute__((address_space(3))) void* lds_void_t;
+
+template <int S>
+__global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restrict__ X, int Npad, int64_t rows_pad,
+                                                          int64_t chunk, int ntile, double* __restrict__ part) {
+    constexpr int LDR = 128 + 16;                  // LDS row stride (doubles)
+    __shared__ double As[S][16 * LDR];
+    __shared__ double Bs[S][16 * LDR];
+    const int nlow = ntile * (ntile + 1) / 2;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int z = L / nlow, t = L % nlow;
+    int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int m0 = ti * 128, n0 = tj * 128;
+    const int64_t r0 = (int64_t)z * chunk;
+    const int64_t r1 = min(rows_pad, r0 + chunk);
+    const int nsteps = (int)((r1 - r0) / 16);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // each wave moves rows 4*wave .. 4*wave+3 of the A and B 16-row slabs
+    auto issue = [&](int step, int buf) {
+        int64_t rb = r0 + (int64_t)step * 16;
+        if (rb >= rows_pad) rb = rows_pad;          // zero tail rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 4 * wave + q;
+            const double* ga = X + (rb + row) * Npad + m0 + 2 * lane;
+            const double* gb = X + (rb + row) * Npad + n0 + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void*)ga, (lds_void_t)(&As[buf][row * LDR]), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)gb, (lds_void_t)(&Bs[buf][row * LDR]), 16, 0, 0);
         }
+    };
+    d4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) issue(s, s);
+    for (int k = 0; k < nsteps; ++k) {
+        // this wave's loads for step k are done once at most (S-2)*8 younger ones remain
+        __builtin_amdgcn_s_waitcnt(((S - 2) * 8 & 0xF) | ((((S - 2) * 8) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+        __builtin_amdgcn_s_barrier();
+        issue(k + S - 1, (k + S - 1) % S);
+        const double* as = As[k % S];
+        const double* bs = Bs[k % S];
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = as[(kk + lk) * LDR + wm + 16 * i + li];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = bs[(kk + lk) * LDR + wn + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0): LDS reads of this buffer done
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    double* out = part + (int64_t)z * Npad * Npad;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(int64_t)(m0 + wm + 16 * i + 4 * r + lk) * Npad + n0 + wn + 16 * j + li] = acc[i][j][r];
 }
 
 __global__ void kreduce_kernel(const double* part, int n_split, int Npad, int N, double* K) {
@@ -177,15 +294,15 @@ hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, 
 
 hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, void* Xt,
                        hipStream_t st) {
-    const int nt = n_tiles_1d(N), Npad = nt * 64;
+    const int nt = n_tiles_1d(N), Npad = xt_ld(N);
     if (prec != RI_FP64) return hipErrorInvalidValue;
     const int mt = (min(n_occ, 128) + 15) / 16;
-    dim3 grid(nt, n_aux, (n_occ + 127) / 128);
+    dim3 grid(nt, (n_aux + 1) / 2, (n_occ + 127) / 128);
     const double* b = (const double*)B;
     double* x = (double*)Xt;
     const int64_t ntl = n_tiles(N);
     switch (mt) {
-#define XCASE(k) case k: x_kernel_f64<k><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, x, Npad); break;
+#define XCASE(k) case k: x2_kernel_f64<k><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
         XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
 #undef XCASE
         default: return hipErrorInvalidValue;
@@ -194,37 +311,37 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
 }
 
 int k_split_count(int N, int n_aux, int n_occ) {
+    // One round of workgroups: 2 resident 128 x 128 tiles per CU on 256 CUs.
     const int nt = n_tiles_1d(N);
-    const int64_t tiles = (int64_t)nt * (nt + 1) / 2;
-    int64_t rows = (int64_t)n_aux * n_occ;
-    int s = (int)((2048 + tiles - 1) / tiles);
-    if (s < 1) s = 1;
+    const int t128 = (nt + 1) / 2;
+    const int64_t tiles = (int64_t)t128 * (t128 + 1) / 2;     // lower 128 x 128 tiles
+    const int64_t steps = ((int64_t)n_aux * n_occ + 15) / 16;
+    int s = (int)std::max<int64_t>(1, 512 / tiles);
     if (s > 64) s = 64;
-    if (rows < (int64_t)s * 64) s = (int)((rows + 63) / 64);
-    return s < 1 ? 1 : s;
+    if (steps < s) s = (int)std::max<int64_t>(1, steps);
+    return s;
 }
+
+// Rows of the Xt buffer: n_aux * n_occ rounded up to 16, plus 16 zero rows.
+int64_t xt_rows(int n_aux, int n_occ) { return ((int64_t)n_aux * n_occ + 15) / 16 * 16 + 16; }
+
+// Row stride of Xt and of the K partial tiles: N rounded up to 128.
+int xt_ld(int N) { return (N + 127) / 128 * 128; }
 
 hipError_t k_syrk(const void* Xt, int prec, int N, int n_aux, int n_occ, double* part, int n_split,
                   double* K, hipStream_t st) {
     if (prec != RI_FP64) return hipErrorInvalidValue;
-    const int nt = n_tiles_1d(N), Npad = nt * 64;
+    const int Npad = xt_ld(N), t128 = Npad / 128;
     const int64_t rows = (int64_t)n_aux * n_occ;
-    const int64_t chunk = ((rows + n_split - 1) / n_split + 15) / 16 * 16;
-    const double* x = (const double*)Xt;
-    const int64_t sq = (int64_t)Npad * Npad;
-    int full = (int)(rows / chunk);
-    if (full > n_split) full = n_split;
-    if (full > 0)
-        RI_TRY(gemm_f64(true, false, Npad, Npad, (int)chunk, 1.0, x, Npad, chunk * Npad, x, Npad,
-                        chunk * Npad, 0.0, part, Npad, sq, full, 0, 1, st));
-    int used = full;
-    int64_t rem = rows - (int64_t)full * chunk;
-    if (rem > 0) {
-        const double* xr = x + (int64_t)full * chunk * Npad;
-        RI_TRY(gemm_f64(true, false, Npad, Npad, (int)rem, 1.0, xr, Npad, 0, xr, Npad, 0, 0.0,
-                        part + (int64_t)full * sq, Npad, 0, 1, 0, 1, st));
-        ++used;
-    }
+    const int64_t rows_pad = (rows + 15) / 16 * 16;
+    double* x = (double*)Xt;
+    // zero the padding rows (real rows .. rows_pad + 16)
+    RI_TRY(fill(x + rows * Npad, 0.0, (rows_pad + 16 - rows) * Npad, st));
+    const int64_t chunk = ((rows_pad + n_split - 1) / n_split + 15) / 16 * 16;
+    const int used = (int)((rows_pad + chunk - 1) / chunk);
+    const int nlow = t128 * (t128 + 1) / 2;
+    syrk_lds_kernel<2><<<nlow * used, 256, 0, st>>>(x, Npad, rows_pad, chunk, t128, part);
+    RI_TRY(hipGetLastError());
     dim3 grid((N + 255) / 256, N);
     kreduce_kernel<<<grid, 256, 0, st>>>(part, used, Npad, N, K);
     return hipGetLastError();

@@ -17,11 +17,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
     const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int tri, int lowerC) {
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+    const int m0 = by * BM, n0 = bx * BN;
     if (lowerC && n0 > m0 + BM - 1) return;
-    A += (int64_t)blockIdx.z * sA;
-    B += (int64_t)blockIdx.z * sB;
-    C += (int64_t)blockIdx.z * sC;
+    A += (int64_t)bz * sA;
+    B += (int64_t)bz * sB;
+    C += (int64_t)bz * sC;
     __shared__ double As[BK][LDP];
     __shared__ double Bs[BK][LDP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -94,6 +97,98 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
+                if (gm < M && gn < N) {
+                    double* c = C + (int64_t)gm * ldc + gn;
+                    double v = alpha * acc[i][j][r];
+                    *c = (beta == 0.0) ? v : v + beta * *c;
+                }
+            }
+}
+
+// 128 x 128 variant: 4 waves in 2 x 2, each owning 64 x 64 of C as 4 x 4 MFMA
+// tiles (64 FP64 accumulators per lane).  Same staging scheme as above.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
+    const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int tri, int lowerC) {
+    constexpr int TM = 128, TN = 128, LD = TM + 1;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+    const int m0 = by * TM, n0 = bx * TN;
+    if (lowerC && n0 > m0 + TM - 1) return;
+    A += (int64_t)bz * sA;
+    B += (int64_t)bz * sB;
+    C += (int64_t)bz * sC;
+    __shared__ double As[BK][LD];
+    __shared__ double Bs[BK][LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    int kbeg = 0, kend = K;
+    if (tri == 1) kend = min(K, m0 + TM);
+    if (tri == 2) kbeg = (m0 / BK) * BK;
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int m, k;
+            if (!TA) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            else     { m = tid & 127; k = (tid >> 7) + 2 * r; }
+            int gm = m0 + m, gk = k0 + k;
+            ra[r] = (gm < M && gk < kend) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0;
+            int n, kb;
+            if (!TB) { n = tid & 127; kb = (tid >> 7) + 2 * r; }
+            else     { kb = tid & 15; n = (tid >> 4) + 16 * r; }
+            int gn = n0 + n, gkb = k0 + kb;
+            rb[r] = (gn < N && gkb < kend) ? (TB ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn]) : 0.0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int m, k;
+            if (!TA) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            else     { m = tid & 127; k = (tid >> 7) + 2 * r; }
+            As[k][m] = ra[r];
+            int n, kb;
+            if (!TB) { n = tid & 127; kb = (tid >> 7) + 2 * r; }
+            else     { kb = tid & 15; n = (tid >> 4) + 16 * r; }
+            Bs[kb][n] = rb[r];
+        }
+    };
+    d4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const int li = lane & 15, lk = lane >> 4;
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk + lk][wm + 16 * i + li];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk + lk][wn + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
@@ -224,6 +319,19 @@ hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const d
                     double beta, double* C, int64_t ldc, int64_t sC, int batch, int tri,
                     int lowerC, hipStream_t s) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    // 128-wide tiles when they still give a few hundred workgroups
+    const int64_t big_tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128) * batch;
+    const bool big = M >= 128 && N >= 128 && big_tiles >= 200;
+    if (big) {
+        dim3 grid((N + 127) / 128, (M + 127) / 128, batch);
+#define G128(a, b) gemm_f64_128_kernel<a, b><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC)
+        if (!ta && !tb) G128(false, false);
+        else if (!ta && tb) G128(false, true);
+        else if (ta && !tb) G128(true, false);
+        else G128(true, true);
+#undef G128
+        return hipGetLastError();
+    }
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
     if (!ta && !tb)
         gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC);

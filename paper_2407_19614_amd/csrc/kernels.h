@@ -29,6 +29,8 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
 hipError_t k_syrk(const void* Xt, int prec, int N, int n_aux, int n_occ, double* part, int n_split,
                   double* K, hipStream_t st);
 int k_split_count(int N, int n_aux, int n_occ);
+int64_t xt_rows(int n_aux, int n_occ);
+int xt_ld(int N);
 // gamma and J from the compressed FP64 tensor.
 hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
                    int n_occ, const double* C, double* dpair, double* gamma, double* jpart,

@@ -128,6 +128,8 @@ def main():
         out["scf"]["abs_dE_vs_oracle"] = abs(res["E_total"] - ref["E_total"])
         if not args.no_pipeline:
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
+    if not args.quick:
+        out["precision"] = precision_leg(s, C, res, args, P, torch, np)
     if args.calib:
         src = torch.empty(2 ** 28, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -138,6 +140,36 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, C.cpu().numpy())
     print(json.dumps(out), flush=True)
+
+
+def precision_leg(s, C, res64, args, P, torch, np):
+    """FP32 exchange contractions at the same workload: Fock builds/s, speedup
+    over FP64, and the FP32 SCF energy's difference from the FP64 one."""
+    dev = C.device
+    pr = P.RIProblem(s, device=dev, prec=P.FP32)
+    pr.build_3c()
+    pr.metric_factor(P.FP32)
+    N, na = s.N, s.n_aux
+    J = torch.empty((N, N), dtype=torch.float64, device=dev)
+    K = torch.empty_like(J)
+    g = torch.empty(na, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        pr.fock_jk(C, J, K, g)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        pr.fock_jk(C, J, K, g)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    # FP32 exchange leaves a commutator floor near 1e-6: converge on |dE| with a looser error bound
+    r32, *_ = pr.energy(tol_E=1e-9, tol_err=1e-5, max_iter=60, raise_on_noconv=False)
+    out = {"fp32_builds_per_s": round(1.0 / dt, 3), "fp32_ms_per_build": round(dt * 1e3, 3),
+           "fp32_scf_E": r32["E_total"], "fp32_scf_iters": r32["n_iter"],
+           "fp32_scf_converged": r32["converged"], "fp32_scf_max_err": r32["max_err"],
+           "fp32_abs_dE_vs_fp64": abs(r32["E_total"] - res64["E_total"])}
+    del pr
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(s, C):

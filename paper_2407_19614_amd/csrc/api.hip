@@ -63,7 +63,7 @@ MetricWS carve_metric(Arena& a, int N, int n_aux, int64_t n_pairs) {
     return w;
 }
 
-struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* gamma; int ks, js; };
+struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* gamma; double* Cp; int ks, js; };
 FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec) {
     FockWS w;
     const int Npad = ri::xt_ld(N);
@@ -74,6 +74,7 @@ FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int pr
     w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
     w.jpart = a.take<double>((int64_t)w.js * std::max<int64_t>(n_pairs, 1));
     w.gamma = a.take<double>(n_aux);
+    w.Cp = a.take<double>(ri::cpad_elems(N, n_occ));
     return w;
 }
 
@@ -109,7 +110,7 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     return w;
 }
 
-struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part; void* Xt; };
+struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part, *Cp; void* Xt; float* Xt32; };
 GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec) {
     GradWS w;
     const int Npad = ri::xt_ld(N);
@@ -124,9 +125,10 @@ GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_
     w.Xi = a.take<double>((int64_t)n_aux * o2);
     w.Zx = a.take<double>((int64_t)n_aux * n_aux);
     w.part = a.take<double>((int64_t)(3 * ri::GRAD_BLOCKS + 1) * 3 * std::max(n_centres, 1));
+    w.Cp = a.take<double>(ri::cpad_elems(N, n_occ));
     // X^T for B_ij, reused afterwards for U^P = C Xi^P ([n_aux][N][n_occ])
-    w.Xt = a.take<char>((int64_t)n_aux * n_occ * Npad * (int64_t)(prec == RI_FP64 ? 8 : 4) + 8);
-    (void)prec;
+    w.Xt = a.take<char>((int64_t)n_aux * n_occ * Npad * 8 + 8);
+    w.Xt32 = prec == RI_FP32 ? a.take<float>((int64_t)n_aux * n_occ * Npad) : nullptr;
     return w;
 }
 
@@ -137,7 +139,7 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
     if (ev) HIPC(hipEventRecord(ev[0], st));
     HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, st));
     if (ev) HIPC(hipEventRecord(ev[1], st));
-    HIPC(ri::x_transform(B, prec, N, n_aux, n_occ, C, w.Xt, st));
+    HIPC(ri::x_transform(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
     if (ev) HIPC(hipEventRecord(ev[2], st));
     HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
     if (ev) HIPC(hipEventRecord(ev[3], st));
@@ -289,7 +291,7 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
     if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
         (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
     Arena a{(char*)ws, ws_bytes, 0, false};
     FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
     if (!a.ok()) return RI_E_WORKSPACE;
@@ -303,7 +305,7 @@ int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B,
     if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
         (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
     Arena a{(char*)ws, ws_bytes, 0, false};
     FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
     if (!a.ok()) return RI_E_WORKSPACE;
@@ -320,7 +322,7 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
         return RI_E_ARG;
     if (opts->guess_kind == 1 && !guess) return RI_E_ARG;
     if (opts->guess_kind != 0 && opts->guess_kind != 1) return RI_E_UNSUPPORTED;
-    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
     Arena a{(char*)ws, ws_bytes, 0, false};
@@ -426,7 +428,7 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
                     size_t ws_bytes, hipStream_t st) {
     if (!valid_sys(sys) || !B || !Linv || !C || !F || !grad || !ws || n_pairs < 0 || (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec != RI_FP64) return RI_E_UNSUPPORTED;
+    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
     if (sys->n_centres > 2048) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, nc = sys->n_centres;
     const int Npad = ri::xt_ld(N);
@@ -442,7 +444,12 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     HIPC(ri::gamma_only(Bc, pairs, n_pairs, na, no, C, w.dpair, w.gamma, st));
     HIPC(ri::gemm_f64(true, false, na, 1, na, 1.0, Linv, na, 0, w.gamma, 1, 0, 0.0, w.c, 1, 0, 1, 2, 0, st));
     // B_ij^P = (C^T B^P C)_ij from X^P = B^P C
-    HIPC(ri::x_transform(B, prec, N, na, no, C, w.Xt, st));
+    if (prec == RI_FP32) {
+        HIPC(ri::x_transform(B, prec, N, na, no, C, w.Cp, w.Xt32, st));
+        HIPC(ri::widen(w.Xt32, (double*)w.Xt, (int64_t)na * no * Npad, st));
+    } else {
+        HIPC(ri::x_transform(B, prec, N, na, no, C, w.Cp, w.Xt, st));
+    }
     HIPC(ri::gemm_f64(false, false, no, no, N, 1.0, (const double*)w.Xt, Npad, (int64_t)no * Npad, C, no, 0, 0.0,
                       w.Bij, no, o2, na, 0, 0, st));
     // Xi = L^{-T} B_ij  (columns ij)

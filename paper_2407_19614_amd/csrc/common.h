@@ -89,6 +89,7 @@ hipError_t dot(const double* x, const double* y, int64_t n, double* out, hipStre
 hipError_t max_abs(const double* x, int64_t n, double* out, hipStream_t s);
 hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s); // y = a x + b y
 hipError_t copy(double* dst, const double* src, int64_t n, hipStream_t s);
+hipError_t widen(const float* x, double* y, int64_t n, hipStream_t s);   // y = (double) x
 
 }  // namespace ri
 

@@ -132,6 +132,318 @@ __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict
             }
 }
 
+typedef __attribute__((address_space(3))) void* lds_void_t;
+
+// X^T via direct global->LDS loads: same work split as x2_kernel_f64 (one
+// row-block I, two auxiliary indices per workgroup), but the B^P tile slices
+// and the C_occ slice are moved by global_load_lds into an S-stage LDS ring,
+// 16 B per lane.  That copy cannot transpose, so layouts are chosen per
+// orientation and XOR-swizzled at 16 B granularity to keep fragment reads
+// off shared banks:
+//   tile (I,J), J <= I, rows mu: slot(mu, chunk c) = mu*8 + (c ^ (mu & 7))
+//   tile (J,I), J > I, rows nu:  slot(nu, c)       = nu*32 + (c ^ ((nu & 1) << 3))
+//   C slice, rows nu:            slot(nu, c)       = nu*64 + (c ^ ((nu & 1) << 3))
+// Cp is C_occ zero-padded to [Npad][128 * zc] (zc = occupied chunks of 128).
+template <int MT, int S>
+__global__ __launch_bounds__(256, 2) void x3_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
+                                                        const double* __restrict__ Cp, int cld, int n_occ,
+                                                        int n_aux, double* __restrict__ Xt, int Npad) {
+    __shared__ double Bs[S][2][1024];     // 2 x (64 x 16) per stage
+    __shared__ double Cs[S][2048];        // 16 x 128 per stage
+    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int I = L % gridDim.x, P0 = 2 * (L / gridDim.x), i0 = blockIdx.z * 128;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int ps = wave >> 1, h = wave & 1;
+    const bool has1 = P0 + 1 < n_aux;
+    const double* Bp[2] = {B + (int64_t)P0 * ntl * 4096, B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096};
+    const int nsl = nt * 4;
+    // wave w issues: B slice of P (w >> 1), instructions 4*(w&1) .. +3; C rows 4w .. 4w+3
+    auto issue = [&](int sl, int buf) {
+        if (sl >= nsl) sl = nsl - 1;                  // look-ahead past the end: reload the last slice
+        const int J = sl >> 2, k0 = (sl & 3) * 16;
+        const bool lower = J <= I;
+        const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
+        const double* tp = Bp[ps] + toff;
+#pragma unroll
+        for (int q = 4 * h; q < 4 * h + 4; ++q) {
+            const int slot = q * 64 + lane;
+            const double* g;
+            if (lower) {
+                const int mu = slot >> 3, c = (slot & 7) ^ (mu & 7);
+                g = tp + mu * 64 + k0 + 2 * c;
+            } else {
+                const int nu = slot >> 5, c = (slot & 31) ^ ((nu & 1) << 3);
+                g = tp + (k0 + nu) * 64 + 2 * c;
+            }
+            __builtin_amdgcn_global_load_lds((const void*)g, (lds_void_t)(&Bs[buf][ps][q * 128]), 16, 0, 0);
+        }
+#pragma unroll
+        for (int q = 4 * wave; q < 4 * wave + 4; ++q) {
+            const int c = lane ^ ((q & 1) << 3);
+            const double* g = Cp + (int64_t)(64 * J + k0 + q) * cld + i0 + 2 * c;
+            __builtin_amdgcn_global_load_lds((const void*)g, (lds_void_t)(&Cs[buf][q * 128]), 16, 0, 0);
+        }
+    };
+    d4_t acc[MT][2];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) { acc[m][0] = d4_t{0, 0, 0, 0}; acc[m][1] = d4_t{0, 0, 0, 0}; }
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) issue(s, s);
+    for (int sl = 0; sl < nsl; ++sl) {
+        __builtin_amdgcn_s_waitcnt(((S - 2) * 8 & 0xF) | ((((S - 2) * 8) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+        __builtin_amdgcn_s_barrier();
+        issue(sl + S - 1, (sl + S - 1) % S);
+        const int buf = sl % S;
+        const bool lower = (sl >> 2) <= I;
+        const double* bs = Bs[buf][ps];
+        const double* cs = Cs[buf];
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int nu = kk + lk;
+            double b[2];
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const int mu = h * 32 + n * 16 + li;
+                int addr;
+                if (lower) addr = 2 * (mu * 8 + ((nu >> 1) ^ (mu & 7))) + (nu & 1);
+                else       addr = 2 * (nu * 32 + ((mu >> 1) ^ ((nu & 1) << 3))) + (mu & 1);
+                b[n] = bs[addr];
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int i = m * 16 + li;
+                const double a = cs[2 * (nu * 64 + ((i >> 1) ^ ((nu & 1) << 3))) + (i & 1)];
+                acc[m][0] = mfma_f64(a, b[0], acc[m][0]);
+                acc[m][1] = mfma_f64(a, b[1], acc[m][1]);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0)
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    const int P = P0 + ps;
+    if (P >= n_aux) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int i = i0 + m * 16 + 4 * r + lk;
+                if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = acc[m][n][r];
+            }
+}
+
+__global__ void cpad_kernel(const double* C, int N, int n_occ, int rows, int cld, double* Cp) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cld) return;
+    int r = e / cld, c = e % cld;
+    Cp[e] = (r < N && c < n_occ) ? C[(int64_t)r * n_occ + c] : 0.0;
+}
+
+// FP32 forms of the exchange contractions (precision extension): B in FP32,
+// v_mfma_f32_16x16x4f32 (lane l holds D[4*(l/16) + r][l%16]), X in FP32.
+__device__ __forceinline__ f4_t mfma_f32(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int MT>
+__global__ __launch_bounds__(256, 2) void x2_kernel_f32(const float* __restrict__ B, int nt, int64_t ntl,
+                                                        const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                                        float* __restrict__ Xt, int Npad) {
+    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int I = L % gridDim.x, P0 = 2 * (L / gridDim.x), i0 = blockIdx.z * 128;
+    constexpr int W = MT * 16;
+    __shared__ float Bs[2][16][65];
+    __shared__ float Cs[16][W + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int ps = wave >> 1, h = wave & 1;
+    const bool has1 = P0 + 1 < n_aux;
+    const float* Bp0 = B + (int64_t)P0 * ntl * 4096;
+    const float* Bp1 = B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096;
+    float rb[8], rc[MT];
+    auto load = [&](int J, int k0) {
+        const bool lower = J <= I;
+        const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int off;
+            if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
+            else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
+            rb[r] = Bp0[toff + off];
+            rb[4 + r] = has1 ? Bp1[toff + off] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < MT; ++r) {
+            int e = tid + 256 * r, k = e / W, i = e % W;
+            int nu = 64 * J + k0 + k, gi = i0 + i;
+            rc[r] = (nu < N && gi < n_occ) ? (float)C[(int64_t)nu * n_occ + gi] : 0.0f;
+        }
+    };
+    auto store = [&](int J) {
+        const bool lower = J <= I;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int k, m;
+            if (lower) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            else       { m = tid & 63; k = (tid >> 6) + 4 * r; }
+            Bs[0][k][m] = rb[r];
+            Bs[1][k][m] = rb[4 + r];
+        }
+#pragma unroll
+        for (int r = 0; r < MT; ++r) {
+            int e = tid + 256 * r;
+            Cs[e / W][e % W] = rc[r];
+        }
+    };
+    f4_t acc[MT][2];
+    d4_t acc64[MT][2];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        acc[m][0] = acc[m][1] = f4_t{0, 0, 0, 0};
+        acc64[m][0] = acc64[m][1] = d4_t{0, 0, 0, 0};
+    }
+    const int nsl = nt * 4;
+    load(0, 0);
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int J = sl >> 2;
+        __syncthreads();
+        store(J);
+        __syncthreads();
+        if (sl + 1 < nsl) load((sl + 1) >> 2, ((sl + 1) & 3) * 16);
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            float b0 = Bs[ps][kk + lk][h * 32 + li], b1 = Bs[ps][kk + lk][h * 32 + 16 + li];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                float a = Cs[kk + lk][m * 16 + li];
+                acc[m][0] = mfma_f32(a, b0, acc[m][0]);
+                acc[m][1] = mfma_f32(a, b1, acc[m][1]);
+            }
+        }
+        if ((sl & 3) == 3) {   // FP32 over one 64-wide nu tile, FP64 across tiles
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        acc64[m][n][r] += (double)acc[m][n][r];
+                        acc[m][n][r] = 0.0f;
+                    }
+        }
+    }
+    const int P = P0 + ps;
+    if (P >= n_aux) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int i = i0 + m * 16 + 4 * lk + r;
+                if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = (float)acc64[m][n][r];
+            }
+}
+
+// FP32 exchange SYRK on the direct-LDS ring: one wave instruction moves two
+// 128-float tile rows (lanes 0-31 the first, 32-63 the second); 16 B chunks
+// of row r sit at chunk ^ ((r & 3) << 2) so the four k-rows a fragment read
+// touches map to disjoint banks.  FP32 accumulation within a split, partial
+// tiles written in FP64 and summed across splits in FP64.
+template <int S>
+__global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __restrict__ X, int Npad, int64_t rows_pad,
+                                                              int64_t chunk, int ntile, double* __restrict__ part) {
+    __shared__ float As[S][16 * 128];
+    __shared__ float Bs[S][16 * 128];
+    const int nlow = ntile * (ntile + 1) / 2;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int z = L / nlow, t = L % nlow;
+    int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int m0 = ti * 128, n0 = tj * 128;
+    const int64_t r0 = (int64_t)z * chunk;
+    const int64_t r1 = min(rows_pad, r0 + chunk);
+    const int nsteps = (int)((r1 - r0) / 16);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // wave w moves row pairs 2w and 2w+1 (rows 4w .. 4w+3) of A and of B
+    auto issue = [&](int step, int buf) {
+        int64_t rb = r0 + (int64_t)step * 16;
+        if (rb >= rows_pad) rb = rows_pad;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int row = 4 * wave + 2 * q + (lane >> 5);
+            const int c = (lane & 31) ^ ((row & 3) << 2);
+            const float* ga = X + (rb + row) * Npad + m0 + 4 * c;
+            const float* gb = X + (rb + row) * Npad + n0 + 4 * c;
+            const int lds_row = 4 * wave + 2 * q;
+            __builtin_amdgcn_global_load_lds((const void*)ga, (lds_void_t)(&As[buf][lds_row * 128]), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)gb, (lds_void_t)(&Bs[buf][lds_row * 128]), 16, 0, 0);
+        }
+    };
+    f4_t acc[4][4];
+    d4_t acc64[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+            acc64[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) issue(s, s);
+    for (int k = 0; k < nsteps; ++k) {
+        if ((k & 3) == 0 && k > 0) {   // FP32 over 64 rows, FP64 across
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        acc64[i][j][r] += (double)acc[i][j][r];
+                        acc[i][j][r] = 0.0f;
+                    }
+        }
+        __builtin_amdgcn_s_waitcnt(((S - 2) * 4 & 0xF) | ((((S - 2) * 4) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+        __builtin_amdgcn_s_barrier();
+        issue(k + S - 1, (k + S - 1) % S);
+        const float* as = As[k % S];
+        const float* bs = Bs[k % S];
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int row = kk + lk, sw = (row & 3) << 2;
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = wm + 16 * i + li;
+                a[i] = as[row * 128 + 4 * ((m >> 2) ^ sw) + (m & 3)];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = wn + 16 * j + li;
+                b[j] = bs[row * 128 + 4 * ((n >> 2) ^ sw) + (n & 3)];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    double* out = part + (int64_t)z * Npad * Npad;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(int64_t)(m0 + wm + 16 * i + 4 * lk + r) * Npad + n0 + wn + 16 * j + li] =
+                    acc64[i][j][r] + (double)acc[i][j][r];
+}
+
 // Exchange SYRK, K_part[z] = sum over rows r of split z of Xt[r][m] Xt[r][n],
 // for the lower 128 x 128 tiles only.  Rows of Xt are streamed through an
 // S-stage LDS ring filled by direct global->LDS loads (global_load_lds, 16 B
@@ -140,7 +452,6 @@ __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict
 // k-step.  Row r is (P, i) flattened; the buffer carries >= 16 zero rows past
 // the last real row, so split ends and the pipeline's look-ahead loads stay
 // in bounds and contribute nothing.
-typedef __attribute__((address_space(3))) void* lds_void_t;
 
 template <int S>
 __global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restrict__ X, int Npad, int64_t rows_pad,
@@ -292,15 +603,45 @@ hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, 
     return hipGetLastError();
 }
 
-hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, void* Xt,
+int cpad_ld(int n_occ) { return (n_occ + 127) / 128 * 128; }
+int64_t cpad_elems(int N, int n_occ) { return (int64_t)n_tiles_1d(N) * 64 * cpad_ld(n_occ); }
+
+int g_x_variant = 0;   // 0: register-staged x2 kernel, 1: direct-LDS x3 kernel
+void set_x_variant(int v) { g_x_variant = v; }
+
+hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, double* Cp, void* Xt,
                        hipStream_t st) {
     const int nt = n_tiles_1d(N), Npad = xt_ld(N);
-    if (prec != RI_FP64) return hipErrorInvalidValue;
     const int mt = (min(n_occ, 128) + 15) / 16;
     dim3 grid(nt, (n_aux + 1) / 2, (n_occ + 127) / 128);
+    if (prec == RI_FP32) {
+        const float* b = (const float*)B;
+        float* x = (float*)Xt;
+        const int64_t ntl = n_tiles(N);
+        switch (mt) {
+#define XCASE(k) case k: x2_kernel_f32<k><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
+            XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
+#undef XCASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (prec != RI_FP64) return hipErrorInvalidValue;
     const double* b = (const double*)B;
     double* x = (double*)Xt;
     const int64_t ntl = n_tiles(N);
+    if (g_x_variant == 1) {
+        const int cld = cpad_ld(n_occ), rows = nt * 64;
+        cpad_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cp);
+        RI_TRY(hipGetLastError());
+        switch (mt) {
+#define XCASE(k) case k: x3_kernel_f64<k, 2><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, n_occ, n_aux, x, Npad); break;
+            XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
+#undef XCASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (mt) {
 #define XCASE(k) case k: x2_kernel_f64<k><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
         XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
@@ -330,17 +671,24 @@ int xt_ld(int N) { return (N + 127) / 128 * 128; }
 
 hipError_t k_syrk(const void* Xt, int prec, int N, int n_aux, int n_occ, double* part, int n_split,
                   double* K, hipStream_t st) {
-    if (prec != RI_FP64) return hipErrorInvalidValue;
+    if (prec != RI_FP64 && prec != RI_FP32) return hipErrorInvalidValue;
     const int Npad = xt_ld(N), t128 = Npad / 128;
     const int64_t rows = (int64_t)n_aux * n_occ;
     const int64_t rows_pad = (rows + 15) / 16 * 16;
-    double* x = (double*)Xt;
-    // zero the padding rows (real rows .. rows_pad + 16)
-    RI_TRY(fill(x + rows * Npad, 0.0, (rows_pad + 16 - rows) * Npad, st));
     const int64_t chunk = ((rows_pad + n_split - 1) / n_split + 15) / 16 * 16;
     const int used = (int)((rows_pad + chunk - 1) / chunk);
     const int nlow = t128 * (t128 + 1) / 2;
-    syrk_lds_kernel<2><<<nlow * used, 256, 0, st>>>(x, Npad, rows_pad, chunk, t128, part);
+    if (prec == RI_FP64) {
+        double* x = (double*)Xt;
+        // zero the padding rows (real rows .. rows_pad + 16)
+        RI_TRY(fill(x + rows * Npad, 0.0, (rows_pad + 16 - rows) * Npad, st));
+        syrk_lds_kernel<2><<<nlow * used, 256, 0, st>>>(x, Npad, rows_pad, chunk, t128, part);
+    } else {
+        float* x = (float*)Xt;
+        // zero padding rows (the region is 512 B aligned: fill it as doubles)
+        RI_TRY(fill((double*)(x + rows * Npad), 0.0, (rows_pad + 16 - rows) * Npad / 2, st));
+        syrk_lds_f32_kernel<4><<<nlow * used, 256, 0, st>>>(x, Npad, rows_pad, chunk, t128, part);
+    }
     RI_TRY(hipGetLastError());
     dim3 grid((N + 255) / 256, N);
     kreduce_kernel<<<grid, 256, 0, st>>>(part, used, Npad, N, K);

@@ -262,6 +262,10 @@ __global__ void identity_kernel(double* p, int n, int64_t ld) {
     int r = i / n, c = i % n;
     p[(int64_t)r * ld + c] = (r == c) ? 1.0 : 0.0;
 }
+__global__ void f32_to_f64_kernel(const float* x, double* y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
 __global__ void axpby_kernel(double* y, const double* x, double a, double b, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -402,6 +406,10 @@ hipError_t max_abs(const double* x, int64_t n, double* out, hipStream_t s) {
 }
 hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
     axpby_kernel<<<nblk(n), 256, 0, s>>>(y, x, a, b, n);
+    return hipGetLastError();
+}
+hipError_t widen(const float* x, double* y, int64_t n, hipStream_t s) {
+    f32_to_f64_kernel<<<nblk(n), 256, 0, s>>>(x, y, n);
     return hipGetLastError();
 }
 hipError_t copy(double* dst, const double* src, int64_t n, hipStream_t s) {

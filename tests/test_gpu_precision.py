@@ -1,0 +1,51 @@
+"""Reduced-precision exchange (FP32 B and X/K contractions) at the tiny
+workload: errors against the FP64 oracle, to the precision extension's bar
+(|dE| <= 1e-6 Eh, gradient <= 1e-5 Eh/bohr)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ri as R
+from oracle import scf as S
+from oracle import gradient as G
+from tests.gpu_common import need_gpu, problem, to_np, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ref():
+    need_gpu()
+    s = synth.config_system("tiny")
+    ri = R.RIData(s)
+    res = S.run_scf(s, ri, tol_E=1e-12, tol_e=1e-10)
+    return s, ri, res, G.analytic_gradient(s, res, ri)
+
+
+def test_fp32_fock_jk(ref):
+    s, ri, *_ = ref
+    import paper_2407_19614_amd as P
+    print("case: tiny fock_jk fp32", flush=True)
+    pr = problem(s, P.FP32)
+    C = synth.random_coeffs(s.N, s.n_occ, seed=0)
+    J, K, _ = pr.fock_jk(dev(C))
+    Jr, Kr = ri.JK(C)
+    dJ = np.abs(to_np(J) - Jr).max()
+    dK = np.abs(to_np(K) - Kr).max()
+    print(f"fp32 max|dJ|={dJ:.2e} max|dK|={dK:.2e}", flush=True)
+    assert dJ < 1e-11            # J stays FP64 (compressed B)
+    assert dK < 1e-5 * np.abs(Kr).max()
+
+
+def test_fp32_energy_and_gradient(ref):
+    s, ri, res, gref = ref
+    import paper_2407_19614_amd as P
+    print("case: tiny energy+gradient fp32", flush=True)
+    pr = problem(s, P.FP32)
+    r, C, F, D = pr.energy(tol_E=1e-10, tol_err=1e-7)
+    dE = abs(r["E_total"] - res.E)
+    g = to_np(pr.gradient())
+    dg = np.abs(g - gref).max()
+    print(f"fp32 |dE|={dE:.2e} max|dg|={dg:.2e}", flush=True)
+    assert dE <= 1e-6
+    assert dg <= 1e-5

@@ -34,6 +34,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-pipeline", action="store_true", help="skip SCF/gradient phase timings")
     ap.add_argument("--calib", action="store_true", help="also run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--learned", action="store_true",
+                    help="also run the learned-SCF-start workload (40-centre random walk) and report it")
+    ap.add_argument("--learned-steps", type=int, default=3000, help="random-walk steps of that workload")
     ap.add_argument("--quick", action="store_true",
                     help="profiling mode: seeded random occupied orbitals instead of the converged SCF "
                          "(same shapes and kernels), no pipeline, no CPU baseline")
@@ -130,6 +133,8 @@ def main():
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
     if not args.quick:
         out["precision"] = precision_leg(s, C, res, args, P, torch, np)
+    if args.learned:
+        out["learned_start"] = learned_leg(args.learned_steps)
     if args.calib:
         src = torch.empty(2 ** 28, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -170,6 +175,76 @@ def precision_leg(s, C, res64, args, P, torch, np):
     del pr
     torch.cuda.empty_cache()
     return out
+
+
+def learned_leg(n_steps):
+    """40-centre cluster (N=400, N_aux=1200, n_occ=40) on a seeded Gaussian
+    random walk (sigma 0.05 bohr per coordinate per step): reference SCF from
+    the core-Hamiltonian guess at every geometry, MLP trained on the first two
+    thirds, learned start evaluated on the last third against the core-H start
+    and the previous-geometry-orbital start."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2407_19614_amd as P
+    import paper_2407_19614_amd.learned as Lr
+    s0 = synth.config_system("n400")
+    traj = synth.random_walk(s0.xyz, n_steps, 0.05, 2.0, seed=7)
+    systems = [s0.with_xyz(x) for x in traj]
+    n_train = (2 * len(systems)) // 3
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    data = Lr.generate(systems[:n_train], log=log)
+    t_gen = time.perf_counter() - t0
+    net = Lr.init_network(seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = Lr.train(net, data, steps=4000, batch=16384, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del data
+    it_core, it_learn, it_prev, dE, fallbacks = [], [], [], [], 0
+    t_learn = t_core = 0.0
+    C_prev = None
+    for k, s in enumerate(systems[n_train:]):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pr, ref, C, D, _ = Lr.solve(s, gradient=True)
+        torch.cuda.synchronize()
+        t_core += time.perf_counter() - t
+        if C_prev is not None:
+            it_prev.append(pr.energy(tol_E=1e-10, tol_err=1e-8, guess=C_prev, raise_on_noconv=False)[0]["n_iter"])
+        C_prev = C.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pr2 = P.RIProblem(s)
+        pr2.build_3c()
+        pr2.metric_factor(P.FP64)
+        Dg = Lr.predict_density(net, pr2)
+        res, C2, F2, _ = pr2.energy(tol_E=1e-10, tol_err=1e-8, guess_density=Dg, raise_on_noconv=False)
+        if not res["converged"] or res["E_total"] > ref["E_total"] + 1e-8:
+            fallbacks += 1
+            res, C2, F2, _ = pr2.energy(tol_E=1e-10, tol_err=1e-8, raise_on_noconv=False)
+        pr2.gradient(C2, F2)
+        torch.cuda.synchronize()
+        t_learn += time.perf_counter() - t
+        it_core.append(ref["n_iter"])
+        it_learn.append(res["n_iter"])
+        dE.append(abs(res["E_total"] - ref["E_total"]))
+        if k % 100 == 0:
+            log(f"test geometry {k}: iters core {ref['n_iter']} learned {res['n_iter']}")
+    n_test = len(it_core)
+    return {"workload": f"n400: 40 He-like centres, N=400, N_aux=1200, n_occ=40; {n_steps}-step walk, "
+                        f"train {n_train} / test {n_test}",
+            "mean_iters_core_h": round(float(np.mean(it_core)), 3),
+            "mean_iters_learned": round(float(np.mean(it_learn)), 3),
+            "mean_iters_previous_orbitals": round(float(np.mean(it_prev)), 3) if it_prev else None,
+            "iterations_saved_per_scf": round(float(np.mean(it_core) - np.mean(it_learn)), 3),
+            "max_abs_dE_vs_core_h": float(np.max(dE)), "fallbacks": fallbacks,
+            "energy_gradient_evals_per_s_learned": round(n_test / t_learn, 3),
+            "energy_gradient_evals_per_s_core_h": round(n_test / t_core, 3),
+            "train_loss_first_last": [losses[0][1], losses[-1][1]],
+            "generate_s": round(t_gen, 1), "train_s": round(t_train, 2)}
 
 
 def cpu_baseline(s, C):

@@ -157,7 +157,9 @@ typedef struct {
     int32_t diis_n;        /* DIIS subspace size, 1..8 (default 6)              */
     double tol_E;          /* |E_k - E_{k-1}| threshold (default 1e-10)         */
     double tol_err;        /* max |F D S - S D F| threshold (default 1e-8)      */
-    int32_t guess_kind;    /* 0 core Hamiltonian, 1 C_occ given in `guess`      */
+    int32_t guess_kind;    /* 0 core Hamiltonian; 1 C_occ [N][n_occ] in `guess`;*/
+                           /* 2 density D [N][N] in `guess`: start from the    */
+                           /*   n_occ largest solutions of (S D S) v = l S v   */
 } ri_scf_opts;
 
 typedef struct {
@@ -173,7 +175,8 @@ typedef struct {
  * The occupied space of each extrapolated Fock matrix (the n_occ lowest
  * orbitals of F C = S C eps) is obtained as the spectral projector by
  * trace-correcting purification, all on the GPU.
- *   guess     [N][n_occ] device C_occ when opts->guess_kind == 1, else NULL.
+ *   guess     device C_occ [N][n_occ] (guess_kind 1) or D [N][N] (guess_kind 2),
+ *             else NULL.
  *   C_occ     [N][n_occ] out: orthonormal (C^T S C = 1) occupied orbitals
  *             spanning the converged occupied space (not canonical).
  *   F_out     [N][N] out: Fock matrix built from C_occ.
@@ -203,9 +206,70 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
                     const double* C_occ, const double* F, double* grad,
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Operation codes for ri_workspace_bytes. */
+/* ------------------------------------------------------------------------
+ * Learned SCF start (project extension, not proposed by the paper; the
+ * paper starts each molecular-dynamics SCF from the previous step's orbitals,
+ * AIMD section).  A 3-layer MLP maps per-pair features to density-matrix
+ * elements D_mu_nu; ri_energy then starts from the occupied space of that
+ * density (guess_kind 2).
+ * Pair features (RI_MLP_NFEAT = 8) of (mu, nu) with centres A, B, exponents a, b:
+ *   |A-B|, ln max(a,b), ln min(a,b), [A == B], exp(-(ab/(a+b))|A-B|^2),
+ *   max and min over {A, B} of c_X = sum_{C != X} exp(-|R_X - R_C|^2 / 8),
+ *   sum_C exp(-|P - R_C|^2 / 4) with P = (aA + bB)/(a + b).
+ * Network: x = (f - mu)/sigma; h1 = silu(x W1 + b1); h2 = silu(h1 W2 + b2);
+ *   y = h2 w3 + b3; silu(z) = z/(1+exp(-z)).  Parameters are one flat FP32
+ *   device array laid out as W1 [8][256], b1 [256], W2 [256][256], b2 [256],
+ *   w3 [256], b3 [1] (offsets RI_MLP_OFF_*). */
+#define RI_MLP_NFEAT 8
+#define RI_MLP_WIDTH 256
+#define RI_MLP_OFF_W1 0
+#define RI_MLP_OFF_B1 (RI_MLP_OFF_W1 + RI_MLP_NFEAT * RI_MLP_WIDTH)
+#define RI_MLP_OFF_W2 (RI_MLP_OFF_B1 + RI_MLP_WIDTH)
+#define RI_MLP_OFF_B2 (RI_MLP_OFF_W2 + RI_MLP_WIDTH * RI_MLP_WIDTH)
+#define RI_MLP_OFF_W3 (RI_MLP_OFF_B2 + RI_MLP_WIDTH)
+#define RI_MLP_OFF_B3 (RI_MLP_OFF_W3 + RI_MLP_WIDTH)
+#define RI_MLP_NPARAM (RI_MLP_OFF_B3 + 1)
+enum { RI_MLP_FP32 = 0, RI_MLP_BF16 = 1 };
+
+typedef struct {
+    float* params;          /* device [RI_MLP_NPARAM]                          */
+    const float* mu;        /* device [RI_MLP_NFEAT] feature shift             */
+    const float* sigma;     /* device [RI_MLP_NFEAT] feature scale             */
+} ri_mlp;
+
+/* ri_pair_features - features of each listed pair.
+ *   feat [n_pairs][RI_MLP_NFEAT] FP32 (device, out).  Asynchronous. */
+int32_t ri_pair_features(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, float* feat,
+                         hipStream_t stream);
+
+/* ri_mlp_forward - y[n] = MLP(feat[n]).  prec RI_MLP_FP32, or RI_MLP_BF16
+ * (the 256 x 256 layer with BF16 operands and FP32 accumulation).
+ * Workspace: ri_workspace_bytes(RI_OP_MLP, .., n_pairs = n, ..). */
+int32_t ri_mlp_forward(const ri_mlp* net, const float* feat, int64_t n, float* y, int32_t prec,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ri_mlp_train_step - one Adam step (beta 0.9 / 0.999, eps 1e-8, step >= 1)
+ * on the mean squared error of the FP32 forward against target[n].
+ *   adam_m, adam_v [RI_MLP_NPARAM] device moments (zero before step 1).
+ *   loss   device float (out): the loss before the update.
+ *   grad   device [RI_MLP_NPARAM] (out, may be NULL): the loss gradient. */
+int32_t ri_mlp_train_step(const ri_mlp* net, float* adam_m, float* adam_v, int32_t step, float lr,
+                          const float* feat, const float* target, int64_t n, float* loss, float* grad,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ri_density_from_pairs - dense symmetric D [N][N] (device, out, FP64) with
+ * D_mu_nu = D_nu_mu = d[q] for pair q = (mu, nu) and zero elsewhere. */
+int32_t ri_density_from_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const float* d,
+                              double* D, hipStream_t stream);
+
+/* ri_density_to_pairs - d[q] = (float) D[mu][nu] for each listed pair q. */
+int32_t ri_density_to_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d,
+                            hipStream_t stream);
+
+/* Operation codes for ri_workspace_bytes.  For RI_OP_MLP, n_pairs is the
+ * number of feature rows per call. */
 enum { RI_OP_BUILD_3C = 0, RI_OP_METRIC = 1, RI_OP_FOCK = 2, RI_OP_ENERGY = 3,
-       RI_OP_GRADIENT = 4 };
+       RI_OP_GRADIENT = 4, RI_OP_MLP = 5 };
 
 /* Bytes of workspace an operation needs (0 on invalid arguments). */
 size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ,

@@ -66,7 +66,7 @@ def analytic_gradient(sys, res, ri: RIData | None = None, parts=False):
     for p0 in range(0, na, 64):
         p1 = min(na, p0 + 64)
         Tp = ri.dense_T_chunk(p0, p1)
-        t[p0:p1] = np.einsum("mi,pmn,nj->pij", Co, Tp, Co)
+        t[p0:p1] = Co.T @ Tp @ Co          # (C^T T_P C) for each P of the chunk
     Xi = sla.cho_solve(ri.cho, t.reshape(na, n * n)).reshape(na, n, n)
     # three-centre term over significant pairs (both orders -> weight w)
     g3 = np.zeros_like(sys.xyz)

@@ -47,6 +47,21 @@ class SCFResult(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RIMlp(ctypes.Structure):
+    _fields_ = [("params", c_void_p), ("mu", c_void_p), ("sigma", c_void_p)]
+
+
+NFEAT, WIDTH = 8, 256
+OFF_W1 = 0
+OFF_B1 = OFF_W1 + NFEAT * WIDTH
+OFF_W2 = OFF_B1 + WIDTH
+OFF_B2 = OFF_W2 + WIDTH * WIDTH
+OFF_W3 = OFF_B2 + WIDTH
+OFF_B3 = OFF_W3 + WIDTH
+NPARAM = OFF_B3 + 1
+MLP_FP32, MLP_BF16 = 0, 1
+OP_MLP = 5
+
 _LIB = None
 _SIGS = {
     "ri_version": (c_char_p, []),
@@ -66,6 +81,12 @@ _SIGS = {
     "ri_energy": (c_int32, [POINTER(RISystem), c_void_p, c_int32, c_void_p, c_void_p, c_int64, POINTER(SCFOpts),
                             c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SCFResult), c_void_p, c_size_t,
                             c_void_p]),
+    "ri_pair_features": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_void_p]),
+    "ri_mlp_forward": (c_int32, [POINTER(RIMlp), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "ri_mlp_train_step": (c_int32, [POINTER(RIMlp), c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p, c_void_p,
+                                    c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ri_density_to_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "ri_density_from_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
@@ -227,9 +248,34 @@ class RIProblem:
                                       _ptr(ws), nb, self.stream(), arr)
         _check(code, "ri_fock_jk_timed")
 
-    def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True):
+    def pair_features(self):
         torch = self.torch
-        opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, 0 if guess is None else 1)
+        f = torch.empty((max(self.n_pairs, 1), NFEAT), dtype=torch.float32, device=self.device)
+        _check(lib().ri_pair_features(ctypes.byref(self.c_sys), _ptr(self.pairs), self.n_pairs, _ptr(f),
+                                      self.stream()), "ri_pair_features")
+        return f[: self.n_pairs]
+
+    def density_to_pairs(self, D):
+        torch = self.torch
+        d = torch.empty(max(self.n_pairs, 1), dtype=torch.float32, device=self.device)
+        _check(lib().ri_density_to_pairs(self.N, _ptr(self.pairs), self.n_pairs, _ptr(D.contiguous()), _ptr(d),
+                                         self.stream()), "ri_density_to_pairs")
+        return d[: self.n_pairs]
+
+    def density_from_pairs(self, d):
+        torch = self.torch
+        D = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
+        _check(lib().ri_density_from_pairs(self.N, _ptr(self.pairs), self.n_pairs, _ptr(d.contiguous()), _ptr(D),
+                                           self.stream()), "ri_density_from_pairs")
+        return D
+
+    def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True,
+               guess_density=None):
+        torch = self.torch
+        kind = 0 if guess is None else 1
+        if guess_density is not None:
+            kind, guess = 2, guess_density
+        opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, kind)
         C = torch.empty((self.N, self.n_occ), dtype=torch.float64, device=self.device)
         F = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
         D = torch.empty_like(F)
@@ -256,3 +302,62 @@ class RIProblem:
                                  self.stream())
         _check(code, "ri_gradient")
         return g
+
+
+class MLP:
+    """Device parameters of the learned-start network plus Adam moments."""
+
+    def __init__(self, params, mu, sigma, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = torch.tensor(np.asarray(params, dtype=np.float32), device=self.device)
+        assert self.params.numel() == NPARAM
+        self.mu = torch.tensor(np.asarray(mu, dtype=np.float32), device=self.device)
+        self.sigma = torch.tensor(np.asarray(sigma, dtype=np.float32), device=self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.c = RIMlp(self.params.data_ptr(), self.mu.data_ptr(), self.sigma.data_ptr())
+        self._ws = None
+
+    def _ws_for(self, n):
+        nb = workspace_bytes(OP_MLP, 1, 1, 1, int(n), FP64)
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        return self._ws, nb
+
+    def stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, feat, prec=MLP_FP32):
+        n = feat.shape[0]
+        y = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        ws, nb = self._ws_for(n)
+        _check(lib().ri_mlp_forward(ctypes.byref(self.c), _ptr(feat.contiguous()), n, _ptr(y), prec, _ptr(ws), nb,
+                                    self.stream()), "ri_mlp_forward")
+        return y
+
+    def train_step(self, feat, target, lr, want_grad=False):
+        n = feat.shape[0]
+        self.step += 1
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
+        g = self.torch.empty_like(self.params) if want_grad else None
+        ws, nb = self._ws_for(n)
+        _check(lib().ri_mlp_train_step(ctypes.byref(self.c), _ptr(self.m), _ptr(self.v), self.step, float(lr),
+                                       _ptr(feat.contiguous()), _ptr(target.contiguous()), n, _ptr(loss), _ptr(g),
+                                       _ptr(ws), nb, self.stream()), "ri_mlp_train_step")
+        return (loss, g) if want_grad else loss
+
+
+def pack_params(p):
+    """Flat parameter vector (layout of include/ri.h) from a dict of arrays."""
+    return np.concatenate([np.asarray(p["W1"]).reshape(-1), p["b1"], np.asarray(p["W2"]).reshape(-1), p["b2"],
+                           p["w3"], p["b3"]]).astype(np.float32)
+
+
+def unpack_params(v):
+    v = np.asarray(v, dtype=np.float64)
+    return {"W1": v[OFF_W1:OFF_B1].reshape(NFEAT, WIDTH), "b1": v[OFF_B1:OFF_W2],
+            "W2": v[OFF_W2:OFF_B2].reshape(WIDTH, WIDTH), "b2": v[OFF_B2:OFF_W3],
+            "w3": v[OFF_W3:OFF_B3], "b3": v[OFF_B3:OFF_B3 + 1]}

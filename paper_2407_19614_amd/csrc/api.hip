@@ -226,6 +226,11 @@ size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, i
         case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec); break;
         case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8); break;
         case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec); break;
+        case RI_OP_MLP: {
+            size_t off = 0;
+            ri::carve_mlp(nullptr, 0, off, std::max<int64_t>(n_pairs, 1));
+            return off + 256;
+        }
         default: return 0;
     }
     return a.off + 256;
@@ -320,8 +325,8 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
         return RI_E_ARG;
     if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0))
         return RI_E_ARG;
-    if (opts->guess_kind == 1 && !guess) return RI_E_ARG;
-    if (opts->guess_kind != 0 && opts->guess_kind != 1) return RI_E_UNSUPPORTED;
+    if (opts->guess_kind != 0 && !guess) return RI_E_ARG;
+    if (opts->guess_kind < 0 || opts->guess_kind > 2) return RI_E_UNSUPPORTED;
     if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
@@ -343,6 +348,12 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
     int32_t rc;
     if (opts->guess_kind == 0) {
         rc = occupied_space(w.H, N, no, w, false, C_occ, st);
+        if (rc) return rc;
+    } else if (opts->guess_kind == 2) {
+        // occupied space of the density: lowest solutions of (-S D S) v = l S v
+        HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.S, N, 0, guess, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
+        HIPC(ri::gemm_f64(false, false, N, N, N, -1.0, w.T1, N, 0, w.S, N, 0, 0.0, w.Fx, N, 0, 1, 0, 0, st));
+        rc = occupied_space(w.Fx, N, no, w, false, C_occ, st);
         if (rc) return rc;
     } else {
         HIPC(ri::copy(C_occ, guess, (int64_t)N * no, st));
@@ -467,6 +478,56 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     HIPC(ri::grad_three_centre(sys, pairs, n_pairs, U, C, no, w.D, w.c, w.part + 2 * GB * rowlen, st));
     HIPC(ri::grad_nuclear(sys, w.part + 3 * GB * rowlen, st));
     HIPC(ri::grad_reduce(w.part, 3 * GB + 1, nc, grad, st));
+    return RI_OK;
+}
+
+int32_t ri_pair_features(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, float* feat, hipStream_t st) {
+    if (!valid_sys(sys) || n_pairs < 0 || (n_pairs > 0 && (!pairs || !feat))) return RI_E_ARG;
+    HIPC(ri::pair_features(sys, pairs, n_pairs, feat, st));
+    return RI_OK;
+}
+
+static bool valid_mlp(const ri_mlp* net) { return net && net->params && net->mu && net->sigma; }
+
+int32_t ri_mlp_forward(const ri_mlp* net, const float* feat, int64_t n, float* y, int32_t prec, void* ws,
+                       size_t ws_bytes, hipStream_t st) {
+    if (!valid_mlp(net) || n <= 0 || !feat || !y || !ws) return RI_E_ARG;
+    if (prec != RI_MLP_FP32 && prec != RI_MLP_BF16) return RI_E_UNSUPPORTED;
+    size_t off = 0;
+    ri::carve_mlp(nullptr, 0, off, n);
+    if (off > ws_bytes) return RI_E_WORKSPACE;
+    off = 0;
+    ri::MlpWS w = ri::carve_mlp((char*)ws, ws_bytes, off, n);
+    HIPC(ri::mlp_forward(net, feat, n, y, prec, w, st));
+    return RI_OK;
+}
+
+int32_t ri_mlp_train_step(const ri_mlp* net, float* m, float* v, int32_t step, float lr, const float* feat,
+                          const float* target, int64_t n, float* loss, float* grad, void* ws, size_t ws_bytes,
+                          hipStream_t st) {
+    if (!valid_mlp(net) || !m || !v || step < 1 || !(lr > 0.0f) || n <= 0 || !feat || !target || !loss || !ws)
+        return RI_E_ARG;
+    size_t off = 0;
+    ri::carve_mlp(nullptr, 0, off, n);
+    if (off > ws_bytes) return RI_E_WORKSPACE;
+    off = 0;
+    ri::MlpWS w = ri::carve_mlp((char*)ws, ws_bytes, off, n);
+    HIPC(ri::mlp_train_step(net, m, v, step, lr, feat, target, n, loss, w, st));
+    if (grad) HIPC(hipMemcpyAsync(grad, w.grad, sizeof(float) * RI_MLP_NPARAM, hipMemcpyDeviceToDevice, st));
+    return RI_OK;
+}
+
+int32_t ri_density_from_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const float* d, double* D,
+                              hipStream_t st) {
+    if (N <= 0 || n_pairs < 0 || !D || (n_pairs > 0 && (!pairs || !d))) return RI_E_ARG;
+    HIPC(ri::scatter_density(N, pairs, n_pairs, d, D, st));
+    return RI_OK;
+}
+
+int32_t ri_density_to_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d,
+                            hipStream_t st) {
+    if (N <= 0 || n_pairs < 0 || !D || (n_pairs > 0 && (!pairs || !d))) return RI_E_ARG;
+    HIPC(ri::gather_density(N, pairs, n_pairs, D, d, st));
     return RI_OK;
 }
 

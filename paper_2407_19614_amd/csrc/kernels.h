@@ -74,3 +74,16 @@ hipError_t grad_reduce(const double* part, int rows, int n_centres, double* grad
 hipError_t gamma_only(const double* Bc, const int32_t* pairs, int64_t n_pairs, int n_aux, int n_occ,
                       const double* C, double* dpair, double* gamma, hipStream_t st);
 }  // namespace ri
+
+namespace ri {
+// ---- learned start (mlp.hip)
+struct MlpWS { float *xh, *z1, *h1, *z2, *h2, *y, *dy, *part, *grad; __bf16* W2t; };
+MlpWS carve_mlp(char* base, size_t cap, size_t& off, int64_t n);
+hipError_t pair_features(const ri_system* s, const int32_t* pairs, int64_t n_pairs, float* feat, hipStream_t st);
+hipError_t mlp_forward(const ri_mlp* net, const float* feat, int64_t n, float* y, int prec, const MlpWS& w,
+                       hipStream_t st);
+hipError_t mlp_train_step(const ri_mlp* net, float* m, float* v, int step, float lr, const float* feat,
+                          const float* target, int64_t n, float* loss, const MlpWS& w, hipStream_t st);
+hipError_t gather_density(int N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d, hipStream_t st);
+hipError_t scatter_density(int N, const int32_t* pairs, int64_t n_pairs, const float* d, double* D, hipStream_t st);
+}  // namespace ri

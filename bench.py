@@ -136,12 +136,16 @@ def main():
     if args.learned:
         out["learned_start"] = learned_leg(args.learned_steps)
     if args.calib:
-        src = torch.empty(2 ** 28, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
+        # counter calibration: one kernel that writes 2 GiB (fill) and one that reads 2 GiB (sum)
+        src = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
+        src.fill_(1.0)                      # writes 2 GiB
         sync()
-        dst.copy_(src)
+        dst = torch.mul(src, 2.0)           # plain copy kernel: reads 2 GiB, writes 2 GiB
         sync()
-        out["calib_copy_bytes_each_way"] = 2 ** 31
+        tot = src.sum()                     # reads 2 GiB
+        sync()
+        out["calib_bytes"] = 2 ** 31
+        del src, dst, tot
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, C.cpu().numpy())
     print(json.dumps(out), flush=True)
@@ -194,7 +198,7 @@ def learned_leg(n_steps):
     n_train = (2 * len(systems)) // 3
     log = lambda m: print(m, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    data = Lr.generate(systems[:n_train], log=log)
+    data = Lr.generate(systems[:n_train], log=log, prev_baseline=False)
     t_gen = time.perf_counter() - t0
     net = Lr.init_network(seed=0)
     torch.cuda.synchronize()
@@ -212,7 +216,7 @@ def learned_leg(n_steps):
         pr, ref, C, D, _ = Lr.solve(s, gradient=True)
         torch.cuda.synchronize()
         t_core += time.perf_counter() - t
-        if C_prev is not None:
+        if C_prev is not None and k % 10 == 1:     # previous-orbital start, sampled
             it_prev.append(pr.energy(tol_E=1e-10, tol_err=1e-8, guess=C_prev, raise_on_noconv=False)[0]["n_iter"])
         C_prev = C.clone()
         torch.cuda.synchronize()

@@ -59,7 +59,7 @@ MetricWS carve_metric(Arena& a, int N, int n_aux, int64_t n_pairs) {
     w.dinv = a.take<double>((int64_t)((n_aux + 63) / 64) * 4096);
     w.bad = a.take<int>(1);
     w.map = a.take<int32_t>((int64_t)N * N);
-    w.tmp = a.take<double>((int64_t)n_aux * std::min<int64_t>(std::max<int64_t>(n_pairs, 1), BC_CHUNK));
+    w.tmp = nullptr;
     return w;
 }
 
@@ -275,14 +275,8 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
         *bad_pivot = bad;
         return RI_E_NOT_PD;
     }
-    // Bc = L^{-1} T, by column chunks through the workspace.
-    for (int64_t c0 = 0; c0 < n_pairs; c0 += BC_CHUNK) {
-        const int64_t nc = std::min<int64_t>(BC_CHUNK, n_pairs - c0);
-        HIPC(ri::gemm_f64(false, false, na, (int)nc, na, 1.0, Linv, na, 0, T + c0, n_pairs, 0, 0.0, w.tmp, nc, 0, 1,
-                          1, 0, st));
-        HIPC(hipMemcpy2DAsync(T + c0, n_pairs * sizeof(double), w.tmp, nc * sizeof(double), nc * sizeof(double), na,
-                              hipMemcpyDeviceToDevice, st));
-    }
+    // Bc = L^{-1} T by blocked forward substitution, in place over T.
+    if (n_pairs > 0) HIPC(ri::trsm_lower_inplace(L, na, na, w.dinv, T, (int)n_pairs, n_pairs, st));
     if (B) {
         HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
         HIPC(ri::pack_b(T, n_pairs, w.map, N, na, B, prec, st));

@@ -49,18 +49,19 @@ def solve(system, guess=None, guess_density=None, tol_E=1e-10, tol_err=1e-8, max
     return pr, res, C, D, g
 
 
-def generate(systems, device="cuda", log=None):
+def generate(systems, device="cuda", log=None, prev_baseline=True):
     """Reference SCF (core-H start) for each geometry; returns per-geometry
-    dicts with features and targets on the device."""
+    dicts with features and targets on the device.  With prev_baseline, also
+    records the iterations of an SCF started from the previous geometry's
+    orbitals (the paper's molecular-dynamics start)."""
     import torch
     out = []
     C_prev = None
     for k, s in enumerate(systems):
         t0 = time.perf_counter()
         pr, res, C, D, _ = solve(s, device=device)
-        # the paper's start: previous geometry's orbitals (iterations recorded)
         it_prev = None
-        if C_prev is not None:
+        if prev_baseline and C_prev is not None:
             r2 = pr.energy(tol_E=1e-10, tol_err=1e-8, guess=C_prev, raise_on_noconv=False)[0]
             it_prev = r2["n_iter"]
         feat = pr.pair_features().clone()

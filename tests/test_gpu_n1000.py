@@ -57,7 +57,7 @@ def test_fock_jk_sampled_rows(setup):
     dJ = np.abs(J[rows] - np.array(ref["J_rows"])).max()
     dK = np.abs(K[rows] - np.array(ref["K_rows"])).max()
     print(f"max|dJ|={dJ:.2e} max|dK|={dK:.2e}", flush=True)
-    assert dJ < 1e-10 and dK < 1e-10
+    assert dJ < 1e-11 and dK < 1e-11
     assert abs(np.trace(J) - ref["J_trace"]) < 1e-8 and abs(np.trace(K) - ref["K_trace"]) < 1e-8
     assert np.abs(K - K.T).max() == 0.0 and np.abs(J - J.T).max() == 0.0
     w = np.linalg.eigvalsh(K)

@@ -24,6 +24,22 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 MFMA
 PEAK_HBM_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "x_kernel_n1000_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2407_19614_amd", "csrc", "fock.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the X kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        txt = open(COUNTERS).read()
+        val = float(txt.split("traffic_bytes_per_launch:")[1].split()[0])
+        sha = txt.split("source_sha256_16:")[1].split()[0]
+    except (OSError, IndexError, ValueError):
+        return None
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    return val if cur == sha else None
 
 
 def main():
@@ -116,7 +132,7 @@ def main():
                    "n_pairs": int(npairs), "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "kernel": "x_kernel_f64 (X^P = B^P C_occ)",
                      "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": measured_traffic(),
                      "flops_per_launch": fl_x, "avg_launch_ms": round(t_x, 4)},
         "phases_ms": {"gamma_J": round(t_j, 4), "X": round(t_x, 4), "K_syrk": round(t_k, 4)},
         "fock_build_frac_fp64_peak": round((fl_x + fl_k) / (ms_step * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),

@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="also run the learned-SCF-start workload (40-centre random walk) and report it")
     ap.add_argument("--learned-steps", type=int, default=3000, help="random-walk steps of that workload")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the batched workload (256 molecules, 10-60 centres) and report SCF/s")
+    ap.add_argument("--batched-n", type=int, default=256, help="molecules in the batched workload")
     ap.add_argument("--quick", action="store_true",
                     help="profiling mode: seeded random occupied orbitals instead of the converged SCF "
                          "(same shapes and kernels), no pipeline, no CPU baseline")
@@ -149,6 +152,8 @@ def main():
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
     if not args.quick:
         out["precision"] = precision_leg(s, C, res, args, P, torch, np)
+    if args.batched:
+        out["batched"] = batched_leg(args.batched_n)
     if args.learned:
         out["learned_start"] = learned_leg(args.learned_steps)
     if args.calib:
@@ -194,6 +199,76 @@ def precision_leg(s, C, res64, args, P, torch, np):
            "fp32_abs_dE_vs_fp64": abs(r32["E_total"] - res64["E_total"])}
     del pr
     torch.cuda.empty_cache()
+    return out
+
+
+def batched_leg(n_mol, wave=128, baseline_n=32):
+    """256 independent He-like clusters with n_centres ~ U{10..60} (N = 10 per
+    centre, N_aux = 30 per centre, n_occ = n_centres), seeds 4001...: pairs, 3c
+    integrals and FP32 B per molecule, then one lockstep SCF per wave of
+    molecules (HIP-graph replay, FP32 exchange, FP64 everything else).  SCF/s
+    counts the whole job from the first screening to the last convergence.
+    The plain FP64 single-molecule path is timed on the first baseline_n
+    molecules for comparison; energies are checked against stored oracle
+    energies for a seeded subset."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2407_19614_amd as P
+    from paper_2407_19614_amd.binding import energy_batched
+    systems = synth.batched_systems(n_mol)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    E = np.full(len(systems), np.nan)
+    iters = np.zeros(len(systems), dtype=int)
+    conv = np.zeros(len(systems), dtype=bool)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_setup = t_scf = 0.0
+    for w0 in range(0, len(systems), wave):
+        ts = time.perf_counter()
+        probs = []
+        for s in systems[w0:w0 + wave]:
+            pr = P.RIProblem(s, prec=P.FP32)
+            pr.build_3c()
+            pr.metric_factor(P.FP32)
+            probs.append(pr)
+        torch.cuda.synchronize()
+        t_setup += time.perf_counter() - ts
+        ts = time.perf_counter()
+        res, _, _ = energy_batched(probs, P.FP32, tol_E=1e-8, tol_err=1e-6, use_graph=True, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t_scf += time.perf_counter() - ts
+        for k, r in enumerate(res):
+            E[w0 + k], iters[w0 + k], conv[w0 + k] = r["E_total"], r["n_iter"], r["converged"]
+        log(f"batched wave {w0}: setup {t_setup:.2f}s scf {t_scf:.2f}s")
+        del probs, res
+        torch.cuda.empty_cache()
+    wall = time.perf_counter() - t0
+    # plain FP64 single-molecule path on the first molecules
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    E64 = []
+    for s in systems[:baseline_n]:
+        pr = P.RIProblem(s)
+        pr.build_3c()
+        pr.metric_factor(P.FP64)
+        r, *_ = pr.energy(tol_E=1e-10, tol_err=1e-8)
+        E64.append(r["E_total"])
+        del pr
+    torch.cuda.synchronize()
+    t_base = time.perf_counter() - tb
+    out = {"workload": f"{len(systems)} He-like clusters, 10-60 centres (N 100-600, N_aux 300-1800), FP32 exchange",
+           "scf_per_s": round(len(systems) / wall, 3), "wall_s": round(wall, 2),
+           "setup_s": round(t_setup, 2), "batched_scf_s": round(t_scf, 2),
+           "all_converged": bool(conv.all()), "mean_iters": round(float(iters.mean()), 2),
+           "fp64_single_path_scf_per_s": round(baseline_n / t_base, 3),
+           "fp64_single_path_sample": f"first {baseline_n} molecules",
+           "max_abs_dE_fp32_batched_vs_fp64_single": float(np.max(np.abs(E[:baseline_n] - np.array(E64))))}
+    gold = os.path.join(ROOT, "tests", "golden", "batch_oracle.json")
+    if os.path.exists(gold) and len(systems) == 256:
+        ref = json.load(open(gold))
+        out["max_abs_dE_vs_oracle_subset"] = float(max(abs(E[m["index"]] - m["E"]) for m in ref["subset"]))
+        out["oracle_subset_size"] = len(ref["subset"])
     return out
 
 

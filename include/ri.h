@@ -266,6 +266,36 @@ int32_t ri_density_from_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, 
 int32_t ri_density_to_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d,
                             hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched SCF (project extension): many independent molecules advance through
+ * the SCF of ri_energy in lockstep, each step one launch over all molecules,
+ * optionally replayed from a captured HIP graph.  Per molecule the caller
+ * supplies the outputs of ri_build_3c / ri_metric_factor. */
+typedef struct {
+    const void* B;          /* packed B in the batch precision                 */
+    const double* Bc;       /* [n_aux][n_pairs] FP64 fitted tensor              */
+    const int32_t* pairs;   /* [n_pairs][2]                                     */
+    int64_t n_pairs;
+    double* C_occ;          /* [N][n_occ] out                                   */
+    double* F;              /* [N][N] out, or NULL                              */
+} ri_batch_mol;
+
+/* Workspace bytes for ri_energy_batched (0 on invalid input).  Supported:
+ * prec RI_FP64 or RI_FP32, n_occ <= 64 for every molecule. */
+size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec);
+
+/* ri_energy_batched - closed-shell RI-HF SCF (as ri_energy, core-Hamiltonian
+ * start) for n_mol molecules at once.
+ * Paper: Roothaan equations and Algorithm 1 SCF loop, applied per molecule.
+ *   sys, mol   host arrays [n_mol] (the pointers inside are device pointers).
+ *   use_graph  1: capture one iteration as a HIP graph and replay it.
+ *   res        host [n_mol] (out).
+ * Returns RI_E_NO_CONV if any molecule did not converge (all results filled).
+ * Synchronises the stream once per iteration. */
+int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
+                          const ri_scf_opts* opts, int32_t use_graph, ri_scf_result* res,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Operation codes for ri_workspace_bytes.  For RI_OP_MLP, n_pairs is the
  * number of feature rows per call. */
 enum { RI_OP_BUILD_3C = 0, RI_OP_METRIC = 1, RI_OP_FOCK = 2, RI_OP_ENERGY = 3,

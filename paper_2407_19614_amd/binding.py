@@ -62,6 +62,11 @@ NPARAM = OFF_B3 + 1
 MLP_FP32, MLP_BF16 = 0, 1
 OP_MLP = 5
 
+class BatchMol(ctypes.Structure):
+    _fields_ = [("B", c_void_p), ("Bc", c_void_p), ("pairs", c_void_p), ("n_pairs", c_int64),
+                ("C_occ", c_void_p), ("F", c_void_p)]
+
+
 _LIB = None
 _SIGS = {
     "ri_version": (c_char_p, []),
@@ -87,6 +92,9 @@ _SIGS = {
                                     c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_density_to_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "ri_density_from_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "ri_energy_batched_workspace": (c_size_t, [c_int32, c_void_p, c_void_p, c_int32]),
+    "ri_energy_batched": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, POINTER(SCFOpts), c_int32, c_void_p,
+                                    c_void_p, c_size_t, c_void_p]),
     "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
@@ -361,3 +369,31 @@ def unpack_params(v):
     return {"W1": v[OFF_W1:OFF_B1].reshape(NFEAT, WIDTH), "b1": v[OFF_B1:OFF_W2],
             "W2": v[OFF_W2:OFF_B2].reshape(WIDTH, WIDTH), "b2": v[OFF_B2:OFF_W3],
             "w3": v[OFF_W3:OFF_B3], "b3": v[OFF_B3:OFF_B3 + 1]}
+
+
+def energy_batched(problems, prec=FP64, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, use_graph=True,
+                   want_fock=False, raise_on_noconv=True):
+    """Lockstep SCF for a list of RIProblem objects (each after build_3c and
+    metric_factor in precision `prec`).  Returns (results, C_occ list, F list)."""
+    import torch
+    n = len(problems)
+    dev = problems[0].device
+    sysarr = (RISystem * n)(*[p.c_sys for p in problems])
+    Cs = [torch.empty((p.N, p.n_occ), dtype=torch.float64, device=dev) for p in problems]
+    Fs = [torch.empty((p.N, p.N), dtype=torch.float64, device=dev) for p in problems] if want_fock else [None] * n
+    mols = (BatchMol * n)(*[BatchMol(p.B.data_ptr(), p.T.data_ptr(), p.pairs.data_ptr(), p.n_pairs,
+                                     Cs[i].data_ptr(), None if Fs[i] is None else Fs[i].data_ptr())
+                            for i, p in enumerate(problems)])
+    nb = int(lib().ri_energy_batched_workspace(n, ctypes.byref(sysarr), ctypes.byref(mols), prec))
+    if nb == 0:
+        raise RIError(7, "ri_energy_batched_workspace")
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    res = (SCFResult * n)()
+    opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, 0)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    code = lib().ri_energy_batched(n, ctypes.byref(sysarr), ctypes.byref(mols), prec, ctypes.byref(opts),
+                                   1 if use_graph else 0, ctypes.byref(res), _ptr(ws), nb, stream)
+    if code not in (0, 3) or (code == 3 and raise_on_noconv):
+        _check(code, "ri_energy_batched")
+    del ws
+    return [r.as_dict() for r in res], Cs, Fs

@@ -1,0 +1,634 @@
+// Batched SCF (project extension): many independent molecules advance in
+// lockstep.  Every step of an SCF iteration (Fock build, Fock assembly,
+// energy, DIIS, purification, occupied space) is one launch over the work
+// items of all active molecules (MolDesc + prefix tables, grouped GEMMs), so
+// the iteration is a fixed launch sequence that can be captured once as a
+// HIP graph and replayed; convergence and DIIS bookkeeping stay on the
+// device and the host reads one counter per iteration.
+#include "kernels.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+using ri::MolDesc;
+
+constexpr int ST_ACTIVE = 0, ST_IT = 1, ST_PUSH = 2, ST_CONV = 3, ST_NSLOT = 4, ST_SLOT0 = 5, ST_BAD = 13;
+constexpr int SC_E = 0, SC_ERR = 5, SC_EOLD = 6, SC_ENUC = 8, SC_BOUNDS = 16, SC_TR = 20;
+
+#define DECODE()                                         \
+    int mol, loc;                                        \
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc); \
+    const MolDesc& m = d[mol];                           \
+    if (!m.state[ST_ACTIVE]) return;
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double block_max256(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+// -------------------------------------------------- elementwise over N x N
+// prefix over ceil(N^2 / 256) blocks per molecule
+__global__ void fock_assemble_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e < (int64_t)m.N * m.N) m.F[e] = m.H[e] + m.J[e] - m.K[e];
+}
+
+__global__ void copy_h_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e < (int64_t)m.N * m.N) m.Fx[e] = m.H[e];
+}
+
+__global__ void commutator_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e >= (int64_t)m.N * m.N) return;
+    int r = e / m.N, c = e % m.N;
+    m.E[e] = m.T2[e] - m.T2[(int64_t)c * m.N + r];
+}
+
+// DIIS ring: slot = pushes mod diis_n (the bookkeeping kernel advances it)
+__global__ void diis_push_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e >= (int64_t)m.N * m.N) return;
+    const int s = m.state[ST_PUSH] % m.diis_n;
+    m.dF[s][e] = m.F[e];
+    m.dE[s][e] = m.E[e];
+}
+
+__global__ void diis_combine_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e >= (int64_t)m.N * m.N) return;
+    const int ns = m.state[ST_NSLOT];
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) s += m.coef[k] * m.dF[m.state[ST_SLOT0 + k]][e];
+    m.Fx[e] = s;
+}
+
+__global__ void tc2_init_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e >= (int64_t)m.N * m.N) return;
+    int r = e / m.N, c = e % m.N;
+    const double lo = m.scal[SC_BOUNDS], hi = m.scal[SC_BOUNDS + 1];
+    m.X[e] = ((r == c ? hi : 0.0) - m.T2[e]) / (hi - lo);
+}
+
+__global__ void tc2_update_b(const MolDesc* d, const int* prefix, int n_mol) {
+    DECODE();
+    int64_t e = (int64_t)loc * 256 + threadIdx.x;
+    if (e >= (int64_t)m.N * m.N) return;
+    const double t1 = m.scal[SC_TR], t2 = m.scal[SC_TR + 1];
+    const bool sq = fabs(t2 - m.n_occ) < fabs(2.0 * t1 - t2 - m.n_occ);
+    m.X[e] = sq ? m.X2[e] : 2.0 * m.X[e] - m.X2[e];
+}
+
+// -------------------------------------------------- one block per molecule
+__global__ __launch_bounds__(256) void state_init_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (threadIdx.x < 16) m.state[threadIdx.x] = (threadIdx.x == ST_ACTIVE) ? 1 : 0;
+    if (threadIdx.x < 64) m.Bmat[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) m.scal[SC_EOLD] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void hash_cp_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    const int64_t n = (int64_t)m.N * m.n_occ;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        uint32_t x = (uint32_t)i * 2654435761u ^ 0x5eed1234u;
+        x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+        m.Cp[i] = (double)x * (2.0 / 4294967296.0) - 1.0;
+    }
+}
+
+// energies E_1e = tr DH, E_J = tr DJ / 2, E_K = -tr DK / 2, then max|e| and
+// the convergence decision (|E - E_old| < tol_E and max|e| < tol_err from the
+// second iteration on); a molecule that converges or reaches max_iter
+// becomes inactive for the rest of the batch.
+__global__ __launch_bounds__(256) void energy_conv_b(const MolDesc* d, int n_mol, int max_iter) {
+    const MolDesc& m = d[blockIdx.x];
+    if (!m.state[ST_ACTIVE]) return;
+    __shared__ double sh[4];
+    const int64_t n = (int64_t)m.N * m.N;
+    double a = 0.0, b = 0.0, c = 0.0, e = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double dd = m.D[i];
+        a += dd * m.H[i];
+        b += dd * m.J[i];
+        c += dd * m.K[i];
+        e = fmax(e, fabs(m.E[i]));
+    }
+    a = block_sum256(a, sh);
+    b = block_sum256(b, sh);
+    c = block_sum256(c, sh);
+    e = block_max256(e, sh);
+    if (threadIdx.x == 0) {
+        const double en = m.scal[SC_ENUC];
+        const double E = a + 0.5 * b - 0.5 * c + en;
+        m.scal[SC_E + 0] = E;
+        m.scal[SC_E + 1] = en;
+        m.scal[SC_E + 2] = a;
+        m.scal[SC_E + 3] = 0.5 * b;
+        m.scal[SC_E + 4] = -0.5 * c;
+        m.scal[SC_ERR] = e;
+        const int it = ++m.state[ST_IT];
+        const double dE = E - m.scal[SC_EOLD];
+        m.scal[SC_EOLD + 1] = dE;
+        if (it > 1 && fabs(dE) < m.tol_E && e < m.tol_err) {
+            m.state[ST_CONV] = 1;
+            m.state[ST_ACTIVE] = 0;
+        } else if (it >= max_iter) {
+            m.state[ST_ACTIVE] = 0;
+        }
+        m.scal[SC_EOLD] = E;
+    }
+}
+
+// after the push: advance the ring and keep the slot order (oldest first)
+__global__ void diis_book_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (threadIdx.x != 0 || !m.state[ST_ACTIVE]) return;
+    const int s = m.state[ST_PUSH] % m.diis_n;
+    m.state[ST_PUSH] += 1;
+    int ns = m.state[ST_NSLOT], w = 0;
+    for (int k = 0; k < ns; ++k)
+        if (m.state[ST_SLOT0 + k] != s) m.state[ST_SLOT0 + w++] = m.state[ST_SLOT0 + k];
+    m.state[ST_SLOT0 + w++] = s;
+    m.state[ST_NSLOT] = w;
+}
+
+// <e_new, e_slot> for every held slot: grid (n_mol, 8)
+__global__ __launch_bounds__(256) void diis_dots_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    const int k = blockIdx.y;
+    if (!m.state[ST_ACTIVE] || k >= m.state[ST_NSLOT]) return;
+    __shared__ double sh[4];
+    const int snew = m.state[ST_SLOT0 + m.state[ST_NSLOT] - 1], sk = m.state[ST_SLOT0 + k];
+    const double* x = m.dE[snew];
+    const double* y = m.dE[sk];
+    const int64_t n = (int64_t)m.N * m.N;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i] * y[i];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) {
+        m.Bmat[snew * 8 + sk] = s;
+        m.Bmat[sk * 8 + snew] = s;
+    }
+}
+
+// Pulay: minimise |sum c_k e_k| with sum c_k = 1 (one thread per molecule);
+// with a single vector the coefficient is 1 (no extrapolation).
+__global__ void diis_solve_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (threadIdx.x != 0 || !m.state[ST_ACTIVE]) return;
+    const int ns = m.state[ST_NSLOT];
+    if (ns < 2) {
+        m.coef[0] = 1.0;
+        return;
+    }
+    double a[9][10];
+    const int n = ns + 1;
+    for (int i = 0; i < ns; ++i) {
+        for (int j = 0; j < ns; ++j) a[i][j] = m.Bmat[m.state[ST_SLOT0 + i] * 8 + m.state[ST_SLOT0 + j]];
+        a[i][ns] = -1.0;
+        a[i][n] = 0.0;
+    }
+    for (int j = 0; j < ns; ++j) a[ns][j] = -1.0;
+    a[ns][ns] = 0.0;
+    a[ns][n] = -1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        if (piv != c)
+            for (int k = 0; k <= n; ++k) { double t = a[c][k]; a[c][k] = a[piv][k]; a[piv][k] = t; }
+        double dd = a[c][c] == 0.0 ? 1e-300 : a[c][c];
+        for (int r = c + 1; r < n; ++r) {
+            double f = a[r][c] / dd;
+            for (int k = c; k <= n; ++k) a[r][k] -= f * a[c][k];
+        }
+    }
+    double x[9];
+    for (int r = n - 1; r >= 0; --r) {
+        double s = a[r][n];
+        for (int k = r + 1; k < n; ++k) s -= a[r][k] * x[k];
+        x[r] = s / (a[r][r] == 0.0 ? 1e-300 : a[r][r]);
+    }
+    for (int i = 0; i < ns; ++i) m.coef[i] = x[i];
+}
+
+__global__ __launch_bounds__(256) void gersh_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (!m.state[ST_ACTIVE]) return;
+    __shared__ double sh[4];
+    double lo = 1e300, hi = -1e300;
+    for (int r = threadIdx.x; r < m.N; r += 256) {
+        const double* row = m.T2 + (int64_t)r * m.N;
+        double off = 0.0;
+        for (int c = 0; c < m.N; ++c)
+            if (c != r) off += fabs(row[c]);
+        lo = fmin(lo, row[r] - off);
+        hi = fmax(hi, row[r] + off);
+    }
+    lo = -block_max256(-lo, sh);
+    hi = block_max256(hi, sh);
+    if (threadIdx.x == 0) {
+        m.scal[SC_BOUNDS] = lo;
+        m.scal[SC_BOUNDS + 1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(256) void traces_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (!m.state[ST_ACTIVE]) return;
+    __shared__ double sh[4];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < m.N; i += 256) {
+        a += m.X[(int64_t)i * m.N + i];
+        b += m.X2[(int64_t)i * m.N + i];
+    }
+    a = block_sum256(a, sh);
+    b = block_sum256(b, sh);
+    if (threadIdx.x == 0) {
+        m.scal[SC_TR] = a;
+        m.scal[SC_TR + 1] = b;
+        m.scal[SC_TR + 2] = a - b;
+    }
+}
+
+// Cholesky of the n_occ x n_occ (<= 64) Gram matrix Mo and its inverse into
+// LinvM (64 x 64, row stride 64).
+__global__ __launch_bounds__(64) void small_chol_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (!m.state[ST_ACTIVE]) return;
+    __shared__ double L[64][65];
+    const int t = threadIdx.x, nb = m.n_occ;
+    for (int c = 0; c < 64; ++c)
+        L[t][c] = (t < nb && c < nb) ? m.Mo[(int64_t)t * nb + c] : (t == c ? 1.0 : 0.0);
+    __syncthreads();
+    int* bad = m.state + ST_BAD;
+    double* out = m.LinvM;
+    potrf_inv_block64(L, nb, [&](int) { atomicAdd(bad, 1); }, [&](int i, int c, double v) { out[i * 64 + c] = v; });
+}
+
+__global__ void count_active_b(const MolDesc* d, int n_mol, int* out) {
+    if (threadIdx.x != 0) return;
+    int c = 0;
+    for (int i = 0; i < n_mol; ++i) c += d[i].state[ST_ACTIVE];
+    *out = c;
+}
+
+// -------------------------------------------------- host side
+struct Table {
+    int* prefix = nullptr;   // device
+    int total = 0;
+};
+
+struct Plan {
+    int n_mol = 0, prec = 0, tc2_iters = 48;
+    MolDesc* d = nullptr;
+    Table n2, rows, pairs, aux, syrk, tail, x[9];
+    struct G { ri::GemmDesc* d = nullptr; Table t; bool ta = false, tb = false; };
+    G g_lfx, g_t2, g_x2, g_y, g_mo, g_cp, g_c, g_d, g_fd, g_fds;
+    int* n_active = nullptr;
+};
+
+#define HC(x)                                  \
+    do {                                       \
+        hipError_t _e = (x);                   \
+        if (_e != hipSuccess) return _e;       \
+    } while (0)
+
+hipError_t occupied_space_b(const Plan& p, hipStream_t st) {
+    const MolDesc* d = p.d;
+    const int nm = p.n_mol;
+    auto gg = [&](const Plan::G& g) { return ri::gemm_grouped(g.ta, g.tb, g.d, g.t.prefix, nm, g.t.total, st); };
+    HC(gg(p.g_lfx));
+    HC(gg(p.g_t2));
+    gersh_b<<<nm, 256, 0, st>>>(d, nm);
+    tc2_init_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+    for (int k = 0; k < p.tc2_iters; ++k) {
+        HC(gg(p.g_x2));
+        traces_b<<<nm, 256, 0, st>>>(d, nm);
+        tc2_update_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        HC(gg(p.g_y));
+        HC(gg(p.g_mo));
+        small_chol_b<<<nm, 64, 0, st>>>(d, nm);
+        HC(gg(p.g_cp));
+    }
+    HC(gg(p.g_c));
+    return hipGetLastError();
+}
+
+hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
+    const MolDesc* d = p.d;
+    const int nm = p.n_mol;
+    auto gg = [&](const Plan::G& g) { return ri::gemm_grouped(g.ta, g.tb, g.d, g.t.prefix, nm, g.t.total, st); };
+    // Fock build
+    HC(ri::zero_tail_b(d, p.tail.prefix, nm, p.tail.total, p.prec, st));
+    HC(ri::gamma_j_b(d, nm, p.pairs.prefix, p.pairs.total, p.aux.prefix, p.aux.total, p.n2.prefix, p.n2.total, st));
+    for (int mt = 1; mt <= 8; ++mt)
+        if (p.x[mt].total > 0) HC(ri::x_transform_b(d, p.x[mt].prefix, nm, p.x[mt].total, mt, p.prec, st));
+    HC(ri::syrk_b(d, p.syrk.prefix, nm, p.syrk.total, p.prec, st));
+    HC(ri::kreduce_b(d, p.rows.prefix, nm, p.rows.total, st));
+    // F, D, energy, error, convergence
+    fock_assemble_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+    HC(gg(p.g_d));
+    HC(gg(p.g_fd));
+    HC(gg(p.g_fds));
+    commutator_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+    energy_conv_b<<<nm, 256, 0, st>>>(d, nm, max_iter);
+    // DIIS and the next occupied space (molecules that just converged skip)
+    diis_push_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+    diis_book_b<<<nm, 64, 0, st>>>(d, nm);
+    diis_dots_b<<<dim3(nm, 8), 256, 0, st>>>(d, nm);
+    diis_solve_b<<<nm, 64, 0, st>>>(d, nm);
+    diis_combine_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+    HC(occupied_space_b(p, st));
+    count_active_b<<<1, 64, 0, st>>>(d, nm, p.n_active);
+    return hipGetLastError();
+}
+
+thread_local std::string g_batch_err;
+
+}  // namespace
+
+namespace {
+
+struct Carver {
+    char* base;
+    size_t cap, off = 0;
+    template <class T>
+    T* take(int64_t n) {
+        size_t b = ((size_t)(n < 0 ? 0 : n) * sizeof(T) + 255) & ~(size_t)255;
+        size_t o = off;
+        off += b;
+        return base ? (T*)(base + o) : nullptr;
+    }
+};
+
+int k_split_small(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(8, rows / 16384)); }
+
+// Lays out (or, with base == nullptr, sizes) the batch workspace and fills
+// the host copies of the descriptors and tables.
+struct HostPlan {
+    std::vector<MolDesc> mols;
+    std::vector<std::vector<int>> prefixes;           // each table's prefix
+    std::vector<std::vector<ri::GemmDesc>> gemms;     // each grouped GEMM's members
+};
+
+}  // namespace
+
+// The workspace layout shared by the size query and the solver.
+static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec, int diis_n,
+                            Carver& cv, Plan& p, HostPlan& hp) {
+    p.n_mol = n_mol;
+    p.prec = prec;
+    hp.mols.assign(n_mol, MolDesc{});
+    for (int i = 0; i < n_mol; ++i) {
+        const ri_system& s = sys[i];
+        MolDesc& m = hp.mols[i];
+        const int N = s.n_fn, na = s.n_aux, no = s.n_occ;
+        if (N <= 0 || na <= 0 || no <= 0 || no > 64 || no > N) return RI_E_UNSUPPORTED;
+        m.N = N; m.n_aux = na; m.n_occ = no; m.diis_n = diis_n;
+        m.nt = ri::n_tiles_1d(N);
+        m.npad = ri::xt_ld(N);
+        m.ntl = ri::n_tiles(N);
+        m.n_pairs = mol[i].n_pairs;
+        m.mt = (no + 15) / 16;
+        const int64_t rows = (int64_t)na * no;
+        m.rows_pad = (rows + 15) / 16 * 16;
+        m.ks = k_split_small(rows);
+        m.chunk = ((m.rows_pad + m.ks - 1) / m.ks + 15) / 16 * 16;
+        m.ks = (int)((m.rows_pad + m.chunk - 1) / m.chunk);
+        m.pairs = mol[i].pairs;
+        m.Bc = mol[i].Bc;
+        m.B = mol[i].B;
+        m.C = mol[i].C_occ;
+        const int64_t n2 = (int64_t)N * N;
+        m.J = cv.take<double>(n2); m.K = cv.take<double>(n2); m.gamma = cv.take<double>(na);
+        m.dpair = cv.take<double>(std::max<int64_t>(1, m.n_pairs));
+        m.part = cv.take<double>((int64_t)m.ks * m.npad * m.npad);
+        m.Xt = cv.take<char>((m.rows_pad + 16) * m.npad * (prec == RI_FP64 ? 8 : 4));
+        double** mats[] = {&m.S, &m.H, &m.LinvS, &m.F, &m.D, &m.T1, &m.T2, &m.E, &m.Fx, &m.X, &m.X2};
+        for (double** q : mats) *q = cv.take<double>(n2);
+        for (int k = 0; k < 8; ++k) {
+            m.dF[k] = k < diis_n ? cv.take<double>(n2) : nullptr;
+            m.dE[k] = k < diis_n ? cv.take<double>(n2) : nullptr;
+        }
+        m.Y = cv.take<double>((int64_t)N * no);
+        m.Cp = cv.take<double>((int64_t)N * no);
+        m.Mo = cv.take<double>((int64_t)no * no);
+        m.LinvM = cv.take<double>(64 * 64);
+        m.dinvM = cv.take<double>(((N + 63) / 64) * 4096);   // Cholesky diagonal blocks of S
+        m.Bmat = cv.take<double>(64);
+        m.coef = cv.take<double>(8);
+        m.scal = cv.take<double>(32);
+        m.state = cv.take<int>(16);
+    }
+    // tables
+    auto mk = [&](std::vector<int> counts, Table& t) {
+        std::vector<int> pre(n_mol + 1, 0);
+        for (int i = 0; i < n_mol; ++i) pre[i + 1] = pre[i] + counts[i];
+        t.total = pre[n_mol];
+        t.prefix = cv.take<int>(n_mol + 1);
+        hp.prefixes.push_back(pre);
+    };
+    std::vector<int> c(n_mol);
+    for (int i = 0; i < n_mol; ++i) c[i] = (int)(((int64_t)hp.mols[i].N * hp.mols[i].N + 255) / 256);
+    mk(c, p.n2);
+    for (int i = 0; i < n_mol; ++i) c[i] = hp.mols[i].N;
+    mk(c, p.rows);
+    for (int i = 0; i < n_mol; ++i) c[i] = (int)((hp.mols[i].n_pairs + 255) / 256);
+    mk(c, p.pairs);
+    for (int i = 0; i < n_mol; ++i) c[i] = hp.mols[i].n_aux;
+    mk(c, p.aux);
+    for (int i = 0; i < n_mol; ++i) {
+        const int t128 = hp.mols[i].npad / 128;
+        c[i] = t128 * (t128 + 1) / 2 * hp.mols[i].ks;
+    }
+    mk(c, p.syrk);
+    for (int i = 0; i < n_mol; ++i) c[i] = 16;
+    mk(c, p.tail);
+    for (int mt = 1; mt <= 8; ++mt) {
+        for (int i = 0; i < n_mol; ++i)
+            c[i] = hp.mols[i].mt == mt ? hp.mols[i].nt * ((hp.mols[i].n_aux + 1) / 2) : 0;
+        mk(c, p.x[mt]);
+    }
+    // grouped GEMMs: member i of each
+    auto mkg = [&](Plan::G& g, bool ta, bool tb, auto fill) {
+        g.ta = ta;
+        g.tb = tb;
+        std::vector<ri::GemmDesc> v(n_mol);
+        std::vector<int> cnt(n_mol);
+        for (int i = 0; i < n_mol; ++i) {
+            fill(hp.mols[i], v[i]);
+            v[i].active = hp.mols[i].state;   // state[0]
+            cnt[i] = ((v[i].M + 63) / 64) * ((v[i].N + 63) / 64);
+        }
+        g.d = cv.take<ri::GemmDesc>(n_mol);
+        hp.gemms.push_back(v);
+        mk(cnt, g.t);
+    };
+    auto set = [](ri::GemmDesc& g, int M, int N, int K, double al, const double* A, int64_t lda, const double* B,
+                  int64_t ldb, double* C, int64_t ldc, int tri) {
+        g.M = M; g.N = N; g.K = K; g.tri = tri; g.alpha = al; g.beta = 0.0;
+        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+    };
+    mkg(p.g_lfx, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.LinvS, m.N, m.Fx, m.N, m.T1, m.N, 1); });
+    mkg(p.g_t2, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.LinvS, m.N, m.T2, m.N, 0); });
+    mkg(p.g_x2, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.X, m.N, m.X, m.N, m.X2, m.N, 0); });
+    mkg(p.g_y, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.X, m.N, m.Cp, m.n_occ, m.Y, m.n_occ, 0); });
+    mkg(p.g_mo, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.n_occ, m.n_occ, m.N, 1.0, m.Y, m.n_occ, m.Y, m.n_occ, m.Mo, m.n_occ, 0); });
+    mkg(p.g_cp, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.n_occ, 1.0, m.Y, m.n_occ, m.LinvM, 64, m.Cp, m.n_occ, 0); });
+    mkg(p.g_c, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.LinvS, m.N, m.Cp, m.n_occ, m.C, m.n_occ, 2); });
+    mkg(p.g_d, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.n_occ, 2.0, m.C, m.n_occ, m.C, m.n_occ, m.D, m.N, 0); });
+    mkg(p.g_fd, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.F, m.N, m.D, m.N, m.T1, m.N, 0); });
+    mkg(p.g_fds, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.S, m.N, m.T2, m.N, 0); });
+    p.d = cv.take<MolDesc>(n_mol);
+    p.n_active = cv.take<int>(4);
+    return RI_OK;
+}
+
+extern "C" {
+
+size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec) {
+    if (n_mol <= 0 || !sys || !mol || (prec != RI_FP64 && prec != RI_FP32)) return 0;
+    Carver cv{nullptr, 0};
+    Plan p;
+    HostPlan hp;
+    if (batch_layout(n_mol, sys, mol, prec, 8, cv, p, hp) != RI_OK) return 0;
+    return cv.off + 256;
+}
+
+int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
+                          const ri_scf_opts* opts, int32_t use_graph, ri_scf_result* res, void* ws, size_t ws_bytes,
+                          hipStream_t st) {
+    if (n_mol <= 0 || !sys || !mol || !opts || !res || !ws) return RI_E_ARG;
+    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0) ||
+        opts->guess_kind != 0)
+        return RI_E_ARG;
+    for (int i = 0; i < n_mol; ++i) {
+        const ri_system& s = sys[i];
+        if (s.n_centres <= 0 || s.n_fn <= 0 || s.n_aux <= 0 || s.n_occ <= 0 || !s.xyz || !s.Z || !s.fn_centre ||
+            !s.fn_exp || !s.aux_centre || !s.aux_exp || !mol[i].B || !mol[i].C_occ || mol[i].n_pairs < 0 ||
+            (mol[i].n_pairs > 0 && (!mol[i].Bc || !mol[i].pairs)))
+            return RI_E_ARG;
+    }
+    Carver cv{(char*)ws, ws_bytes};
+    Plan p;
+    HostPlan hp;
+    int32_t rc = batch_layout(n_mol, sys, mol, prec, 8, cv, p, hp);
+    if (rc != RI_OK) return rc;
+    if (cv.off > ws_bytes) return RI_E_WORKSPACE;
+    for (auto& m : hp.mols) {
+        m.tol_E = opts->tol_E;
+        m.tol_err = opts->tol_err;
+        m.diis_n = opts->diis_n;
+    }
+#define HIPR(x)                                                          \
+    do {                                                                 \
+        hipError_t _e = (x);                                             \
+        if (_e != hipSuccess) { g_batch_err = hipGetErrorString(_e); return RI_E_HIP; } \
+    } while (0)
+    // upload descriptors and tables
+    HIPR(hipMemcpyAsync(p.d, hp.mols.data(), sizeof(MolDesc) * n_mol, hipMemcpyHostToDevice, st));
+    {
+        std::vector<Table*> tabs = {&p.n2, &p.rows, &p.pairs, &p.aux, &p.syrk, &p.tail};
+        for (int mt = 1; mt <= 8; ++mt) tabs.push_back(&p.x[mt]);
+        Plan::G* gs[] = {&p.g_lfx, &p.g_t2, &p.g_x2, &p.g_y, &p.g_mo, &p.g_cp, &p.g_c, &p.g_d, &p.g_fd, &p.g_fds};
+        for (auto* g : gs) tabs.push_back(&g->t);
+        for (size_t k = 0; k < tabs.size(); ++k)
+            HIPR(hipMemcpyAsync(tabs[k]->prefix, hp.prefixes[k].data(), sizeof(int) * (n_mol + 1),
+                                hipMemcpyHostToDevice, st));
+        for (size_t k = 0; k < 10; ++k)
+            HIPR(hipMemcpyAsync(gs[k]->d, hp.gemms[k].data(), sizeof(ri::GemmDesc) * n_mol, hipMemcpyHostToDevice,
+                                st));
+        HIPR(hipStreamSynchronize(st));
+    }
+    // per-molecule setup: S, h, E_nn, Cholesky of S and L_S^{-1}
+    int* bad = p.n_active + 1;
+    HIPR(ri::fill_i32(bad, INT_MAX, 1, st));
+    for (int i = 0; i < n_mol; ++i) {
+        const MolDesc& m = hp.mols[i];
+        HIPR(ri::one_electron(&sys[i], m.S, m.H, st));
+        HIPR(ri::nuclear_repulsion(&sys[i], m.scal + SC_ENUC, st));
+        HIPR(ri::copy(m.T1, m.S, (int64_t)m.N * m.N, st));
+        HIPR(ri::cholesky_inv(m.T1, m.N, m.N, m.LinvS, m.N, m.dinvM, bad, st));
+    }
+    state_init_b<<<n_mol, 256, 0, st>>>(p.d, n_mol);
+    hash_cp_b<<<n_mol, 256, 0, st>>>(p.d, n_mol);
+    HIPR(hipGetLastError());
+    int hbad = INT_MAX;
+    HIPR(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPR(hipStreamSynchronize(st));
+    if (hbad != INT_MAX) return RI_E_NOT_PD;
+    // core-Hamiltonian start
+    copy_h_b<<<p.n2.total, 256, 0, st>>>(p.d, p.n2.prefix, n_mol);
+    HIPR(occupied_space_b(p, st));
+    // iterations
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph) {
+        HIPR(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = iteration_b(p, opts->max_iter, st);
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        HIPR(e);
+        HIPR(e2);
+        HIPR(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    int active = n_mol;
+    for (int it = 0; it < opts->max_iter && active > 0; ++it) {
+        if (use_graph) HIPR(hipGraphLaunch(exec, st));
+        else HIPR(iteration_b(p, opts->max_iter, st));
+        HIPR(hipMemcpyAsync(&active, p.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPR(hipStreamSynchronize(st));
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    // results
+    bool all = true;
+    for (int i = 0; i < n_mol; ++i) {
+        const MolDesc& m = hp.mols[i];
+        double sc[8];
+        int stt[16];
+        HIPR(hipMemcpyAsync(sc, m.scal, sizeof(sc), hipMemcpyDeviceToHost, st));
+        HIPR(hipMemcpyAsync(stt, m.state, sizeof(stt), hipMemcpyDeviceToHost, st));
+        HIPR(hipStreamSynchronize(st));
+        ri_scf_result& r = res[i];
+        r.E_total = sc[0]; r.E_nuc = sc[1]; r.E_1e = sc[2]; r.E_J = sc[3]; r.E_K = sc[4];
+        r.max_err = sc[5]; r.last_dE = sc[7];
+        r.n_iter = stt[ST_IT];
+        r.converged = stt[ST_CONV];
+        all = all && stt[ST_CONV];
+        if (mol[i].F) HIPR(ri::copy(mol[i].F, m.F, (int64_t)m.N * m.N, st));
+    }
+    HIPR(hipStreamSynchronize(st));
+    return all ? RI_OK : RI_E_NO_CONV;
+}
+
+}  // extern "C"

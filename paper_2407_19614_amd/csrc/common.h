@@ -61,6 +61,41 @@ __device__ __forceinline__ double boys_f1(double t) {
     return (boys_f0(t) - e) / (2.0 * t);
 }
 
+// Lower Cholesky of an nb x nb (nb <= 64) block held in LDS as L[64][65]
+// (rows/columns beyond nb set to the identity by the caller), in place, and
+// its inverse: thread t (64 threads) writes column t of L^{-1} through
+// store(i, t, value).  A pivot that is not positive is reported through
+// bad(j) and replaced by 1.
+template <class Bad, class Store>
+__device__ __forceinline__ void potrf_inv_block64(double (*L)[65], int nb, Bad bad, Store store) {
+    const int t = threadIdx.x;
+    for (int j = 0; j < nb; ++j) {
+        if (t == j) {
+            double d = L[j][j];
+            if (!(d > 0.0)) {
+                bad(j);
+                d = 1.0;
+            }
+            L[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        if (t > j && t < nb) L[t][j] /= L[j][j];
+        __syncthreads();
+        if (t > j && t < nb)
+            for (int c = j + 1; c <= t; ++c) L[t][c] -= L[t][j] * L[c][j];
+        __syncthreads();
+    }
+    double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = 0.0;
+    for (int i = 0; i < 64; ++i) {
+        double s = (i == t) ? 1.0 : 0.0;
+        for (int k = t; k < i; ++k) s -= L[i][k] * x[k];
+        x[i] = (i >= t) ? s / L[i][i] : 0.0;
+    }
+    for (int i = 0; i < 64; ++i) store(i, t, x[i]);
+}
+
 // ------------------------------------------------------------ launch helpers
 namespace ri {
 

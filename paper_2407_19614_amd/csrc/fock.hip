@@ -49,11 +49,9 @@ __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_p
 // staged C_occ slice serves both P.  Next-slice global loads are held in
 // registers while the current slice is multiplied.
 template <int MT>
-__global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
-                                                     const double* __restrict__ C, int N, int n_occ, int n_aux,
-                                                     double* __restrict__ Xt, int Npad) {
-    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int I = L % gridDim.x, P0 = 2 * (L / gridDim.x), i0 = blockIdx.z * 128;
+__device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double* __restrict__ B, int nt, int64_t ntl,
+                                            const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                            double* __restrict__ Xt, int Npad) {
     constexpr int W = MT * 16;
     __shared__ double Bs[2][16][65];
     __shared__ double Cs[16][W + 1];
@@ -130,6 +128,14 @@ __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict
                 int i = i0 + m * 16 + 4 * r + lk;
                 if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = acc[m][n][r];
             }
+}
+
+template <int MT>
+__global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
+                                                     const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                                     double* __restrict__ Xt, int Npad) {
+    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    x2_body_f64<MT>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt, Npad);
 }
 
 typedef __attribute__((address_space(3))) void* lds_void_t;
@@ -247,11 +253,9 @@ __device__ __forceinline__ f4_t mfma_f32(float a, float b, f4_t c) {
 }
 
 template <int MT>
-__global__ __launch_bounds__(256, 2) void x2_kernel_f32(const float* __restrict__ B, int nt, int64_t ntl,
-                                                        const double* __restrict__ C, int N, int n_occ, int n_aux,
-                                                        float* __restrict__ Xt, int Npad) {
-    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int I = L % gridDim.x, P0 = 2 * (L / gridDim.x), i0 = blockIdx.z * 128;
+__device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* __restrict__ B, int nt, int64_t ntl,
+                                            const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                            float* __restrict__ Xt, int Npad) {
     constexpr int W = MT * 16;
     __shared__ float Bs[2][16][65];
     __shared__ float Cs[16][W + 1];
@@ -345,19 +349,24 @@ __global__ __launch_bounds__(256, 2) void x2_kernel_f32(const float* __restrict_
             }
 }
 
+template <int MT>
+__global__ __launch_bounds__(256, 2) void x2_kernel_f32(const float* __restrict__ B, int nt, int64_t ntl,
+                                                        const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                                        float* __restrict__ Xt, int Npad) {
+    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    x2_body_f32<MT>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt, Npad);
+}
+
 // FP32 exchange SYRK on the direct-LDS ring: one wave instruction moves two
 // 128-float tile rows (lanes 0-31 the first, 32-63 the second); 16 B chunks
 // of row r sit at chunk ^ ((r & 3) << 2) so the four k-rows a fragment read
 // touches map to disjoint banks.  FP32 accumulation within a split, partial
 // tiles written in FP64 and summed across splits in FP64.
 template <int S>
-__global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __restrict__ X, int Npad, int64_t rows_pad,
-                                                              int64_t chunk, int ntile, double* __restrict__ part) {
+__device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restrict__ X, int Npad, int64_t rows_pad,
+                                              int64_t chunk, double* __restrict__ part) {
     __shared__ float As[S][16 * 128];
     __shared__ float Bs[S][16 * 128];
-    const int nlow = ntile * (ntile + 1) / 2;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int z = L / nlow, t = L % nlow;
     int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
@@ -444,6 +453,14 @@ __global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __res
                     acc64[i][j][r] + (double)acc[i][j][r];
 }
 
+template <int S>
+__global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __restrict__ X, int Npad, int64_t rows_pad,
+                                                              int64_t chunk, int ntile, double* __restrict__ part) {
+    const int nlow = ntile * (ntile + 1) / 2;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    syrk_body_f32<S>(L / nlow, L % nlow, X, Npad, rows_pad, chunk, part);
+}
+
 // Exchange SYRK, K_part[z] = sum over rows r of split z of Xt[r][m] Xt[r][n],
 // for the lower 128 x 128 tiles only.  Rows of Xt are streamed through an
 // S-stage LDS ring filled by direct global->LDS loads (global_load_lds, 16 B
@@ -454,14 +471,11 @@ __global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __res
 // in bounds and contribute nothing.
 
 template <int S>
-__global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restrict__ X, int Npad, int64_t rows_pad,
-                                                          int64_t chunk, int ntile, double* __restrict__ part) {
+__device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __restrict__ X, int Npad, int64_t rows_pad,
+                                              int64_t chunk, double* __restrict__ part) {
     constexpr int LDR = 128 + 16;                  // LDS row stride (doubles)
     __shared__ double As[S][16 * LDR];
     __shared__ double Bs[S][16 * LDR];
-    const int nlow = ntile * (ntile + 1) / 2;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int z = L / nlow, t = L % nlow;
     int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
@@ -522,6 +536,14 @@ __global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restri
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 out[(int64_t)(m0 + wm + 16 * i + 4 * r + lk) * Npad + n0 + wn + 16 * j + li] = acc[i][j][r];
+}
+
+template <int S>
+__global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restrict__ X, int Npad, int64_t rows_pad,
+                                                          int64_t chunk, int ntile, double* __restrict__ part) {
+    const int nlow = ntile * (ntile + 1) / 2;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    syrk_body_f64<S>(L / nlow, L % nlow, X, Npad, rows_pad, chunk, part);
 }
 
 __global__ void kreduce_kernel(const double* part, int n_split, int Npad, int N, double* K) {
@@ -711,6 +733,167 @@ hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int 
     jpair_kernel<<<dim3(pb, n_jsplit), 256, 0, st>>>(Bc, n_pairs, n_aux, gamma, per, jpart);
     RI_TRY(hipGetLastError());
     jscatter_kernel<<<pb, 256, 0, st>>>(jpart, n_jsplit, pairs, n_pairs, N, J);
+    return hipGetLastError();
+}
+
+}  // namespace ri
+
+// ------------------------------------------------------------ batched forms
+namespace {
+
+template <int MT, int PREC>
+__global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, loc;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
+    const ri::MolDesc& m = d[mol];
+    if (!m.state[0] || m.mt != MT) return;
+    const int I = loc % m.nt, P0 = 2 * (loc / m.nt);
+    if (PREC == RI_FP64)
+        x2_body_f64<MT>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
+    else
+        x2_body_f32<MT>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void syrk_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, loc;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
+    const ri::MolDesc& m = d[mol];
+    if (!m.state[0]) return;
+    const int t128 = m.npad / 128, nlow = t128 * (t128 + 1) / 2;
+    if (PREC == RI_FP64)
+        syrk_body_f64<2>(loc / nlow, loc % nlow, (const double*)m.Xt, m.npad, m.rows_pad, m.chunk, m.part);
+    else
+        syrk_body_f32<4>(loc / nlow, loc % nlow, (const float*)m.Xt, m.npad, m.rows_pad, m.chunk, m.part);
+}
+
+// one block per row mu of each molecule: K[mu][nu] = K[nu][mu] = sum_z part[z][mu][nu], nu <= mu
+__global__ void kreduce_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, mu;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, mu);
+    const ri::MolDesc& m = d[mol];
+    if (!m.state[0]) return;
+    const int used = (int)((m.rows_pad + m.chunk - 1) / m.chunk);
+    for (int nu = threadIdx.x; nu <= mu; nu += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < used; ++k) s += m.part[((int64_t)k * m.npad + mu) * m.npad + nu];
+        m.K[(int64_t)mu * m.N + nu] = s;
+        m.K[(int64_t)nu * m.N + mu] = s;
+    }
+}
+
+// zero the 16-row-aligned tail of each molecule's Xt (rows n_aux*n_occ .. rows_pad + 16)
+template <int PREC>
+__global__ void zero_tail_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, loc;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
+    const ri::MolDesc& m = d[mol];
+    if (!m.state[0]) return;
+    const int64_t r0 = (int64_t)m.n_aux * m.n_occ, n = (m.rows_pad + 16 - r0) * m.npad;
+    for (int64_t e = (int64_t)loc * blockDim.x + threadIdx.x; e < n; e += 16ll * blockDim.x) {   // 16 blocks per molecule
+        if (PREC == RI_FP64) ((double*)m.Xt)[r0 * m.npad + e] = 0.0;
+        else ((float*)m.Xt)[r0 * m.npad + e] = 0.0f;
+    }
+}
+
+// gamma and J on compressed pairs, batched: dpair per pair, gamma per P,
+// J per pair (full P loop), then scatter into the zeroed dense J.
+__global__ void dpair_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, loc;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
+    const ri::MolDesc& m = d[mol];
+    int64_t q = (int64_t)loc * blockDim.x + threadIdx.x;
+    if (!m.state[0] || q >= m.n_pairs) return;
+    int mu = m.pairs[2 * q], nu = m.pairs[2 * q + 1];
+    const double* a = m.C + (int64_t)mu * m.n_occ;
+    const double* b = m.C + (int64_t)nu * m.n_occ;
+    double s = 0.0;
+    for (int i = 0; i < m.n_occ; ++i) s += a[i] * b[i];
+    m.dpair[q] = (mu == nu ? 2.0 : 4.0) * s;
+}
+
+__global__ __launch_bounds__(256) void gamma_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, P;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, P);
+    const ri::MolDesc& m = d[mol];
+    if (!m.state[0]) return;
+    const double* row = m.Bc + (int64_t)P * m.n_pairs;
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < m.n_pairs; q += 256) s += row[q] * m.dpair[q];
+    __shared__ double sh[4];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) m.gamma[P] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void jfill_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, loc;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
+    const ri::MolDesc& m = d[mol];
+    int64_t e = (int64_t)loc * blockDim.x + threadIdx.x;
+    if (!m.state[0] || e >= (int64_t)m.N * m.N) return;
+    m.J[e] = 0.0;
+}
+
+__global__ void jpair_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, loc;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
+    const ri::MolDesc& m = d[mol];
+    int64_t q = (int64_t)loc * blockDim.x + threadIdx.x;
+    if (!m.state[0] || q >= m.n_pairs) return;
+    double s = 0.0;
+    for (int P = 0; P < m.n_aux; ++P) s += m.Bc[(int64_t)P * m.n_pairs + q] * m.gamma[P];
+    int mu = m.pairs[2 * q], nu = m.pairs[2 * q + 1];
+    m.J[(int64_t)mu * m.N + nu] = s;
+    m.J[(int64_t)nu * m.N + mu] = s;
+}
+
+}  // namespace
+
+namespace ri {
+
+hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int mt, int prec, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+#define XB(k)                                                                                           \
+    case k:                                                                                             \
+        if (prec == RI_FP64) x_b_kernel<k, RI_FP64><<<total, 256, 0, st>>>(d, prefix, n_mol);         \
+        else x_b_kernel<k, RI_FP32><<<total, 256, 0, st>>>(d, prefix, n_mol);                          \
+        break;
+    switch (mt) {
+        XB(1) XB(2) XB(3) XB(4) XB(5) XB(6) XB(7) XB(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef XB
+    return hipGetLastError();
+}
+
+hipError_t syrk_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    if (prec == RI_FP64) syrk_b_kernel<RI_FP64><<<total, 256, 0, st>>>(d, prefix, n_mol);
+    else syrk_b_kernel<RI_FP32><<<total, 256, 0, st>>>(d, prefix, n_mol);
+    return hipGetLastError();
+}
+
+hipError_t kreduce_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    kreduce_b_kernel<<<total, 256, 0, st>>>(d, prefix, n_mol);
+    return hipGetLastError();
+}
+
+hipError_t zero_tail_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    if (prec == RI_FP64) zero_tail_b_kernel<RI_FP64><<<total, 256, 0, st>>>(d, prefix, n_mol);
+    else zero_tail_b_kernel<RI_FP32><<<total, 256, 0, st>>>(d, prefix, n_mol);
+    return hipGetLastError();
+}
+
+hipError_t gamma_j_b(const MolDesc* d, int n_mol, const int* pre_pairs, int tot_pairs, const int* pre_aux, int tot_aux,
+                     const int* pre_n2, int tot_n2, hipStream_t st) {
+    if (tot_n2 > 0) jfill_b_kernel<<<tot_n2, 256, 0, st>>>(d, pre_n2, n_mol);
+    if (tot_pairs > 0) dpair_b_kernel<<<tot_pairs, 256, 0, st>>>(d, pre_pairs, n_mol);
+    if (tot_aux > 0) gamma_b_kernel<<<tot_aux, 256, 0, st>>>(d, pre_aux, n_mol);
+    if (tot_pairs > 0) jpair_b_kernel<<<tot_pairs, 256, 0, st>>>(d, pre_pairs, n_mol);
     return hipGetLastError();
 }
 

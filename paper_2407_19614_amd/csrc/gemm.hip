@@ -1,6 +1,7 @@
 // FP64 MFMA GEMM and the dense linear algebra built on it: blocked Cholesky
 // with non-positive pivot detection and the triangular inverse.
 #include "common.h"
+#include "kernels.h"
 #include <climits>
 
 namespace {
@@ -13,18 +14,9 @@ constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 1;
 // consecutive addresses.  Global loads for the next k-slice are issued before
 // the MFMAs of the current one.
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(
-    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
-    const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
-    int64_t ldc, int64_t sC, int tri, int lowerC) {
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
-    const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
-    const int m0 = by * BM, n0 = bx * BN;
-    if (lowerC && n0 > m0 + BM - 1) return;
-    A += (int64_t)bz * sA;
-    B += (int64_t)bz * sB;
-    C += (int64_t)bz * sC;
+__device__ __forceinline__ void gemm_tile64(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                            int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
+                                            double* __restrict__ C, int64_t ldc, int tri, int m0, int n0) {
     __shared__ double As[BK][LDP];
     __shared__ double Bs[BK][LDP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -106,6 +98,33 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
                     *c = (beta == 0.0) ? v : v + beta * *c;
                 }
             }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
+    const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int tri, int lowerC) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+    const int m0 = by * BM, n0 = bx * BN;
+    if (lowerC && n0 > m0 + BM - 1) return;
+    gemm_tile64<TA, TB>(M, N, K, alpha, A + (int64_t)bz * sA, lda, B + (int64_t)bz * sB, ldb, beta,
+                        C + (int64_t)bz * sC, ldc, tri, m0, n0);
+}
+
+// Grouped GEMM: problem g owns tiles prefix[g] .. prefix[g+1]-1 (row-major
+// over its 64 x 64 tiles); a problem whose `active` flag is 0 is skipped.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(const ri::GemmDesc* d, const int* prefix, int n) {
+    int g, loc;
+    ri::decode_item(prefix, n, blockIdx.x, g, loc);
+    const ri::GemmDesc& p = d[g];
+    if (p.active && !*p.active) return;
+    const int tn = (p.N + BN - 1) / BN;
+    gemm_tile64<TA, TB>(p.M, p.N, p.K, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, p.tri,
+                        (loc / tn) * BM, (loc % tn) * BN);
 }
 
 // 128 x 128 variant: 4 waves in 2 x 2, each owning 64 x 64 of C as 4 x 4 MFMA
@@ -209,34 +228,10 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int n, int64_
     for (int c = 0; c < 64; ++c)
         L[t][c] = (t < nb && c < nb) ? A[(int64_t)(o + t) * lda + o + c] : (t == c ? 1.0 : 0.0);
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (t == j) {
-            double d = L[j][j];
-            if (!(d > 0.0)) {
-                atomicMin(bad, o + j);
-                d = 1.0;
-            }
-            L[j][j] = sqrt(d);
-        }
-        __syncthreads();
-        if (t > j && t < nb) L[t][j] /= L[j][j];
-        __syncthreads();
-        if (t > j && t < nb)
-            for (int c = j + 1; c <= t; ++c) L[t][c] -= L[t][j] * L[c][j];
-        __syncthreads();
-    }
+    potrf_inv_block64(L, nb, [&](int j) { atomicMin(bad, o + j); },
+                      [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
     for (int c = 0; c < 64; ++c)
         if (t < nb && c < nb) A[(int64_t)(o + t) * lda + o + c] = (c <= t) ? L[t][c] : 0.0;
-    // column t of L^{-1} by forward substitution
-    double x[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) x[i] = 0.0;
-    for (int i = 0; i < 64; ++i) {
-        double s = (i == t) ? 1.0 : 0.0;
-        for (int k = t; k < i; ++k) s -= L[i][k] * x[k];
-        x[i] = (i >= t) ? s / L[i][i] : 0.0;
-    }
-    for (int i = 0; i < 64; ++i) Dinv[i * 64 + t] = x[i];
 }
 
 __global__ void zero_upper_kernel(double* A, int n, int64_t lda) {
@@ -406,6 +401,15 @@ hipError_t trsm_lower_inplace(const double* L, int n, int64_t lda, const double*
                             B + (int64_t)K0 * ldb, ldb, 0, 1.0, B + (int64_t)K1 * ldb, ldb, 0, 1, 0, 0, s));
     }
     return hipSuccess;
+}
+
+hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (!ta && !tb) gemm_grouped_kernel<false, false><<<total, 256, 0, s>>>(d, prefix, n);
+    else if (!ta && tb) gemm_grouped_kernel<false, true><<<total, 256, 0, s>>>(d, prefix, n);
+    else if (ta && !tb) gemm_grouped_kernel<true, false><<<total, 256, 0, s>>>(d, prefix, n);
+    else gemm_grouped_kernel<true, true><<<total, 256, 0, s>>>(d, prefix, n);
+    return hipGetLastError();
 }
 
 hipError_t fill(double* p, double v, int64_t n, hipStream_t s) {

@@ -87,3 +87,54 @@ hipError_t mlp_train_step(const ri_mlp* net, float* m, float* v, int step, float
 hipError_t gather_density(int N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d, hipStream_t st);
 hipError_t scatter_density(int N, const int32_t* pairs, int64_t n_pairs, const float* d, double* D, hipStream_t st);
 }  // namespace ri
+
+namespace ri {
+// ---- batched SCF (many molecules per launch)
+// Per-molecule state of a batched SCF, resident in device memory.  Batched
+// kernels run over work items of all molecules: a per-kernel prefix table
+// (device, n_mol + 1 ints) maps each linear block index to (molecule, local).
+struct MolDesc {
+    int N, n_aux, n_occ, nt, npad, ks, mt, diis_n;
+    int64_t n_pairs, ntl, rows_pad, chunk;
+    double tol_E, tol_err;
+    const int32_t* pairs;
+    const double* Bc;
+    const void* B;
+    double *C, *J, *K, *gamma, *dpair, *part;
+    void* Xt;
+    double *S, *H, *LinvS, *F, *D, *T1, *T2, *E, *Fx, *X, *X2, *Y, *Cp, *Mo, *LinvM, *dinvM;
+    double *dF[8], *dE[8];
+    double *Bmat, *coef, *scal;
+    int* state;   // 0 active, 1 iteration, 2 DIIS pushes, 3 converged, 4.. DIIS slot order [8]
+};
+
+// One member of a grouped FP64 GEMM: C = alpha op(A) op(B) + beta C.
+struct GemmDesc {
+    int M, N, K, tri;
+    double alpha, beta;
+    const double* A;
+    const double* B;
+    double* C;
+    int64_t lda, ldb, ldc;
+    const int* active;
+};
+hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s);
+
+__device__ __forceinline__ void decode_item(const int* prefix, int n_mol, int L, int& mol, int& local) {
+    int lo = 0, hi = n_mol;            // prefix[lo] <= L < prefix[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= L) lo = mid; else hi = mid;
+    }
+    mol = lo;
+    local = L - prefix[lo];
+}
+
+// batched Fock build pieces (fock.hip); `prec` is RI_FP64 or RI_FP32 for all molecules
+hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int mt, int prec, hipStream_t st);
+hipError_t syrk_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);
+hipError_t kreduce_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st);
+hipError_t zero_tail_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);
+hipError_t gamma_j_b(const MolDesc* d, int n_mol, const int* pre_pairs, int tot_pairs, const int* pre_aux, int tot_aux,
+                     const int* pre_n2, int tot_n2, hipStream_t st);
+}  // namespace ri

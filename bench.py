@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="also run the batched workload (256 molecules, 10-60 centres) and report SCF/s")
     ap.add_argument("--batched-n", type=int, default=256, help="molecules in the batched workload")
+    ap.add_argument("--batched-prec", default="fp32", choices=["fp32", "fp64"],
+                    help="exchange precision of the batched workload")
     ap.add_argument("--quick", action="store_true",
                     help="profiling mode: seeded random occupied orbitals instead of the converged SCF "
                          "(same shapes and kernels), no pipeline, no CPU baseline")
@@ -153,7 +155,7 @@ def main():
     if not args.quick:
         out["precision"] = precision_leg(s, C, res, args, P, torch, np)
     if args.batched:
-        out["batched"] = batched_leg(args.batched_n)
+        out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec)
     if args.learned:
         out["learned_start"] = learned_leg(args.learned_steps)
     if args.calib:
@@ -202,7 +204,7 @@ def precision_leg(s, C, res64, args, P, torch, np):
     return out
 
 
-def batched_leg(n_mol, wave=128, baseline_n=32):
+def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32"):
     """256 independent He-like clusters with n_centres ~ U{10..60} (N = 10 per
     centre, N_aux = 30 per centre, n_occ = n_centres), seeds 4001...: pairs, 3c
     integrals and FP32 B per molecule, then one lockstep SCF per wave of
@@ -217,6 +219,10 @@ def batched_leg(n_mol, wave=128, baseline_n=32):
     import paper_2407_19614_amd as P
     from paper_2407_19614_amd.binding import energy_batched
     systems = synth.batched_systems(n_mol)
+    prec = P.FP32 if prec_name == "fp32" else P.FP64
+    if prec == P.FP64:
+        wave = min(wave, 96)                      # FP64 packed B is twice the size
+    tol = dict(tol_E=1e-7, tol_err=1e-5) if prec == P.FP32 else dict(tol_E=1e-10, tol_err=1e-8)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     E = np.full(len(systems), np.nan)
     iters = np.zeros(len(systems), dtype=int)
@@ -228,14 +234,14 @@ def batched_leg(n_mol, wave=128, baseline_n=32):
         ts = time.perf_counter()
         probs = []
         for s in systems[w0:w0 + wave]:
-            pr = P.RIProblem(s, prec=P.FP32)
+            pr = P.RIProblem(s, prec=prec)
             pr.build_3c()
-            pr.metric_factor(P.FP32)
+            pr.metric_factor(prec)
             probs.append(pr)
         torch.cuda.synchronize()
         t_setup += time.perf_counter() - ts
         ts = time.perf_counter()
-        res, _, _ = energy_batched(probs, P.FP32, tol_E=1e-8, tol_err=1e-6, use_graph=True, raise_on_noconv=False)
+        res, _, _ = energy_batched(probs, prec, use_graph=True, raise_on_noconv=False, **tol)
         torch.cuda.synchronize()
         t_scf += time.perf_counter() - ts
         for k, r in enumerate(res):
@@ -257,13 +263,14 @@ def batched_leg(n_mol, wave=128, baseline_n=32):
         del pr
     torch.cuda.synchronize()
     t_base = time.perf_counter() - tb
-    out = {"workload": f"{len(systems)} He-like clusters, 10-60 centres (N 100-600, N_aux 300-1800), FP32 exchange",
+    out = {"workload": f"{len(systems)} He-like clusters, 10-60 centres (N 100-600, N_aux 300-1800), "
+                       f"{prec_name.upper()} exchange",
            "scf_per_s": round(len(systems) / wall, 3), "wall_s": round(wall, 2),
            "setup_s": round(t_setup, 2), "batched_scf_s": round(t_scf, 2),
            "all_converged": bool(conv.all()), "mean_iters": round(float(iters.mean()), 2),
            "fp64_single_path_scf_per_s": round(baseline_n / t_base, 3),
            "fp64_single_path_sample": f"first {baseline_n} molecules",
-           "max_abs_dE_fp32_batched_vs_fp64_single": float(np.max(np.abs(E[:baseline_n] - np.array(E64))))}
+           "max_abs_dE_batched_vs_fp64_single": float(np.max(np.abs(E[:baseline_n] - np.array(E64))))}
     gold = os.path.join(ROOT, "tests", "golden", "batch_oracle.json")
     if os.path.exists(gold) and len(systems) == 256:
         ref = json.load(open(gold))

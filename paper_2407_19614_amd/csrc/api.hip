@@ -192,6 +192,10 @@ int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool hav
 
 }  // namespace
 
+namespace ri {
+void set_hip_error(const char* text) { g_hip_err = text; }
+}  // namespace ri
+
 extern "C" {
 
 const char* ri_version(void) { return "libri 0.1 (gfx950)"; }

@@ -372,7 +372,6 @@ hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
     return hipGetLastError();
 }
 
-thread_local std::string g_batch_err;
 
 }  // namespace
 
@@ -553,7 +552,7 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
 #define HIPR(x)                                                          \
     do {                                                                 \
         hipError_t _e = (x);                                             \
-        if (_e != hipSuccess) { g_batch_err = hipGetErrorString(_e); return RI_E_HIP; } \
+        if (_e != hipSuccess) { ri::set_hip_error(hipGetErrorString(_e)); return RI_E_HIP; } \
     } while (0)
     // upload descriptors and tables
     HIPR(hipMemcpyAsync(p.d, hp.mols.data(), sizeof(MolDesc) * n_mol, hipMemcpyHostToDevice, st));
@@ -590,26 +589,39 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
     // core-Hamiltonian start
     copy_h_b<<<p.n2.total, 256, 0, st>>>(p.d, p.n2.prefix, n_mol);
     HIPR(occupied_space_b(p, st));
-    // iterations
+    // iterations.  A graph is captured on a private non-blocking stream (the
+    // caller's stream may be the legacy default stream, which cannot be
+    // captured); the host waits for every iteration, so ordering with the
+    // caller's stream is kept by synchronising before the first replay.
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipStream_t cs = st;
     if (use_graph) {
-        HIPR(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e = iteration_b(p, opts->max_iter, st);
-        hipError_t e2 = hipStreamEndCapture(st, &graph);
-        HIPR(e);
-        HIPR(e2);
-        HIPR(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPR(hipStreamSynchronize(st));
+        HIPR(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e0 = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        hipError_t e = e0 == hipSuccess ? iteration_b(p, opts->max_iter, cs) : e0;
+        hipError_t e2 = e0 == hipSuccess ? hipStreamEndCapture(cs, &graph) : hipSuccess;
+        hipError_t e3 = (e == hipSuccess && e2 == hipSuccess) ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)
+                                                               : hipSuccess;
+        if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            hipStreamDestroy(cs);
+            HIPR(e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3));
+        }
     }
     int active = n_mol;
+    hipError_t loop_err = hipSuccess;
     for (int it = 0; it < opts->max_iter && active > 0; ++it) {
-        if (use_graph) HIPR(hipGraphLaunch(exec, st));
-        else HIPR(iteration_b(p, opts->max_iter, st));
-        HIPR(hipMemcpyAsync(&active, p.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPR(hipStreamSynchronize(st));
+        loop_err = use_graph ? hipGraphLaunch(exec, cs) : iteration_b(p, opts->max_iter, cs);
+        if (loop_err == hipSuccess) loop_err = hipMemcpyAsync(&active, p.n_active, sizeof(int), hipMemcpyDeviceToHost, cs);
+        if (loop_err == hipSuccess) loop_err = hipStreamSynchronize(cs);
+        if (loop_err != hipSuccess) break;
     }
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
+    if (cs != st) hipStreamDestroy(cs);
+    HIPR(loop_err);
     // results
     bool all = true;
     for (int i = 0; i < n_mol; ++i) {

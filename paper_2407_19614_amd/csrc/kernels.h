@@ -89,6 +89,7 @@ hipError_t scatter_density(int N, const int32_t* pairs, int64_t n_pairs, const f
 }  // namespace ri
 
 namespace ri {
+void set_hip_error(const char* text);   // text returned by ri_last_hip_error
 // ---- batched SCF (many molecules per launch)
 // Per-molecule state of a batched SCF, resident in device memory.  Batched
 // kernels run over work items of all molecules: a per-kernel prefix table

@@ -175,32 +175,35 @@ def main():
 
 
 def precision_leg(s, C, res64, args, P, torch, np):
-    """FP32 exchange contractions at the same workload: Fock builds/s, speedup
-    over FP64, and the FP32 SCF energy's difference from the FP64 one."""
+    """Reduced-precision exchange contractions at the same workload: Fock
+    builds/s and speedup over FP64, and each SCF energy's difference from the
+    FP64 one.  FP32: FP32 MFMA; BF16X3 / BF16X6: two- and three-part BF16
+    splits with 3 and 6 products on BF16 MFMA.  gamma and J stay FP64."""
     dev = C.device
-    pr = P.RIProblem(s, device=dev, prec=P.FP32)
-    pr.build_3c()
-    pr.metric_factor(P.FP32)
     N, na = s.N, s.n_aux
-    J = torch.empty((N, N), dtype=torch.float64, device=dev)
-    K = torch.empty_like(J)
-    g = torch.empty(na, dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        pr.fock_jk(C, J, K, g)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(args.steps):
-        pr.fock_jk(C, J, K, g)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / args.steps
-    # FP32 exchange leaves a commutator floor near 1e-6: converge on |dE| with a looser error bound
-    r32, *_ = pr.energy(tol_E=1e-9, tol_err=1e-5, max_iter=60, raise_on_noconv=False)
-    out = {"fp32_builds_per_s": round(1.0 / dt, 3), "fp32_ms_per_build": round(dt * 1e3, 3),
-           "fp32_scf_E": r32["E_total"], "fp32_scf_iters": r32["n_iter"],
-           "fp32_scf_converged": r32["converged"], "fp32_scf_max_err": r32["max_err"],
-           "fp32_abs_dE_vs_fp64": abs(r32["E_total"] - res64["E_total"])}
-    del pr
-    torch.cuda.empty_cache()
+    out = {}
+    for name, prec, tol in (("fp32", P.FP32, (1e-9, 1e-5)), ("bf16x3", P.BF16X3, (1e-7, 1e-5)),
+                            ("bf16x6", P.BF16X6, (1e-9, 1e-6))):
+        pr = P.RIProblem(s, device=dev, prec=prec)
+        pr.build_3c()
+        pr.metric_factor(prec)
+        J = torch.empty((N, N), dtype=torch.float64, device=dev)
+        K = torch.empty_like(J)
+        g = torch.empty(na, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            pr.fock_jk(C, J, K, g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            pr.fock_jk(C, J, K, g)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
+        out[name] = {"builds_per_s": round(1.0 / dt, 3), "ms_per_build": round(dt * 1e3, 3),
+                     "scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
+                     "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])}
+        del pr, J, K, g
+        torch.cuda.empty_cache()
     return out
 
 

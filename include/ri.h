@@ -55,9 +55,11 @@ typedef enum {
     RI_FP64 = 0,     /* B in FP64, FP64 MFMA                                  */
     RI_FP32 = 1,     /* B in FP32, FP32 MFMA, FP32 accumulation per P-chunk,  */
                      /* FP64 across chunks                                    */
-    RI_BF16X3 = 2    /* B split as hi + lo bfloat16; products hi*hi + hi*lo + */
+    RI_BF16X3 = 2,   /* B split as hi + lo bfloat16; products hi*hi + hi*lo + */
                      /* lo*hi on BF16 MFMA with FP32 accumulation per chunk,  */
                      /* FP64 across chunks                                    */
+    RI_BF16X6 = 3    /* three-part split hi + mid + lo; the six products whose */
+                     /* part orders add to at most 2 (about FP32 accuracy)    */
 } ri_precision;
 
 /* Molecular system.  The struct lives in host memory; every array is a
@@ -79,9 +81,11 @@ typedef struct {
  * Symmetry-utilisation section) and is stored as the lower triangle of
  * 64 x 64 tiles: tile (I, J), I >= J, has index I(I+1)/2 + J and holds
  * B^P[64I + r][64J + c] at offset r*64 + c; entries beyond N are zero.
- * Layout [n_aux][n_tiles][64*64] of the storage type (double, float, or for
- * RI_BF16X3 two planes of uint16 bfloat16 words: the hi plane for all P
- * followed by the lo plane).  ri_packed_b_bytes() returns the size. */
+ * Layout [n_aux][n_tiles][64*64] of the storage type (double or float).
+ * The split-BF16 precisions store full square tiles instead, in 2 (BF16X3)
+ * or 3 (BF16X6) planes of bfloat16 parts: [part][n_aux][nt][nt][64*64] with
+ * tile (I, J) holding B^P[64I + r][64J + c] at r*64 + c for every I and J.
+ * ri_packed_b_bytes() returns the size. */
 #define RI_TILE 64
 size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec);
 

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libri.so")
 
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 OP_BUILD_3C, OP_METRIC, OP_FOCK, OP_ENERGY, OP_GRADIENT = range(5)
 STATUS = {0: "RI_OK", 1: "RI_E_ARG", 2: "RI_E_NOT_PD", 3: "RI_E_NO_CONV", 4: "RI_E_WORKSPACE",
           5: "RI_E_CAPACITY", 6: "RI_E_HIP", 7: "RI_E_UNSUPPORTED"}

@@ -47,6 +47,7 @@ bool valid_sys(const ri_system* s) {
 }
 
 size_t elem_size(int prec) { return prec == RI_FP64 ? 8 : (prec == RI_FP32 ? 4 : 2); }
+bool is_bf16(int prec) { return prec == RI_BF16X3 || prec == RI_BF16X6; }
 
 // ---------------------------------------------------------------- layouts
 struct BuildWS { int32_t* counts; int64_t* offsets; };
@@ -67,8 +68,19 @@ struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* ga
 FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec) {
     FockWS w;
     const int Npad = ri::xt_ld(N);
-    w.ks = ri::k_split_count(N, n_aux, n_occ);
     w.js = ri::j_split_count(n_aux);
+    if (is_bf16(prec)) {
+        const int ns = ri::bf16_parts(prec);
+        w.ks = ri::bf16_split_count(N, n_aux, n_occ);
+        w.Xt = a.take<char>(ri::bf16_xb_elems(N, n_aux, n_occ) * ns * 2);
+        w.part = a.take<double>((int64_t)w.ks * Npad * Npad);
+        w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
+        w.jpart = a.take<double>((int64_t)w.js * std::max<int64_t>(n_pairs, 1));
+        w.gamma = a.take<double>(n_aux);
+        w.Cp = a.take<double>(ri::bf16_ct_elems(N, n_occ) * ns / 4 + 1);   // bf16 parts of C^T
+        return w;
+    }
+    w.ks = ri::k_split_count(N, n_aux, n_occ);
     w.Xt = a.take<char>(ri::xt_rows(n_aux, n_occ) * Npad * (int64_t)(prec == RI_FP64 ? 8 : 4));
     w.part = a.take<double>((int64_t)w.ks * Npad * Npad);
     w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
@@ -139,6 +151,13 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
     if (ev) HIPC(hipEventRecord(ev[0], st));
     HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, st));
     if (ev) HIPC(hipEventRecord(ev[1], st));
+    if (is_bf16(prec)) {
+        HIPC(ri::x_transform_bf16(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
+        if (ev) HIPC(hipEventRecord(ev[2], st));
+        HIPC(ri::k_syrk_bf16(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
+        if (ev) HIPC(hipEventRecord(ev[3], st));
+        return RI_OK;
+    }
     HIPC(ri::x_transform(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
     if (ev) HIPC(hipEventRecord(ev[2], st));
     HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
@@ -217,12 +236,16 @@ const char* ri_status_str(int32_t s) {
 }
 
 size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec) {
-    if (N <= 0 || n_aux <= 0 || prec < 0 || prec > 2) return 0;
-    return (size_t)n_aux * ri::tile_elems(N) * elem_size(prec) * (prec == RI_BF16X3 ? 2 : 1);
+    if (N <= 0 || n_aux <= 0 || prec < 0 || prec > 3) return 0;
+    if (is_bf16(prec)) {
+        const int64_t nt = ri::n_tiles_1d(N);
+        return (size_t)ri::bf16_parts(prec) * n_aux * nt * nt * 4096 * 2;
+    }
+    return (size_t)n_aux * ri::tile_elems(N) * elem_size(prec);
 }
 
 size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, int64_t n_pairs, int32_t prec) {
-    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_pairs < 0 || prec < 0 || prec > 2) return 0;
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_pairs < 0 || prec < 0 || prec > 3) return 0;
     Arena a{nullptr, 0, 0, true};
     switch (op) {
         case RI_OP_BUILD_3C: carve_build(a, N); break;
@@ -262,8 +285,7 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
                          hipStream_t st) {
     if (!valid_sys(sys) || n_pairs < 0 || (n_pairs > 0 && (!pairs || !T)) || !L || !Linv || !bad_pivot || !ws)
         return RI_E_ARG;
-    if (prec < 0 || prec > 2) return RI_E_UNSUPPORTED;
-    if (B && prec == RI_BF16X3) return RI_E_UNSUPPORTED;
+    if (prec < 0 || prec > 3) return RI_E_UNSUPPORTED;
     const int na = sys->n_aux, N = sys->n_fn;
     Arena a{(char*)ws, ws_bytes, 0, false};
     MetricWS w = carve_metric(a, N, na, n_pairs);
@@ -283,7 +305,8 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
     if (n_pairs > 0) HIPC(ri::trsm_lower_inplace(L, na, na, w.dinv, T, (int)n_pairs, n_pairs, st));
     if (B) {
         HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
-        HIPC(ri::pack_b(T, n_pairs, w.map, N, na, B, prec, st));
+        if (is_bf16(prec)) HIPC(ri::pack_b_bf16(T, n_pairs, w.map, N, na, B, prec, st));
+        else HIPC(ri::pack_b(T, n_pairs, w.map, N, na, B, prec, st));
     }
     return RI_OK;
 }
@@ -294,7 +317,7 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
     if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
         (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    if (prec < 0 || prec > 3 || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
     Arena a{(char*)ws, ws_bytes, 0, false};
     FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
     if (!a.ok()) return RI_E_WORKSPACE;
@@ -308,7 +331,7 @@ int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B,
     if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
         (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    if (prec < 0 || prec > 3 || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
     Arena a{(char*)ws, ws_bytes, 0, false};
     FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
     if (!a.ok()) return RI_E_WORKSPACE;
@@ -325,7 +348,7 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
         return RI_E_ARG;
     if (opts->guess_kind != 0 && !guess) return RI_E_ARG;
     if (opts->guess_kind < 0 || opts->guess_kind > 2) return RI_E_UNSUPPORTED;
-    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    if (prec < 0 || prec > 3 || (is_bf16(prec) && sys->n_occ > 128)) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
     Arena a{(char*)ws, ws_bytes, 0, false};

@@ -139,3 +139,18 @@ hipError_t zero_tail_b(const MolDesc* d, const int* prefix, int n_mol, int total
 hipError_t gamma_j_b(const MolDesc* d, int n_mol, const int* pre_pairs, int tot_pairs, const int* pre_aux, int tot_aux,
                      const int* pre_n2, int tot_n2, hipStream_t st);
 }  // namespace ri
+
+namespace ri {
+// ---- split-BF16 exchange (bf16.hip)
+int bf16_parts(int prec);
+int64_t bf16_R(int n_aux, int n_occ);
+int64_t bf16_ct_elems(int N, int n_occ);
+int64_t bf16_xb_elems(int N, int n_aux, int n_occ);
+int bf16_split_count(int N, int n_aux, int n_occ);
+hipError_t pack_b_bf16(const double* Bc, int64_t n_pairs, const int32_t* map, int N, int n_aux, void* B, int prec,
+                       hipStream_t st);
+hipError_t x_transform_bf16(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, void* Ct,
+                            void* Xb, hipStream_t st);
+hipError_t k_syrk_bf16(const void* Xb, int prec, int N, int n_aux, int n_occ, double* part, int n_split, double* K,
+                       hipStream_t st);
+}  // namespace ri

@@ -49,3 +49,23 @@ def test_fp32_energy_and_gradient(ref):
     print(f"fp32 |dE|={dE:.2e} max|dg|={dg:.2e}", flush=True)
     assert dE <= 1e-6
     assert dg <= 1e-5
+
+
+@pytest.mark.parametrize("prec_name,tolK,tolE", [("BF16X3", 5e-4, 1e-4), ("BF16X6", 1e-6, 1e-6)])
+def test_bf16_split_fock_and_energy(ref, prec_name, tolK, tolE):
+    s, ri, res, _ = ref
+    import paper_2407_19614_amd as P
+    prec = {"BF16X3": P.BF16X3, "BF16X6": P.BF16X6}[prec_name]
+    print(f"case: tiny {prec_name}", flush=True)
+    pr = problem(s, prec)
+    C = synth.random_coeffs(s.N, s.n_occ, seed=0)
+    J, K, _ = pr.fock_jk(dev(C))
+    Jr, Kr = ri.JK(C)
+    dJ = np.abs(to_np(J) - Jr).max()
+    dK = np.abs(to_np(K) - Kr).max() / np.abs(Kr).max()
+    r, *_ = pr.energy(tol_E=1e-9, tol_err=1e-6, max_iter=60, raise_on_noconv=False)
+    dE = abs(r["E_total"] - res.E)
+    print(f"{prec_name} max|dJ|={dJ:.2e} max rel|dK|={dK:.2e} |dE|={dE:.2e} conv={r['converged']}", flush=True)
+    assert dJ < 1e-11
+    assert dK < tolK
+    assert dE < tolE

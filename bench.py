@@ -192,14 +192,21 @@ def precision_leg(s, C, res64, args, P, torch, np):
         g = torch.empty(na, dtype=torch.float64, device=dev)
         for _ in range(args.warmup):
             pr.fock_jk(C, J, K, g)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        for e4 in ev:
+            for e in e4:
+                e.record(torch.cuda.current_stream(dev))
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(args.steps):
-            pr.fock_jk(C, J, K, g)
+        for e4 in ev:
+            pr.fock_jk_timed(C, J, K, g, e4)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
+        ph = np.array([[e4[i].elapsed_time(e4[i + 1]) for i in range(3)] for e4 in ev]).mean(0)
         r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
         out[name] = {"builds_per_s": round(1.0 / dt, 3), "ms_per_build": round(dt * 1e3, 3),
+                     "phases_ms": {"gamma_J": round(float(ph[0]), 3), "X": round(float(ph[1]), 3),
+                                   "K_syrk": round(float(ph[2]), 3)},
                      "scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
                      "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])}
         del pr, J, K, g

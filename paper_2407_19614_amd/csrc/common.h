@@ -8,6 +8,8 @@
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+// LDS destination operand of __builtin_amdgcn_global_load_lds
+typedef __attribute__((address_space(3))) void* lds_void_t;
 
 #define RI_PI 3.14159265358979323846
 

@@ -138,7 +138,6 @@ __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict
     x2_body_f64<MT>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt, Npad);
 }
 
-typedef __attribute__((address_space(3))) void* lds_void_t;
 
 // X^T via direct global->LDS loads: same work split as x2_kernel_f64 (one
 // row-block I, two auxiliary indices per workgroup), but the B^P tile slices

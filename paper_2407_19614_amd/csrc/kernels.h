@@ -142,6 +142,8 @@ hipError_t gamma_j_b(const MolDesc* d, int n_mol, const int* pre_pairs, int tot_
 
 namespace ri {
 // ---- split-BF16 exchange (bf16.hip)
+// compute units of the current device (256 if it cannot be queried); cached per device
+int device_cus();
 int bf16_parts(int prec);
 int64_t bf16_R(int n_aux, int n_occ);
 int64_t bf16_ct_elems(int N, int n_occ);

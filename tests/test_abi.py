@@ -38,7 +38,9 @@ def test_workspace_and_packed_sizes():
     # packed tiles: 16 x 17 / 2 tiles of 64 x 64 per auxiliary function at N=1000
     assert P.packed_b_bytes(1000, 3000, P.FP64) == 3000 * 136 * 4096 * 8
     assert P.packed_b_bytes(1000, 3000, P.FP32) == 3000 * 136 * 4096 * 4
-    assert P.packed_b_bytes(1000, 3000, P.BF16X3) == 3000 * 136 * 4096 * 2 * 2
+    # split BF16: full square 64 x 64 tiles (16 x 16 per auxiliary), 2 or 3 bf16 parts
+    assert P.packed_b_bytes(1000, 3000, P.BF16X3) == 2 * 3000 * 256 * 4096 * 2
+    assert P.packed_b_bytes(1000, 3000, P.BF16X6) == 3 * 3000 * 256 * 4096 * 2
     for op in range(4):
         assert P.workspace_bytes(op, 32, 80, 8, 528, P.FP64) > 0
     assert P.workspace_bytes(0, 0, 80, 8, 528, P.FP64) == 0

@@ -6,9 +6,9 @@
 // FP64 across chunks.
 //
 // Layouts:
-//   B  [NS][n_aux][nt][nt][64][64]  full square tiles: tile (I,J) holds
-//      B^P[64I + r][64J + c] at r*64 + c (both triangles stored, so a row
-//      block is contiguous along nu in every tile).
+//   B  [NS][n_aux][nt][nt][2][64][32]  full square tiles (both triangles):
+//      tile (I,J) holds B^P[64I + r][64J + 32h + c] at h*2048 + r*32 + c, so
+//      the 32-deep half h of 16 consecutive rows is one contiguous 1 KB run.
 //   Ct [NS][W][Npad]   C_occ^T parts, W = 16 * MT occupied rows (zero padded).
 //   Xb [NS][Npad][R]   X parts with mu as the row and (P, i) -> P*n_occ + i
 //      as the contiguous K index, R = n_aux*n_occ rounded up to 64.
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void pack_bf16_kernel(const double* Bc, int64_
     const int64_t plane = (int64_t)n_aux * nt * nt * 4096;
     __bf16* out = B + ((int64_t)P * nt * nt + t) * 4096;
     for (int e = threadIdx.x; e < 4096; e += 256) {
-        int mu = 64 * I + (e >> 6), nu = 64 * J + (e & 63);
+        int mu = 64 * I + ((e >> 5) & 63), nu = 64 * J + 32 * (e >> 11) + (e & 31);
         double v = 0.0;
         if (mu < N && nu < N) {
             int a = max(mu, nu), b = min(mu, nu);
@@ -86,22 +86,24 @@ __global__ void xb_pad_kernel(__bf16* Xb, int ns, int Npad, int64_t R, int rows_
     Xb[(int64_t)k * Npad * R + idx] = (__bf16)0.0f;
 }
 
-// Both contractions stream their operands through a three-stage LDS ring
-// filled by direct global->LDS loads (16 B per lane; one wave instruction
-// moves 16 rows x 64 B, i.e. a 32-deep k-slice of 16 rows).  Each 64 B row
-// holds four 16 B chunks; chunk c of row r sits at c ^ ((r >> 2) & 3) so that
-// the 16 rows one fragment read touches fall on distinct banks.  A stage is
-// consumed two iterations after it is issued (one barrier per stage).
+// Both contractions run 8 waves per workgroup (two per SIMD) and stage shared
+// operands through a three-slot LDS ring filled by direct global->LDS loads
+// (16 B per lane; one wave instruction moves 16 rows x 64 B, a 32-deep
+// k-slice of 16 rows).  Each 64 B ring row holds four 16 B chunks; chunk c of
+// row r sits at c ^ ((r >> 1) & 3), so any 8 consecutive lanes of a fragment
+// read (8 rows, same chunk) touch 8 distinct 16 B bank groups.  A slot is
+// consumed two stages after it is issued, with one barrier per stage.
 //
-// Accumulation: the leading product (part 0 x part 0) of every 32-deep MFMA
-// starts from zero and is added to an FP64 accumulator at once; the
-// correction products (orders 1 and 2, at most 2^-8 of the leading term)
-// share an FP32 accumulator.  Rounding therefore costs one FP32 rounding of a
-// 32-term partial sum per fold instead of a chain of them.
+// Accumulation per output tile: the leading product (part 0 x part 0) of each
+// 32-deep step starts from zero and is added to an FP64 accumulator at once;
+// the correction products (orders 1 .. NS-1, at most 2^-8 of the leading
+// term) share an FP32 accumulator that is folded into the FP64 one every
+// eight steps.  The leading term thus carries one FP32 rounding per 32-term
+// partial sum.
 constexpr int RING = 3;
 constexpr int ROWB = 32;   // bf16 per ring row (one 32-deep k-slice)
 
-__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
+__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
 
 // s_waitcnt with vmcnt = n (expcnt / lgkmcnt not waited on)
 template <int n>
@@ -114,128 +116,173 @@ __device__ __forceinline__ bf8_t lds_frag(const __bf16* base, int row, int lk) {
     return *(const bf8_t*)(base + row * ROWB + 8 * swz(row, lk));
 }
 
+// One 32-deep split product: leading term into the FP64 accumulator,
+// corrections into the FP32 one (see above).
+template <int NS>
+__device__ __forceinline__ void split_mfma(const bf8_t (&a)[NS], const bf8_t (&b)[NS], d4_t& acc, f4_t& corr) {
+#pragma unroll
+    for (int o = 1; o < NS; ++o)
+#pragma unroll
+        for (int p = 0; p <= o; ++p) corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[p], b[o - p], corr, 0, 0, 0);
+    const f4_t t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], f4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += (double)t[r];
+}
+
+__device__ __forceinline__ void fold(d4_t& acc, f4_t& corr) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        acc[r] += (double)corr[r];
+        corr[r] = 0.f;
+    }
+}
+
 // X for items (row block I2 of 128 rows, auxiliary P), item = I2 + nt2 * P,
-// items b, b + G, ... for block b of G (persistent).  D[mu][i] = sum_nu
-// B^P[mu][nu] C[nu][i]; wave w owns mu rows 32w .. 32w+31 of the block and
-// all MT occupied tiles.
+// items b, b + G, ... for workgroup b of G (persistent).  D[mu][i] = sum_nu
+// B^P[mu][nu] C[nu][i].  Wave w owns rows 32 (w % 4) .. +31 of the item and
+// column half w / 4 (tiles 0 .. MA-1 or MA .. MT-1).  B fragments go straight
+// to registers (each is used by one wave pair), three buffers deep; C goes
+// through the LDS ring.  Item, stage and slot advance by counters; rows of a
+// tile index >= nt load tile nt - 1 and are never written.
 template <int NS, int MT>
-__global__ __launch_bounds__(256, 1) void x_bf16_kernel(const __bf16* __restrict__ B, int nt, int n_aux,
+__global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict__ B, int nt, int n_aux,
                                                         const __bf16* __restrict__ Ct, int Npad, int n_occ,
                                                         __bf16* __restrict__ Xb, int64_t R) {
-    constexpr int W = 16 * MT;
-    constexpr int SB = NS * 128 * ROWB, SC = NS * W * ROWB, STAGE = SB + SC;
-    constexpr int NB = NS * 8 / 4;                 // B instructions per wave per stage
-    constexpr int NCI = NS * MT, NC = (NCI + 3) / 4;   // C instructions (total, per wave)
-    constexpr int LOADS = NB + NC;
-    __shared__ __attribute__((aligned(16))) __bf16 ring[RING * STAGE];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-    const int nt2 = (nt + 1) / 2, spi = 2 * nt;    // stages per item
-    const int64_t n_items = (int64_t)nt2 * n_aux;
-    const int64_t mine = n_items > blockIdx.x ? (n_items - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-    const int64_t total = mine * spi;
+    constexpr int W = 16 * MT, MA = (MT + 1) / 2;
+    constexpr int SC = NS * W * ROWB;
+    constexpr int NCI = NS * MT, NC = (NCI + 7) / 8;   // C instructions (total, per wave)
+    constexpr int LOADS = 2 * NS + NC;                 // VMEM ops per wave per stage
+    __shared__ __attribute__((aligned(16))) __bf16 cring[RING * SC];
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rg = wave & 3, cg = wave >> 2;
+    const int m0 = cg * MA, mcount = cg ? MT - MA : MA;
+    const int nt2 = (nt + 1) / 2, spi = 2 * nt;        // stages per item
+    const int n_items = nt2 * n_aux;
+    const int G = gridDim.x;
+    const int mine = n_items > (int)blockIdx.x ? (n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
+    if (mine == 0) return;
     const int64_t bplane = (int64_t)n_aux * nt * nt * 4096;
     const int64_t cplane = (int64_t)W * Npad;
-    const int lrow = lane >> 2, lch = lane & 3;    // row within a 16-row load group, chunk
+    const int lrow = lane >> 2, lch = lane & 3;
+    const int boff = ((rg & 1) * 32 + li) * ROWB + 8 * lk;   // + 16 * ROWB for the second fragment
+    const int btile = rg >> 1;
+    const __bf16* csrc[NC];
+    int cdst[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+        const int t = min(wave + 8 * u, NCI - 1), q = t / MT, mg = t % MT, row = 16 * mg + lrow;
+        csrc[u] = Ct + q * cplane + (int64_t)row * Npad + 8 * swz(row, lch);
+        cdst[u] = (q * W + 16 * mg) * ROWB;
+    }
 
-    auto issue = [&](int64_t g) {
-        if (g >= total) g = total - 1;             // tail: reload the last stage (never read)
-        const int64_t item = blockIdx.x + (g / spi) * gridDim.x;
-        const int s = (int)(g % spi), J = s >> 1, ks = s & 1;
-        const int I2 = (int)(item % nt2), P = (int)(item / nt2);
-        __bf16* st = ring + (int)(g % RING) * STAGE;
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int t = wave + 4 * u, p = t >> 3, rg = t & 7;
-            const int row = 16 * rg + lrow;
-            const int I = min(2 * I2 + (row >> 6), nt - 1);
-            const __bf16* src = B + p * bplane + (((int64_t)P * nt + I) * nt + J) * 4096 + (row & 63) * 64 +
-                                32 * ks + 8 * swz(row, lch);
-            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t)(st + (p * 128 + 16 * rg) * ROWB), 16, 0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < NC; ++u) {
-            const int t = min(wave + 4 * u, NCI - 1), q = t / MT, mg = t % MT;
-            const int row = 16 * mg + lrow;
-            const __bf16* src = Ct + q * cplane + (int64_t)row * Npad + 64 * J + 32 * ks + 8 * swz(row, lch);
-            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t)(st + SB + (q * W + 16 * mg) * ROWB), 16,
-                                             0, 0);
-        }
-    };
-
-    d4_t acc64[2][MT];
-    f4_t accc[2][MT];
-    const f4_t zero = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int m = 0; m < MT; ++m) { acc64[f][m] = d4_t{0, 0, 0, 0}; accc[f][m] = zero; }
-    if (total == 0) return;
-    issue(0);
-    issue(1);
-    for (int64_t g = 0; g < total; ++g) {
-        wait_vm<LOADS>();
-        __builtin_amdgcn_s_barrier();
-        issue(g + 2);
-        const __bf16* sb = ring + (int)(g % RING) * STAGE;
-        const __bf16* sc = sb + SB;
-        bf8_t a[2][NS];
+    int ij = 0, is = 0;                                 // next stage to issue
+    int iI2 = (int)blockIdx.x % nt2, iP = (int)blockIdx.x / nt2;
+    auto issue = [&](bf8_t (&bf)[2][NS], int slot) {
+        const int J = is >> 1, ks = is & 1;
+        const int I = min(2 * iI2 + btile, nt - 1);
+        const __bf16* tb = B + (((int64_t)iP * nt + I) * nt + J) * 4096 + ks * 2048 + boff;
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int p = 0; p < NS; ++p) a[f][p] = lds_frag(sb + p * 128 * ROWB, 32 * wave + 16 * f + li, lk);
+            for (int p = 0; p < NS; ++p) bf[f][p] = *(const bf8_t*)(tb + p * bplane + f * 16 * ROWB);
+        __bf16* st = cring + slot * SC;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            bf8_t c[NS];
+        for (int u = 0; u < NC; ++u)
+            __builtin_amdgcn_global_load_lds((const void*)(csrc[u] + 64 * J + 32 * ks), (lds_void_t)(st + cdst[u]),
+                                             16, 0, 0);
+        if (is + 1 < spi) ++is;
+        else if (ij + 1 < mine) {
+            is = 0;
+            ++ij;
+            const int item = (int)blockIdx.x + ij * G;
+            iI2 = item % nt2;
+            iP = item / nt2;
+        }   // else: stay on the last stage (tail reloads, never read)
+    };
+
+    d4_t acc[2][MA];
+    f4_t corr[2][MA];
 #pragma unroll
-            for (int q = 0; q < NS; ++q) c[q] = lds_frag(sc + q * W * ROWB, 16 * m + li, lk);
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                const f4_t h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f][0], c[0], zero, 0, 0, 0);
+        for (int m = 0; m < MA; ++m) { acc[f][m] = d4_t{0, 0, 0, 0}; corr[f][m] = f4_t{0.f, 0.f, 0.f, 0.f}; }
+    int64_t g = 0;
+    const int64_t total = (int64_t)mine * spi;
+    int cj = 0, cs = 0;
+    int cI2 = (int)blockIdx.x % nt2, cP = (int)blockIdx.x / nt2;
+    const int64_t xplane = (int64_t)Npad * R;
+
+    // compute the stage in registers `cur` / ring slot `slot`; returns true when done
+    auto body = [&](bf8_t (&cur)[2][NS], bf8_t (&nxt)[2][NS], int slot) -> bool {
+        wait_vm<LOADS>();
+        __builtin_amdgcn_s_barrier();
+        issue(nxt, slot == 0 ? 2 : slot - 1);
+        const __bf16* sc = cring + slot * SC;
 #pragma unroll
-                for (int p = 0; p < NS; ++p)
+        for (int mi = 0; mi < MA; ++mi) {
+            if (mi < mcount) {
+                bf8_t c[NS];
 #pragma unroll
-                    for (int q = 0; q < NS; ++q)
-                        if (p + q > 0 && p + q < NS)
-                            accc[f][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f][p], c[q], accc[f][m], 0, 0, 0);
+                for (int q = 0; q < NS; ++q) c[q] = lds_frag(sc + q * W * ROWB, 16 * (m0 + mi) + li, lk);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc64[f][m][r] += (double)h[r];
+                for (int f = 0; f < 2; ++f) split_mfma<NS>(cur[f], c, acc[f][mi], corr[f][mi]);
             }
         }
-        if ((g + 1) % spi == 0) {                  // item complete: write X parts, reset
-            const int64_t item = blockIdx.x + (g / spi) * gridDim.x;
-            const int I2 = (int)(item % nt2), P = (int)(item / nt2);
-            const int64_t xplane = (int64_t)Npad * R;
+        if ((cs & 7) == 7) {
 #pragma unroll
             for (int f = 0; f < 2; ++f)
 #pragma unroll
-                for (int m = 0; m < MT; ++m) {
+                for (int mi = 0; mi < MA; ++mi) fold(acc[f][mi], corr[f][mi]);
+        }
+        if (++cs == spi) {                               // item complete: write X parts, reset
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int mi = 0; mi < MA; ++mi) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int mu = 128 * I2 + 32 * wave + 16 * f + 4 * lk + r, i = 16 * m + li;
-                        if (mu < 64 * nt && i < n_occ) {
+                        const int mu = 128 * cI2 + 32 * rg + 16 * f + 4 * lk + r, i = 16 * (m0 + mi) + li;
+                        if (mi < mcount && mu < 64 * nt && i < n_occ) {
                             __bf16 pt[3];
-                            split_parts(acc64[f][m][r] + (double)accc[f][m][r], NS, pt);
-                            const int64_t o = (int64_t)mu * R + (int64_t)P * n_occ + i;
+                            split_parts(acc[f][mi][r] + (double)corr[f][mi][r], NS, pt);
+                            const int64_t o = (int64_t)mu * R + (int64_t)cP * n_occ + i;
 #pragma unroll
                             for (int k = 0; k < NS; ++k) Xb[k * xplane + o] = pt[k];
                         }
                     }
-                    acc64[f][m] = d4_t{0, 0, 0, 0};
-                    accc[f][m] = zero;
+                    acc[f][mi] = d4_t{0, 0, 0, 0};
+                    corr[f][mi] = f4_t{0.f, 0.f, 0.f, 0.f};
                 }
+            cs = 0;
+            if (++cj < mine) {
+                const int item = (int)blockIdx.x + cj * G;
+                cI2 = item % nt2;
+                cP = item / nt2;
+            }
         }
+        return ++g == total;
+    };
+
+    bf8_t b0[2][NS], b1[2][NS], b2[2][NS];
+    issue(b0, 0);
+    issue(b1, 1);
+    while (true) {
+        if (body(b0, b2, 0)) break;
+        if (body(b1, b0, 1)) break;
+        if (body(b2, b1, 2)) break;
     }
     wait_vm<0>();
 }
 
 // K partials over lower 128 x 128 tiles, split over the K index in multiples
 // of 32: part[z][mu][nu] = sum_r X[mu][r] X[nu][r] (split products).  Wave w
-// owns the 64 x 64 quarter (w / 2, w % 2).
+// owns rows 64 (w % 2) .. +63 and columns 32 (w / 2) .. +31 of the tile.
 template <int NS>
-__global__ __launch_bounds__(256, 1) void syrk_bf16_kernel(const __bf16* __restrict__ Xb, int Npad, int64_t R,
+__global__ __launch_bounds__(512, 1) void syrk_bf16_kernel(const __bf16* __restrict__ Xb, int Npad, int64_t R,
                                                            int64_t chunk, int ntile, double* __restrict__ part) {
     constexpr int SA = NS * 128 * ROWB, STAGE = 2 * SA;
-    constexpr int LOADS = 2 * NS * 8 / 4;
+    constexpr int LOADS = 2 * NS * 8 / 8;
     __shared__ __attribute__((aligned(16))) __bf16 ring[RING * STAGE];
     const int nlow = ntile * (ntile + 1) / 2;
     const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -244,77 +291,74 @@ __global__ __launch_bounds__(256, 1) void syrk_bf16_kernel(const __bf16* __restr
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
     const int tj = t - ti * (ti + 1) / 2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lrow = lane >> 2, lch = lane & 3;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
     const int64_t r0 = (int64_t)z * chunk, r1 = min(R, r0 + chunk);
     const int nst = (int)((r1 - r0) / ROWB);
     const int64_t xplane = (int64_t)Npad * R;
 
-    auto issue = [&](int s) {
-        if (s >= nst) s = nst - 1;
-        const int64_t rr = r0 + (int64_t)s * ROWB;
-        __bf16* st = ring + (s % RING) * STAGE;
+    const __bf16* src[LOADS];
+    int dst[LOADS];
 #pragma unroll
-        for (int u = 0; u < LOADS; ++u) {
-            const int tt = wave + 4 * u, side = tt / (NS * 8), rem = tt % (NS * 8), p = rem >> 3, rg = rem & 7;
-            const int row = 16 * rg + lrow;
-            const int base = side ? tj * 128 : ti * 128;
-            const __bf16* src = Xb + p * xplane + (int64_t)(base + row) * R + rr + 8 * swz(row, lch);
-            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t)(st + side * SA + (p * 128 + 16 * rg) * ROWB),
-                                             16, 0, 0);
-        }
+    for (int u = 0; u < LOADS; ++u) {
+        const int tt = wave + 8 * u, side = tt / (NS * 8), rem = tt % (NS * 8), p = rem >> 3, rg = rem & 7;
+        const int row = 16 * rg + lrow;
+        const int base = side ? tj * 128 : ti * 128;
+        src[u] = Xb + p * xplane + (int64_t)(base + row) * R + r0 + 8 * swz(row, lch);
+        dst[u] = side * SA + (p * 128 + 16 * rg) * ROWB;
+    }
+    int is = 0;
+    auto issue = [&](int slot) {
+        __bf16* st = ring + slot * STAGE;
+        const int64_t off = (int64_t)is * ROWB;
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u)
+            __builtin_amdgcn_global_load_lds((const void*)(src[u] + off), (lds_void_t)(st + dst[u]), 16, 0, 0);
+        if (is + 1 < nst) ++is;                    // tail: reload the last stage (never read)
     };
 
-    d4_t acc64[4][4];
-    f4_t accc[4][4];
-    const f4_t zero = {0.f, 0.f, 0.f, 0.f};
+    d4_t acc[4][2];
+    f4_t corr[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) { acc64[i][j] = d4_t{0, 0, 0, 0}; accc[i][j] = zero; }
+        for (int j = 0; j < 2; ++j) { acc[i][j] = d4_t{0, 0, 0, 0}; corr[i][j] = f4_t{0.f, 0.f, 0.f, 0.f}; }
+    int s = 0;
+    auto body = [&](int slot) -> bool {
+        wait_vm<LOADS>();
+        __builtin_amdgcn_s_barrier();
+        issue(slot == 0 ? 2 : slot - 1);
+        const __bf16* sa = ring + slot * STAGE;
+        const __bf16* sbb = sa + SA;
+        bf8_t a[4][NS], b[2][NS];
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i][p] = lds_frag(sa + p * 128 * ROWB, wm + 16 * i + li, lk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j][p] = lds_frag(sbb + p * 128 * ROWB, wn + 16 * j + li, lk);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) split_mfma<NS>(a[i], b[j], acc[i][j], corr[i][j]);
+        if ((s & 7) == 7) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) fold(acc[i][j], corr[i][j]);
+        }
+        return ++s == nst;
+    };
     if (nst > 0) {
         issue(0);
         issue(1);
-        for (int s = 0; s < nst; ++s) {
-            wait_vm<LOADS>();
-            __builtin_amdgcn_s_barrier();
-            issue(s + 2);
-            const __bf16* sa = ring + (s % RING) * STAGE;
-            const __bf16* sbb = sa + SA;
-            bf8_t a[4][NS], b[4][NS];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int p = 0; p < NS; ++p) {
-                    a[i][p] = lds_frag(sa + p * 128 * ROWB, wm + 16 * i + li, lk);
-                    b[i][p] = lds_frag(sbb + p * 128 * ROWB, wn + 16 * i + li, lk);
-                }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const f4_t h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], zero, 0, 0, 0);
-#pragma unroll
-                    for (int p = 0; p < NS; ++p)
-#pragma unroll
-                        for (int q = 0; q < NS; ++q)
-                            if (p + q > 0 && p + q < NS)
-                                accc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][p], b[j][q], accc[i][j], 0, 0, 0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)h[r];
-                }
-            if ((s & 7) == 7) {                    // corrections: FP32 over 256 rows, FP64 across
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            acc64[i][j][r] += (double)accc[i][j][r];
-                            accc[i][j][r] = 0.f;
-                        }
-            }
+        while (true) {
+            if (body(0)) break;
+            if (body(1)) break;
+            if (body(2)) break;
         }
         wait_vm<0>();
     }
@@ -322,11 +366,11 @@ __global__ __launch_bounds__(256, 1) void syrk_bf16_kernel(const __bf16* __restr
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 out[(int64_t)(ti * 128 + wm + 16 * i + 4 * lk + r) * Npad + tj * 128 + wn + 16 * j + li] =
-                    acc64[i][j][r] + (double)accc[i][j][r];
+                    acc[i][j][r] + (double)corr[i][j][r];
 }
 
 __global__ void kreduce_bf_kernel(const double* part, int n_split, int Npad, int N, double* K) {
@@ -389,7 +433,7 @@ hipError_t x_transform_bf16(const void* B, int prec, int N, int n_aux, int n_occ
     const int64_t n_items = (int64_t)((nt + 1) / 2) * n_aux;
     const unsigned grid = (unsigned)std::min<int64_t>(n_items, device_cus());
     const __bf16* b = (const __bf16*)B;
-#define XB(NS, M) case M: x_bf16_kernel<NS, M><<<grid, 256, 0, st>>>(b, nt, n_aux, ct, Npad, n_occ, xb, R); break;
+#define XB(NS, M) case M: x_bf16_kernel<NS, M><<<grid, 512, 0, st>>>(b, nt, n_aux, ct, Npad, n_occ, xb, R); break;
     if (ns == 3) {
         switch (mt) { XB(3, 1) XB(3, 2) XB(3, 3) XB(3, 4) XB(3, 5) XB(3, 6) XB(3, 7) XB(3, 8) default: return hipErrorInvalidValue; }
     } else {
@@ -407,8 +451,8 @@ hipError_t k_syrk_bf16(const void* Xb, int prec, int N, int n_aux, int n_occ, do
     const int t128 = Npad / 128, nlow = t128 * (t128 + 1) / 2;
     const int64_t chunk = ((R + n_split - 1) / n_split + 31) / 32 * 32;
     const int used = (int)((R + chunk - 1) / chunk);
-    if (ns == 3) syrk_bf16_kernel<3><<<nlow * used, 256, 0, st>>>(xb, Npad, R, chunk, t128, part);
-    else syrk_bf16_kernel<2><<<nlow * used, 256, 0, st>>>(xb, Npad, R, chunk, t128, part);
+    if (ns == 3) syrk_bf16_kernel<3><<<nlow * used, 512, 0, st>>>(xb, Npad, R, chunk, t128, part);
+    else syrk_bf16_kernel<2><<<nlow * used, 512, 0, st>>>(xb, Npad, R, chunk, t128, part);
     RI_TRY(hipGetLastError());
     dim3 g2((N + 255) / 256, N);
     kreduce_bf_kernel<<<g2, 256, 0, st>>>(part, used, Npad, N, K);

@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 MFMA
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 COUNTERS = os.path.join(ROOT, "profiles", "x_kernel_n1000_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2407_19614_amd", "csrc", "fock.hip")
 
@@ -152,8 +153,7 @@ def main():
         out["scf"]["abs_dE_vs_oracle"] = abs(res["E_total"] - ref["E_total"])
         if not args.no_pipeline:
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
-    if not args.quick:
-        out["precision"] = precision_leg(s, C, res, args, P, torch, np)
+    out["precision"] = precision_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
     if args.batched:
         out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec)
     if args.learned:
@@ -174,11 +174,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def precision_leg(s, C, res64, args, P, torch, np):
+def precision_leg(s, C, res64, args, P, torch, np, ms_fp64):
     """Reduced-precision exchange contractions at the same workload: Fock
     builds/s and speedup over FP64, and each SCF energy's difference from the
-    FP64 one.  FP32: FP32 MFMA; BF16X3 / BF16X6: two- and three-part BF16
-    splits with 3 and 6 products on BF16 MFMA.  gamma and J stay FP64."""
+    FP64 one (skipped when res64 is None).  FP32: FP32 MFMA; BF16X3 / BF16X6:
+    two- and three-part BF16 splits with 3 and 6 products on BF16 MFMA.
+    gamma and J stay FP64.  The X roofline counts the MFMA work actually
+    issued: full square tiles of the padded size times the product count."""
     dev = C.device
     N, na = s.N, s.n_aux
     out = {}
@@ -203,12 +205,25 @@ def precision_leg(s, C, res64, args, P, torch, np):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
         ph = np.array([[e4[i].elapsed_time(e4[i + 1]) for i in range(3)] for e4 in ev]).mean(0)
-        r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
         out[name] = {"builds_per_s": round(1.0 / dt, 3), "ms_per_build": round(dt * 1e3, 3),
+                     "speedup_vs_fp64": round(ms_fp64 / (dt * 1e3), 3),
                      "phases_ms": {"gamma_J": round(float(ph[0]), 3), "X": round(float(ph[1]), 3),
-                                   "K_syrk": round(float(ph[2]), 3)},
-                     "scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
-                     "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])}
+                                   "K_syrk": round(float(ph[2]), 3)}}
+        if prec in (P.BF16X3, P.BF16X6):
+            ns, nprod = (2, 3) if prec == P.BF16X3 else (3, 6)
+            npad = 64 * ((N + 63) // 64)
+            w = 16 * ((s.n_occ + 15) // 16)
+            fl = 2.0 * na * npad * npad * w * nprod          # MFMA work issued
+            by = 2.0 * ns * na * npad * npad                  # B parts read (full square tiles)
+            tx = ph[1] * 1e-3
+            out[name]["x_roofline"] = {"mfma_tflops": round(fl / tx / 1e12, 1),
+                                       "mfma_frac": round(fl / tx / 1e12 / PEAK_BF16_TFLOPS, 4),
+                                       "b_read_GBs": round(by / tx / 1e9, 1),
+                                       "hbm_frac": round(by / tx / 1e9 / PEAK_HBM_GBS, 4)}
+        if res64 is not None:
+            r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
+            out[name].update({"scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
+                              "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
         del pr, J, K, g
         torch.cuda.empty_cache()
     return out

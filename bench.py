@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--batched-n", type=int, default=256, help="molecules in the batched workload")
     ap.add_argument("--batched-prec", default="fp32", choices=["fp32", "fp64"],
                     help="exchange precision of the batched workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workload with the default launch shapes instead of autotuned ones")
     ap.add_argument("--quick", action="store_true",
                     help="profiling mode: seeded random occupied orbitals instead of the converged SCF "
                          "(same shapes and kernels), no pipeline, no CPU baseline")
@@ -155,7 +157,7 @@ def main():
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
     out["precision"] = precision_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
     if args.batched:
-        out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec)
+        out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec, autotune=not args.no_autotune)
     if args.learned:
         out["learned_start"] = learned_leg(args.learned_steps)
     if args.calib:
@@ -224,12 +226,11 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64):
             r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
             out[name].update({"scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
                               "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
-        del pr, J, K, g
-        torch.cuda.empty_cache()
+        del pr, J, K, g   # blocks stay in torch's cache for the next leg (see batched_leg)
     return out
 
 
-def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32"):
+def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True):
     """256 independent He-like clusters with n_centres ~ U{10..60} (N = 10 per
     centre, N_aux = 30 per centre, n_occ = n_centres), seeds 4001...: pairs, 3c
     integrals and FP32 B per molecule, then one lockstep SCF per wave of
@@ -242,11 +243,9 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32"):
     import torch
     import synth
     import paper_2407_19614_amd as P
-    from paper_2407_19614_amd.binding import energy_batched
+    from paper_2407_19614_amd.binding import batch_autotune, energy_batched
     systems = synth.batched_systems(n_mol)
     prec = P.FP32 if prec_name == "fp32" else P.FP64
-    if prec == P.FP64:
-        wave = min(wave, 96)                      # FP64 packed B is twice the size
     tol = dict(tol_E=1e-7, tol_err=1e-5) if prec == P.FP32 else dict(tol_E=1e-10, tol_err=1e-8)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     E = np.full(len(systems), np.nan)
@@ -254,7 +253,8 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32"):
     conv = np.zeros(len(systems), dtype=bool)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    t_setup = t_scf = 0.0
+    t_setup = t_scf = t_tune = 0.0
+    tune = None
     for w0 in range(0, len(systems), wave):
         ts = time.perf_counter()
         probs = []
@@ -265,15 +265,21 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32"):
             probs.append(pr)
         torch.cuda.synchronize()
         t_setup += time.perf_counter() - ts
+        if tune is None and autotune:
+            # launch shapes per size bucket, timed on the first wave's molecules and kept for the rest
+            ts = time.perf_counter()
+            tune = batch_autotune(probs, prec)
+            t_tune = time.perf_counter() - ts
         ts = time.perf_counter()
-        res, _, _ = energy_batched(probs, prec, use_graph=True, raise_on_noconv=False, **tol)
+        res, _, _ = energy_batched(probs, prec, use_graph=True, raise_on_noconv=False, tuning=tune, **tol)
         torch.cuda.synchronize()
         t_scf += time.perf_counter() - ts
         for k, r in enumerate(res):
             E[w0 + k], iters[w0 + k], conv[w0 + k] = r["E_total"], r["n_iter"], r["converged"]
         log(f"batched wave {w0}: setup {t_setup:.2f}s scf {t_scf:.2f}s")
+        # the next wave reuses these blocks through torch's caching allocator: returning
+        # them to the driver makes later allocations wait for freed memory to be reclaimed
         del probs, res
-        torch.cuda.empty_cache()
     wall = time.perf_counter() - t0
     # plain FP64 single-molecule path on the first molecules
     torch.cuda.synchronize()
@@ -291,7 +297,8 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32"):
     out = {"workload": f"{len(systems)} He-like clusters, 10-60 centres (N 100-600, N_aux 300-1800), "
                        f"{prec_name.upper()} exchange",
            "scf_per_s": round(len(systems) / wall, 3), "wall_s": round(wall, 2),
-           "setup_s": round(t_setup, 2), "batched_scf_s": round(t_scf, 2),
+           "setup_s": round(t_setup, 2), "autotune_s": round(t_tune, 3), "batched_scf_s": round(t_scf, 2),
+           "wave": wave, "tuning": tune.as_dict() if tune is not None else None,
            "all_converged": bool(conv.all()), "mean_iters": round(float(iters.mean()), 2),
            "fp64_single_path_scf_per_s": round(baseline_n / t_base, 3),
            "fp64_single_path_sample": f"first {baseline_n} molecules",

@@ -288,17 +288,50 @@ typedef struct {
  * prec RI_FP64 or RI_FP32, n_occ <= 64 for every molecule. */
 size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec);
 
+/* Launch shapes of the batched SCF per size bucket.  Molecule m belongs to
+ * bucket b = ceil(N_m / 128) - 1, clamped to n_buckets - 1.
+ *   gemm_tile[b]   64 or 128: tile edge of the grouped FP64 GEMMs whose three
+ *                  dimensions are N (orthogonalisation, purification squares,
+ *                  F D and F D S products).
+ *   syrk_split[b]  1 .. 8: pieces the exchange SYRK reduction index
+ *                  (n_aux * n_occ) is split into.
+ *   gemm_ms[b], syrk_ms[b]  (filled by ri_batch_autotune) the measured time
+ *                  of the chosen shape on the bucket's molecules, in ms.
+ * Host memory, owned by the caller. */
+#define RI_TUNE_BUCKETS 8
+typedef struct {
+    int32_t n_buckets;
+    int32_t gemm_tile[RI_TUNE_BUCKETS];
+    int32_t syrk_split[RI_TUNE_BUCKETS];
+    float gemm_ms[RI_TUNE_BUCKETS];
+    float syrk_ms[RI_TUNE_BUCKETS];
+} ri_batch_tuning;
+
+/* ri_batch_autotune - choose ri_batch_tuning for a batch by timing each
+ * candidate shape (GEMM tile 64 / 128 on the purification square X X; SYRK
+ * split 8, 4, 2, 1 including its reduction, stopping at the first candidate
+ * 1.5x slower than the best) with HIP events on the batch's own molecules of
+ * each bucket, and keeping the fastest.  Takes the same
+ * arguments and workspace as ri_energy_batched (sized by
+ * ri_energy_batched_workspace) and leaves no result in it; C_occ and F of
+ * mol are not touched.  Buckets with no molecule get the defaults (tile 64,
+ * split from the reduction length).  Synchronises the stream. */
+int32_t ri_batch_autotune(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
+                          ri_batch_tuning* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ri_energy_batched - closed-shell RI-HF SCF (as ri_energy, core-Hamiltonian
  * start) for n_mol molecules at once.
  * Paper: Roothaan equations and Algorithm 1 SCF loop, applied per molecule.
  *   sys, mol   host arrays [n_mol] (the pointers inside are device pointers).
  *   use_graph  1: capture one iteration as a HIP graph and replay it.
+ *   tuning     launch shapes per size bucket (from ri_batch_autotune), or
+ *              NULL for the defaults; RI_E_ARG if a value is out of range.
  *   res        host [n_mol] (out).
  * Returns RI_E_NO_CONV if any molecule did not converge (all results filled).
  * Synchronises the stream once per iteration. */
 int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
-                          const ri_scf_opts* opts, int32_t use_graph, ri_scf_result* res,
-                          void* ws, size_t ws_bytes, hipStream_t stream);
+                          const ri_scf_opts* opts, int32_t use_graph, const ri_batch_tuning* tuning,
+                          ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Operation codes for ri_workspace_bytes.  For RI_OP_MLP, n_pairs is the
  * number of feature rows per call. */

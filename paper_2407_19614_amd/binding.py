@@ -67,6 +67,22 @@ class BatchMol(ctypes.Structure):
                 ("C_occ", c_void_p), ("F", c_void_p)]
 
 
+TUNE_BUCKETS = 8
+
+
+class BatchTuning(ctypes.Structure):
+    """Launch shapes of the batched SCF per size bucket (bucket b: N in
+    (128 b, 128 (b + 1)]); see ri_batch_autotune."""
+    _fields_ = [("n_buckets", c_int32), ("gemm_tile", c_int32 * TUNE_BUCKETS),
+                ("syrk_split", c_int32 * TUNE_BUCKETS), ("gemm_ms", ctypes.c_float * TUNE_BUCKETS),
+                ("syrk_ms", ctypes.c_float * TUNE_BUCKETS)]
+
+    def as_dict(self):
+        n = self.n_buckets
+        return {"n_buckets": n, "gemm_tile": list(self.gemm_tile[:n]), "syrk_split": list(self.syrk_split[:n]),
+                "gemm_ms": [round(x, 4) for x in self.gemm_ms[:n]], "syrk_ms": [round(x, 4) for x in self.syrk_ms[:n]]}
+
+
 _LIB = None
 _SIGS = {
     "ri_version": (c_char_p, []),
@@ -93,8 +109,9 @@ _SIGS = {
     "ri_density_to_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "ri_density_from_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "ri_energy_batched_workspace": (c_size_t, [c_int32, c_void_p, c_void_p, c_int32]),
+    "ri_batch_autotune": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_energy_batched": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, POINTER(SCFOpts), c_int32, c_void_p,
-                                    c_void_p, c_size_t, c_void_p]),
+                                    c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
@@ -371,10 +388,7 @@ def unpack_params(v):
             "w3": v[OFF_W3:OFF_B3], "b3": v[OFF_B3:OFF_B3 + 1]}
 
 
-def energy_batched(problems, prec=FP64, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, use_graph=True,
-                   want_fock=False, raise_on_noconv=True):
-    """Lockstep SCF for a list of RIProblem objects (each after build_3c and
-    metric_factor in precision `prec`).  Returns (results, C_occ list, F list)."""
+def _batch_args(problems, want_fock=False):
     import torch
     n = len(problems)
     dev = problems[0].device
@@ -384,15 +398,48 @@ def energy_batched(problems, prec=FP64, max_iter=100, diis_n=6, tol_E=1e-10, tol
     mols = (BatchMol * n)(*[BatchMol(p.B.data_ptr(), p.T.data_ptr(), p.pairs.data_ptr(), p.n_pairs,
                                      Cs[i].data_ptr(), None if Fs[i] is None else Fs[i].data_ptr())
                             for i, p in enumerate(problems)])
+    return n, dev, sysarr, mols, Cs, Fs
+
+
+def _batch_ws(n, sysarr, mols, prec, dev):
+    import torch
     nb = int(lib().ri_energy_batched_workspace(n, ctypes.byref(sysarr), ctypes.byref(mols), prec))
     if nb == 0:
         raise RIError(7, "ri_energy_batched_workspace")
-    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    return torch.empty(nb, dtype=torch.uint8, device=dev), nb
+
+
+def batch_autotune(problems, prec=FP64):
+    """Times the candidate launch shapes of the batched SCF on these problems
+    (each after build_3c and metric_factor in `prec`) and returns the chosen
+    BatchTuning (pass it to energy_batched)."""
+    import torch
+    n, dev, sysarr, mols, _, _ = _batch_args(problems)
+    ws, nb = _batch_ws(n, sysarr, mols, prec, dev)
+    out = BatchTuning()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    code = lib().ri_batch_autotune(n, ctypes.byref(sysarr), ctypes.byref(mols), prec, ctypes.byref(out), _ptr(ws),
+                                   nb, stream)
+    _check(code, "ri_batch_autotune")
+    del ws
+    return out
+
+
+def energy_batched(problems, prec=FP64, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, use_graph=True,
+                   want_fock=False, raise_on_noconv=True, tuning=None):
+    """Lockstep SCF for a list of RIProblem objects (each after build_3c and
+    metric_factor in precision `prec`), with launch shapes from `tuning`
+    (a BatchTuning, or None for the defaults).  Returns (results, C_occ
+    list, F list)."""
+    import torch
+    n, dev, sysarr, mols, Cs, Fs = _batch_args(problems, want_fock)
+    ws, nb = _batch_ws(n, sysarr, mols, prec, dev)
     res = (SCFResult * n)()
     opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, 0)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     code = lib().ri_energy_batched(n, ctypes.byref(sysarr), ctypes.byref(mols), prec, ctypes.byref(opts),
-                                   1 if use_graph else 0, ctypes.byref(res), _ptr(ws), nb, stream)
+                                   1 if use_graph else 0, None if tuning is None else ctypes.byref(tuning),
+                                   ctypes.byref(res), _ptr(ws), nb, stream)
     if code not in (0, 3) or (code == 3 and raise_on_noconv):
         _check(code, "ri_energy_batched")
     del ws

@@ -309,7 +309,8 @@ struct Plan {
     int n_mol = 0, prec = 0, tc2_iters = 48;
     MolDesc* d = nullptr;
     Table n2, rows, pairs, aux, syrk, tail, x[9];
-    struct G { ri::GemmDesc* d = nullptr; Table t; bool ta = false, tb = false; };
+    // members on 64 x 64 tiles in t, on 128 x 128 tiles in t128
+    struct G { ri::GemmDesc* d = nullptr; Table t, t128; bool ta = false, tb = false; };
     G g_lfx, g_t2, g_x2, g_y, g_mo, g_cp, g_c, g_d, g_fd, g_fds;
     int* n_active = nullptr;
 };
@@ -323,7 +324,10 @@ struct Plan {
 hipError_t occupied_space_b(const Plan& p, hipStream_t st) {
     const MolDesc* d = p.d;
     const int nm = p.n_mol;
-    auto gg = [&](const Plan::G& g) { return ri::gemm_grouped(g.ta, g.tb, g.d, g.t.prefix, nm, g.t.total, st); };
+    auto gg = [&](const Plan::G& g) {
+        hipError_t e = ri::gemm_grouped(g.ta, g.tb, g.d, g.t.prefix, nm, g.t.total, st, 64);
+        return e == hipSuccess ? ri::gemm_grouped(g.ta, g.tb, g.d, g.t128.prefix, nm, g.t128.total, st, 128) : e;
+    };
     HC(gg(p.g_lfx));
     HC(gg(p.g_t2));
     gersh_b<<<nm, 256, 0, st>>>(d, nm);
@@ -346,7 +350,10 @@ hipError_t occupied_space_b(const Plan& p, hipStream_t st) {
 hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
     const MolDesc* d = p.d;
     const int nm = p.n_mol;
-    auto gg = [&](const Plan::G& g) { return ri::gemm_grouped(g.ta, g.tb, g.d, g.t.prefix, nm, g.t.total, st); };
+    auto gg = [&](const Plan::G& g) {
+        hipError_t e = ri::gemm_grouped(g.ta, g.tb, g.d, g.t.prefix, nm, g.t.total, st, 64);
+        return e == hipSuccess ? ri::gemm_grouped(g.ta, g.tb, g.d, g.t128.prefix, nm, g.t128.total, st, 128) : e;
+    };
     // Fock build
     HC(ri::zero_tail_b(d, p.tail.prefix, nm, p.tail.total, p.prec, st));
     HC(ri::gamma_j_b(d, nm, p.pairs.prefix, p.pairs.total, p.aux.prefix, p.aux.total, p.n2.prefix, p.n2.total, st));
@@ -395,18 +402,40 @@ int k_split_small(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int6
 // the host copies of the descriptors and tables.
 struct HostPlan {
     std::vector<MolDesc> mols;
-    std::vector<std::vector<int>> prefixes;           // each table's prefix
-    std::vector<std::vector<ri::GemmDesc>> gemms;     // each grouped GEMM's members
+    std::vector<int> tile;                            // GEMM tile edge per molecule
+    std::vector<Table*> tabs;                         // every table, in layout order
+    std::vector<std::vector<int>> prefixes;           // each table's prefix (same order)
+    std::vector<Plan::G*> gs;                         // every grouped GEMM
+    std::vector<std::vector<ri::GemmDesc>> gemms;     // each grouped GEMM's members (same order)
 };
+
+int tune_bucket(int N, int n_buckets) { return std::min((N + 127) / 128, n_buckets) - 1; }
+
+bool tuning_ok(const ri_batch_tuning* t) {
+    if (!t) return true;
+    if (t->n_buckets < 1 || t->n_buckets > RI_TUNE_BUCKETS) return false;
+    for (int b = 0; b < t->n_buckets; ++b)
+        if ((t->gemm_tile[b] != 64 && t->gemm_tile[b] != 128) || t->syrk_split[b] < 1 || t->syrk_split[b] > 8)
+            return false;
+    return true;
+}
+
+// SYRK split of a molecule's reduction length into ks pieces of a multiple of 16 rows
+void set_split(MolDesc& m, int ks) {
+    m.ks = ks;
+    m.chunk = ((m.rows_pad + m.ks - 1) / m.ks + 15) / 16 * 16;
+    m.ks = (int)((m.rows_pad + m.chunk - 1) / m.chunk);
+}
 
 }  // namespace
 
 // The workspace layout shared by the size query and the solver.
 static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec, int diis_n,
-                            Carver& cv, Plan& p, HostPlan& hp) {
+                            const ri_batch_tuning* tune, Carver& cv, Plan& p, HostPlan& hp) {
     p.n_mol = n_mol;
     p.prec = prec;
     hp.mols.assign(n_mol, MolDesc{});
+    hp.tile.assign(n_mol, 64);
     for (int i = 0; i < n_mol; ++i) {
         const ri_system& s = sys[i];
         MolDesc& m = hp.mols[i];
@@ -420,9 +449,13 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         m.mt = (no + 15) / 16;
         const int64_t rows = (int64_t)na * no;
         m.rows_pad = (rows + 15) / 16 * 16;
-        m.ks = k_split_small(rows);
-        m.chunk = ((m.rows_pad + m.ks - 1) / m.ks + 15) / 16 * 16;
-        m.ks = (int)((m.rows_pad + m.chunk - 1) / m.chunk);
+        if (tune) {
+            const int b = tune_bucket(N, tune->n_buckets);
+            set_split(m, tune->syrk_split[b]);
+            hp.tile[i] = tune->gemm_tile[b];
+        } else {
+            set_split(m, k_split_small(rows));
+        }
         m.pairs = mol[i].pairs;
         m.Bc = mol[i].Bc;
         m.B = mol[i].B;
@@ -430,7 +463,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         const int64_t n2 = (int64_t)N * N;
         m.J = cv.take<double>(n2); m.K = cv.take<double>(n2); m.gamma = cv.take<double>(na);
         m.dpair = cv.take<double>(std::max<int64_t>(1, m.n_pairs));
-        m.part = cv.take<double>((int64_t)m.ks * m.npad * m.npad);
+        m.part = cv.take<double>((int64_t)8 * m.npad * m.npad);   // the largest split any tuning may choose
         m.Xt = cv.take<char>((m.rows_pad + 16) * m.npad * (prec == RI_FP64 ? 8 : 4));
         double** mats[] = {&m.S, &m.H, &m.LinvS, &m.F, &m.D, &m.T1, &m.T2, &m.E, &m.Fx, &m.X, &m.X2};
         for (double** q : mats) *q = cv.take<double>(n2);
@@ -454,6 +487,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         for (int i = 0; i < n_mol; ++i) pre[i + 1] = pre[i] + counts[i];
         t.total = pre[n_mol];
         t.prefix = cv.take<int>(n_mol + 1);
+        hp.tabs.push_back(&t);
         hp.prefixes.push_back(pre);
     };
     std::vector<int> c(n_mol);
@@ -478,39 +512,170 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         mk(c, p.x[mt]);
     }
     // grouped GEMMs: member i of each
-    auto mkg = [&](Plan::G& g, bool ta, bool tb, auto fill) {
+    // tunable: the member runs on the molecule's tuned tile (else on 64 x 64)
+    auto mkg = [&](Plan::G& g, bool ta, bool tb, bool tunable, auto fill) {
         g.ta = ta;
         g.tb = tb;
         std::vector<ri::GemmDesc> v(n_mol);
-        std::vector<int> cnt(n_mol);
+        std::vector<int> c64(n_mol), c128(n_mol);
         for (int i = 0; i < n_mol; ++i) {
             fill(hp.mols[i], v[i]);
             v[i].active = hp.mols[i].state;   // state[0]
-            cnt[i] = ((v[i].M + 63) / 64) * ((v[i].N + 63) / 64);
+            const bool big = tunable && hp.tile[i] == 128;
+            c64[i] = big ? 0 : ((v[i].M + 63) / 64) * ((v[i].N + 63) / 64);
+            c128[i] = big ? ((v[i].M + 127) / 128) * ((v[i].N + 127) / 128) : 0;
         }
         g.d = cv.take<ri::GemmDesc>(n_mol);
+        hp.gs.push_back(&g);
         hp.gemms.push_back(v);
-        mk(cnt, g.t);
+        mk(c64, g.t);
+        mk(c128, g.t128);
     };
     auto set = [](ri::GemmDesc& g, int M, int N, int K, double al, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double* C, int64_t ldc, int tri) {
         g.M = M; g.N = N; g.K = K; g.tri = tri; g.alpha = al; g.beta = 0.0;
         g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
     };
-    mkg(p.g_lfx, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.LinvS, m.N, m.Fx, m.N, m.T1, m.N, 1); });
-    mkg(p.g_t2, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.LinvS, m.N, m.T2, m.N, 0); });
-    mkg(p.g_x2, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.X, m.N, m.X, m.N, m.X2, m.N, 0); });
-    mkg(p.g_y, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.X, m.N, m.Cp, m.n_occ, m.Y, m.n_occ, 0); });
-    mkg(p.g_mo, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.n_occ, m.n_occ, m.N, 1.0, m.Y, m.n_occ, m.Y, m.n_occ, m.Mo, m.n_occ, 0); });
-    mkg(p.g_cp, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.n_occ, 1.0, m.Y, m.n_occ, m.LinvM, 64, m.Cp, m.n_occ, 0); });
-    mkg(p.g_c, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.LinvS, m.N, m.Cp, m.n_occ, m.C, m.n_occ, 2); });
-    mkg(p.g_d, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.n_occ, 2.0, m.C, m.n_occ, m.C, m.n_occ, m.D, m.N, 0); });
-    mkg(p.g_fd, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.F, m.N, m.D, m.N, m.T1, m.N, 0); });
-    mkg(p.g_fds, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.S, m.N, m.T2, m.N, 0); });
+    mkg(p.g_lfx, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.LinvS, m.N, m.Fx, m.N, m.T1, m.N, 1); });
+    mkg(p.g_t2, false, true, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.LinvS, m.N, m.T2, m.N, 0); });
+    mkg(p.g_x2, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.X, m.N, m.X, m.N, m.X2, m.N, 0); });
+    mkg(p.g_y, false, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.X, m.N, m.Cp, m.n_occ, m.Y, m.n_occ, 0); });
+    mkg(p.g_mo, true, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.n_occ, m.n_occ, m.N, 1.0, m.Y, m.n_occ, m.Y, m.n_occ, m.Mo, m.n_occ, 0); });
+    mkg(p.g_cp, false, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.n_occ, 1.0, m.Y, m.n_occ, m.LinvM, 64, m.Cp, m.n_occ, 0); });
+    mkg(p.g_c, true, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.LinvS, m.N, m.Cp, m.n_occ, m.C, m.n_occ, 2); });
+    mkg(p.g_d, false, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.n_occ, 2.0, m.C, m.n_occ, m.C, m.n_occ, m.D, m.N, 0); });
+    mkg(p.g_fd, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.F, m.N, m.D, m.N, m.T1, m.N, 0); });
+    mkg(p.g_fds, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.S, m.N, m.T2, m.N, 0); });
     p.d = cv.take<MolDesc>(n_mol);
     p.n_active = cv.take<int>(4);
     return RI_OK;
 }
+
+namespace {
+
+#define HIPR(x)                                                          \
+    do {                                                                 \
+        hipError_t _e = (x);                                             \
+        if (_e != hipSuccess) { ri::set_hip_error(hipGetErrorString(_e)); return RI_E_HIP; } \
+    } while (0)
+
+int32_t check_batch(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec) {
+    if (n_mol <= 0 || !sys || !mol) return RI_E_ARG;
+    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    for (int i = 0; i < n_mol; ++i) {
+        const ri_system& s = sys[i];
+        if (s.n_centres <= 0 || s.n_fn <= 0 || s.n_aux <= 0 || s.n_occ <= 0 || !s.xyz || !s.Z || !s.fn_centre ||
+            !s.fn_exp || !s.aux_centre || !s.aux_exp || !mol[i].B || !mol[i].C_occ || mol[i].n_pairs < 0 ||
+            (mol[i].n_pairs > 0 && (!mol[i].Bc || !mol[i].pairs)))
+            return RI_E_ARG;
+    }
+    return RI_OK;
+}
+
+int32_t upload_plan(const Plan& p, const HostPlan& hp, hipStream_t st) {
+    const int n_mol = p.n_mol;
+    HIPR(hipMemcpyAsync(p.d, hp.mols.data(), sizeof(MolDesc) * n_mol, hipMemcpyHostToDevice, st));
+    for (size_t k = 0; k < hp.tabs.size(); ++k)
+        HIPR(hipMemcpyAsync(hp.tabs[k]->prefix, hp.prefixes[k].data(), sizeof(int) * (n_mol + 1),
+                            hipMemcpyHostToDevice, st));
+    for (size_t k = 0; k < hp.gs.size(); ++k)
+        HIPR(hipMemcpyAsync(hp.gs[k]->d, hp.gemms[k].data(), sizeof(ri::GemmDesc) * n_mol, hipMemcpyHostToDevice,
+                            st));
+    HIPR(hipStreamSynchronize(st));   // host vectors are read by the copies above
+    return RI_OK;
+}
+
+// Mean time in ms of `reps` launches of fn after one untimed launch.
+template <class F>
+int32_t time_ms(F fn, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, float* ms) {
+    HIPR(fn());
+    HIPR(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) HIPR(fn());
+    HIPR(hipEventRecord(e1, st));
+    HIPR(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPR(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / reps;
+    return RI_OK;
+}
+
+int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
+                      ri_batch_tuning* out, void* ws, size_t ws_bytes, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    Carver cv{(char*)ws, ws_bytes};
+    Plan p;
+    HostPlan hp;
+    int32_t rc = batch_layout(n_mol, sys, mol, prec, 8, nullptr, cv, p, hp);
+    if (rc != RI_OK) return rc;
+    if (cv.off > ws_bytes) return RI_E_WORKSPACE;
+    rc = upload_plan(p, hp, st);
+    if (rc != RI_OK) return rc;
+    // every molecule active; operands zeroed (the timings do not depend on values)
+    state_init_b<<<n_mol, 256, 0, st>>>(p.d, n_mol);
+    HIPR(hipGetLastError());
+    for (const MolDesc& m : hp.mols) {
+        HIPR(ri::fill(m.X, 0.0, (int64_t)m.N * m.N, st));
+        const int64_t xt = (m.rows_pad + 16) * m.npad * (prec == RI_FP64 ? 8 : 4);
+        HIPR(ri::fill((double*)m.Xt, 0.0, xt / 8, st));
+    }
+    std::memset(out, 0, sizeof(*out));
+    int nb = 1;
+    for (const MolDesc& m : hp.mols) nb = std::max(nb, tune_bucket(m.N, RI_TUNE_BUCKETS) + 1);
+    out->n_buckets = nb;
+    Plan::G& gx = p.g_x2;
+    for (int b = 0; b < nb; ++b) {
+        std::vector<int> members;
+        for (int i = 0; i < n_mol; ++i)
+            if (tune_bucket(hp.mols[i].N, RI_TUNE_BUCKETS) == b) members.push_back(i);
+        out->gemm_tile[b] = 64;
+        out->syrk_split[b] = 1;
+        if (members.empty()) continue;
+        // GEMM tile: the purification square X X of the bucket's molecules
+        float best = 1e30f;
+        for (int tile : {64, 128}) {
+            std::vector<int> pre(n_mol + 1, 0);
+            for (int i = 0; i < n_mol; ++i) {
+                const int M = hp.mols[i].N;
+                const int t = tile == 64 ? ((M + 63) / 64) * ((M + 63) / 64) : ((M + 127) / 128) * ((M + 127) / 128);
+                pre[i + 1] = pre[i] + (tune_bucket(M, RI_TUNE_BUCKETS) == b ? t : 0);
+            }
+            HIPR(hipMemcpyAsync(gx.t.prefix, pre.data(), sizeof(int) * (n_mol + 1), hipMemcpyHostToDevice, st));
+            float ms = 0.f;
+            rc = time_ms([&] { return ri::gemm_grouped(gx.ta, gx.tb, gx.d, gx.t.prefix, n_mol, pre[n_mol], st, tile); },
+                         st, e0, e1, 2, &ms);
+            if (rc != RI_OK) return rc;
+            if (ms < best) { best = ms; out->gemm_tile[b] = tile; out->gemm_ms[b] = ms; }
+        }
+        // SYRK split: SYRK partials and their reduction for the bucket's molecules;
+        // candidates from the widest down, stopping once one is 1.5x the best
+        best = 1e30f;
+        for (int ks : {8, 4, 2, 1}) {
+            std::vector<int> ps(n_mol + 1, 0), pr(n_mol + 1, 0);
+            std::vector<MolDesc> mols = hp.mols;
+            for (int i = 0; i < n_mol; ++i) {
+                const bool in = tune_bucket(mols[i].N, RI_TUNE_BUCKETS) == b;
+                if (in) set_split(mols[i], ks);
+                const int t128 = mols[i].npad / 128;
+                ps[i + 1] = ps[i] + (in ? t128 * (t128 + 1) / 2 * mols[i].ks : 0);
+                pr[i + 1] = pr[i] + (in ? mols[i].N : 0);
+            }
+            HIPR(hipMemcpyAsync(p.d, mols.data(), sizeof(MolDesc) * n_mol, hipMemcpyHostToDevice, st));
+            HIPR(hipMemcpyAsync(p.syrk.prefix, ps.data(), sizeof(int) * (n_mol + 1), hipMemcpyHostToDevice, st));
+            HIPR(hipMemcpyAsync(p.rows.prefix, pr.data(), sizeof(int) * (n_mol + 1), hipMemcpyHostToDevice, st));
+            float ms = 0.f;
+            rc = time_ms([&] {
+                hipError_t e = ri::syrk_b(p.d, p.syrk.prefix, n_mol, ps[n_mol], prec, st);
+                return e == hipSuccess ? ri::kreduce_b(p.d, p.rows.prefix, n_mol, pr[n_mol], st) : e;
+            }, st, e0, e1, 2, &ms);
+            if (rc != RI_OK) return rc;   // the host vectors stay alive until the timing synchronised
+            if (ms < best) { best = ms; out->syrk_split[b] = ks; out->syrk_ms[b] = ms; }
+            if (ms > 1.5f * best) break;
+        }
+    }
+    HIPR(hipStreamSynchronize(st));
+    return RI_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -519,29 +684,42 @@ size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri
     Carver cv{nullptr, 0};
     Plan p;
     HostPlan hp;
-    if (batch_layout(n_mol, sys, mol, prec, 8, cv, p, hp) != RI_OK) return 0;
+    if (batch_layout(n_mol, sys, mol, prec, 8, nullptr, cv, p, hp) != RI_OK) return 0;
     return cv.off + 256;
 }
 
+int32_t ri_batch_autotune(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
+                          ri_batch_tuning* out, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!out || !ws) return RI_E_ARG;
+    int32_t rc = check_batch(n_mol, sys, mol, prec);
+    if (rc != RI_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPR(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        ri::set_hip_error("hipEventCreate failed");
+        return RI_E_HIP;
+    }
+    rc = autotune_impl(n_mol, sys, mol, prec, out, ws, ws_bytes, st, e0, e1);
+    if (rc == RI_E_HIP) hipStreamSynchronize(st);   // let queued copies read their host sources
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
 int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
-                          const ri_scf_opts* opts, int32_t use_graph, ri_scf_result* res, void* ws, size_t ws_bytes,
-                          hipStream_t st) {
-    if (n_mol <= 0 || !sys || !mol || !opts || !res || !ws) return RI_E_ARG;
-    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+                          const ri_scf_opts* opts, int32_t use_graph, const ri_batch_tuning* tuning,
+                          ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!opts || !res || !ws || !tuning_ok(tuning)) return RI_E_ARG;
+    int32_t rc = check_batch(n_mol, sys, mol, prec);
+    if (rc != RI_OK) return rc;
     if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0) ||
         opts->guess_kind != 0)
         return RI_E_ARG;
-    for (int i = 0; i < n_mol; ++i) {
-        const ri_system& s = sys[i];
-        if (s.n_centres <= 0 || s.n_fn <= 0 || s.n_aux <= 0 || s.n_occ <= 0 || !s.xyz || !s.Z || !s.fn_centre ||
-            !s.fn_exp || !s.aux_centre || !s.aux_exp || !mol[i].B || !mol[i].C_occ || mol[i].n_pairs < 0 ||
-            (mol[i].n_pairs > 0 && (!mol[i].Bc || !mol[i].pairs)))
-            return RI_E_ARG;
-    }
     Carver cv{(char*)ws, ws_bytes};
     Plan p;
     HostPlan hp;
-    int32_t rc = batch_layout(n_mol, sys, mol, prec, 8, cv, p, hp);
+    rc = batch_layout(n_mol, sys, mol, prec, 8, tuning, cv, p, hp);
     if (rc != RI_OK) return rc;
     if (cv.off > ws_bytes) return RI_E_WORKSPACE;
     for (auto& m : hp.mols) {
@@ -549,26 +727,8 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
         m.tol_err = opts->tol_err;
         m.diis_n = opts->diis_n;
     }
-#define HIPR(x)                                                          \
-    do {                                                                 \
-        hipError_t _e = (x);                                             \
-        if (_e != hipSuccess) { ri::set_hip_error(hipGetErrorString(_e)); return RI_E_HIP; } \
-    } while (0)
-    // upload descriptors and tables
-    HIPR(hipMemcpyAsync(p.d, hp.mols.data(), sizeof(MolDesc) * n_mol, hipMemcpyHostToDevice, st));
-    {
-        std::vector<Table*> tabs = {&p.n2, &p.rows, &p.pairs, &p.aux, &p.syrk, &p.tail};
-        for (int mt = 1; mt <= 8; ++mt) tabs.push_back(&p.x[mt]);
-        Plan::G* gs[] = {&p.g_lfx, &p.g_t2, &p.g_x2, &p.g_y, &p.g_mo, &p.g_cp, &p.g_c, &p.g_d, &p.g_fd, &p.g_fds};
-        for (auto* g : gs) tabs.push_back(&g->t);
-        for (size_t k = 0; k < tabs.size(); ++k)
-            HIPR(hipMemcpyAsync(tabs[k]->prefix, hp.prefixes[k].data(), sizeof(int) * (n_mol + 1),
-                                hipMemcpyHostToDevice, st));
-        for (size_t k = 0; k < 10; ++k)
-            HIPR(hipMemcpyAsync(gs[k]->d, hp.gemms[k].data(), sizeof(ri::GemmDesc) * n_mol, hipMemcpyHostToDevice,
-                                st));
-        HIPR(hipStreamSynchronize(st));
-    }
+    rc = upload_plan(p, hp, st);
+    if (rc != RI_OK) return rc;
     // per-molecule setup: S, h, E_nn, Cholesky of S and L_S^{-1}
     int* bad = p.n_active + 1;
     HIPR(ri::fill_i32(bad, INT_MAX, 1, st));

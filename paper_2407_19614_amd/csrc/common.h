@@ -87,15 +87,15 @@ __device__ __forceinline__ void potrf_inv_block64(double (*L)[65], int nb, Bad b
             for (int c = j + 1; c <= t; ++c) L[t][c] -= L[t][j] * L[c][j];
         __syncthreads();
     }
-    double x[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) x[i] = 0.0;
+    // column t of L^{-1} by forward substitution; thread t owns column t of X
+    // (kept in LDS: a per-thread array indexed from t would live in scratch)
+    __shared__ double X[64][65];
     for (int i = 0; i < 64; ++i) {
         double s = (i == t) ? 1.0 : 0.0;
-        for (int k = t; k < i; ++k) s -= L[i][k] * x[k];
-        x[i] = (i >= t) ? s / L[i][i] : 0.0;
+        for (int k = t; k < i; ++k) s -= L[i][k] * X[k][t];
+        X[i][t] = (i >= t) ? s / L[i][i] : 0.0;
     }
-    for (int i = 0; i < 64; ++i) store(i, t, x[i]);
+    for (int i = 0; i < 64; ++i) store(i, t, X[i][t]);
 }
 
 // ------------------------------------------------------------ launch helpers

@@ -130,19 +130,10 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const ri::GemmDesc* d
 // 128 x 128 variant: 4 waves in 2 x 2, each owning 64 x 64 of C as 4 x 4 MFMA
 // tiles (64 FP64 accumulators per lane).  Same staging scheme as above.
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
-    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
-    const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
-    int64_t ldc, int64_t sC, int tri, int lowerC) {
-    constexpr int TM = 128, TN = 128, LD = TM + 1;
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
-    const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
-    const int m0 = by * TM, n0 = bx * TN;
-    if (lowerC && n0 > m0 + TM - 1) return;
-    A += (int64_t)bz * sA;
-    B += (int64_t)bz * sB;
-    C += (int64_t)bz * sC;
+__device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                             int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
+                                             double* __restrict__ C, int64_t ldc, int tri, int m0, int n0) {
+    constexpr int TM = 128, LD = TM + 1;
     __shared__ double As[BK][LD];
     __shared__ double Bs[BK][LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -217,6 +208,34 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
                     *c = (beta == 0.0) ? v : v + beta * *c;
                 }
             }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
+    const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sC, int tri, int lowerC) {
+    constexpr int TM = 128, TN = 128;
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
+    const int m0 = by * TM, n0 = bx * TN;
+    if (lowerC && n0 > m0 + TM - 1) return;
+    gemm_tile128<TA, TB>(M, N, K, alpha, A + (int64_t)bz * sA, lda, B + (int64_t)bz * sB, ldb, beta,
+                         C + (int64_t)bz * sC, ldc, tri, m0, n0);
+}
+
+// Grouped GEMM on 128 x 128 tiles: problem g owns tiles prefix[g] ..
+// prefix[g+1]-1 (row-major over its tiles); inactive problems are skipped.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm_grouped128_kernel(const ri::GemmDesc* d, const int* prefix, int n) {
+    int g, loc;
+    ri::decode_item(prefix, n, blockIdx.x, g, loc);
+    const ri::GemmDesc& p = d[g];
+    if (p.active && !*p.active) return;
+    const int tn = (p.N + 127) / 128;
+    gemm_tile128<TA, TB>(p.M, p.N, p.K, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, p.tri,
+                         (loc / tn) * 128, (loc % tn) * 128);
 }
 
 // Factor one 64x64 diagonal block in place (lower Cholesky) and write the
@@ -415,8 +434,17 @@ hipError_t trsm_lower_inplace(const double* L, int n, int64_t lda, const double*
     return hipSuccess;
 }
 
-hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s) {
+hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s,
+                        int tile) {
     if (total <= 0) return hipSuccess;
+    if (tile == 128) {
+        if (!ta && !tb) gemm_grouped128_kernel<false, false><<<total, 256, 0, s>>>(d, prefix, n);
+        else if (!ta && tb) gemm_grouped128_kernel<false, true><<<total, 256, 0, s>>>(d, prefix, n);
+        else if (ta && !tb) gemm_grouped128_kernel<true, false><<<total, 256, 0, s>>>(d, prefix, n);
+        else gemm_grouped128_kernel<true, true><<<total, 256, 0, s>>>(d, prefix, n);
+        return hipGetLastError();
+    }
+    if (tile != 64) return hipErrorInvalidValue;
     if (!ta && !tb) gemm_grouped_kernel<false, false><<<total, 256, 0, s>>>(d, prefix, n);
     else if (!ta && tb) gemm_grouped_kernel<false, true><<<total, 256, 0, s>>>(d, prefix, n);
     else if (ta && !tb) gemm_grouped_kernel<true, false><<<total, 256, 0, s>>>(d, prefix, n);

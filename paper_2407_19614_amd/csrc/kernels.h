@@ -119,7 +119,9 @@ struct GemmDesc {
     int64_t lda, ldb, ldc;
     const int* active;
 };
-hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s);
+// tile: 64 (64 x 64 tiles) or 128 (128 x 128 tiles); prefix counts tiles of that size.
+hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s,
+                        int tile = 64);
 
 __device__ __forceinline__ void decode_item(const int* prefix, int n_mol, int L, int& mol, int& local) {
     int lo = 0, hi = n_mol;            // prefix[lo] <= L < prefix[hi]

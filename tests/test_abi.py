@@ -64,6 +64,21 @@ def test_bad_arguments_rejected_before_device_work():
     res = Bd.SCFResult()
     assert lib.ri_energy(ctypes.byref(s), None, 0, None, None, 0, ctypes.byref(opts), None, None, None, None,
                          ctypes.byref(res), None, 0, None) == 1
+    # batched: an out-of-range launch shape is rejected before anything else is read
+    sysarr = (Bd.RISystem * 1)(s)
+    mols = (Bd.BatchMol * 1)()
+    ws = ctypes.create_string_buffer(256)
+    opts6 = Bd.SCFOpts(10, 6, 1e-10, 1e-8, 0)
+    res1 = (Bd.SCFResult * 1)()
+    for tile, split, nb in ((96, 2, 1), (64, 0, 1), (128, 9, 1), (64, 2, 0), (64, 2, 9)):
+        t = Bd.BatchTuning()
+        t.n_buckets = nb
+        for b in range(Bd.TUNE_BUCKETS):
+            t.gemm_tile[b], t.syrk_split[b] = tile, split
+        assert lib.ri_energy_batched(1, ctypes.byref(sysarr), ctypes.byref(mols), 0, ctypes.byref(opts6), 0,
+                                     ctypes.byref(t), ctypes.byref(res1), ws, 256, None) == 1
+    assert lib.ri_batch_autotune(1, ctypes.byref(sysarr), ctypes.byref(mols), 0, None, ws, 256, None) == 1
+    assert ctypes.sizeof(Bd.BatchTuning) == 4 + 4 * 8 * 4
 
 
 def test_product_path_has_no_oracle_import():

@@ -58,3 +58,47 @@ def test_batched_fp32_error():
     for s, r in zip(systems, res):
         ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
         assert r["converged"] and abs(r["E_total"] - ref.E) < 1e-6
+
+
+def test_batched_autotune_and_forced_shapes_agree():
+    """Molecules in four size buckets (N = 40, 140, 270, 400): the autotuner's
+    choices are valid, and the SCF energies under the default shapes, the
+    autotuned ones and two forced extremes (128-tiles with split 8, 64-tiles
+    with split 1) agree to 1e-9 Eh."""
+    need_gpu()
+    import paper_2407_19614_amd as P
+    from paper_2407_19614_amd.binding import BatchTuning, batch_autotune, energy_batched
+    print("case: batched autotune, 4 buckets", flush=True)
+    systems = []
+    for k, nc in enumerate([4, 14, 27, 40]):
+        xyz = synth.ball_cluster(nc, 0.01, 2.5, 500 + k)
+        systems.append(synth.make_system(xyz, synth.ORB_BIG, synth.AUX_BIG[::2], tau=1e-12))
+    assert [s.N for s in systems] == [40, 140, 270, 400]
+    probs = []
+    for s in systems:
+        pr = P.RIProblem(s)
+        pr.build_3c()
+        pr.metric_factor(P.FP64)
+        probs.append(pr)
+    tune = batch_autotune(probs, P.FP64)
+    d = tune.as_dict()
+    print("tuning", d, flush=True)
+    assert d["n_buckets"] == 4
+    for b in range(4):
+        assert d["gemm_tile"][b] in (64, 128) and d["syrk_split"][b] in (1, 2, 4, 8)
+        assert d["gemm_ms"][b] > 0 and d["syrk_ms"][b] > 0
+
+    def forced(tile, split):
+        t = BatchTuning()
+        t.n_buckets = 4
+        for b in range(4):
+            t.gemm_tile[b], t.syrk_split[b] = tile, split
+        return t
+
+    kw = dict(tol_E=1e-11, tol_err=1e-9)
+    E0 = [r["E_total"] for r in energy_batched(probs, P.FP64, **kw)[0]]
+    for t in (tune, forced(128, 8), forced(64, 1)):
+        res = energy_batched(probs, P.FP64, tuning=t, **kw)[0]
+        for k, r in enumerate(res):
+            assert r["converged"]
+            assert abs(r["E_total"] - E0[k]) < 1e-9, (k, r["E_total"], E0[k])

@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--batched-n", type=int, default=256, help="molecules in the batched workload")
     ap.add_argument("--batched-prec", default="fp32", choices=["fp32", "fp64"],
                     help="exchange precision of the batched workload")
+    ap.add_argument("--aimd", action="store_true",
+                    help="also run Born-Oppenheimer NVE dynamics of the N=1000 workload (1 fs steps)")
+    ap.add_argument("--aimd-steps", type=int, default=10, help="time steps of that run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched workload with the default launch shapes instead of autotuned ones")
     ap.add_argument("--quick", action="store_true",
@@ -160,6 +163,8 @@ def main():
         out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec, autotune=not args.no_autotune)
     if args.learned:
         out["learned_start"] = learned_leg(args.learned_steps)
+    if args.aimd:
+        out["aimd"] = aimd_leg(args.aimd_steps)
     if args.calib:
         # counter calibration: one kernel that writes 2 GiB (fill) and one that reads 2 GiB (sum)
         src = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
@@ -309,6 +314,31 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True)
         out["max_abs_dE_vs_oracle_subset"] = float(max(abs(E[m["index"]] - m["E"]) for m in ref["subset"]))
         out["oracle_subset_size"] = len(ref["subset"])
     return out
+
+
+def aimd_leg(n_steps, name="n1000"):
+    """Born-Oppenheimer NVE dynamics of the N=1000 workload released at rest
+    from its (non-equilibrium) geometry with 1 fs steps.  Each step: Verlet
+    kick and drift, 3c build, metric factor and B, SCF started from the
+    previous step's orbitals, analytic gradient, closing kick.  Reports
+    steady-state steps/s (steps after the first, whose SCF starts from the
+    core Hamiltonian), ps of simulation per day, SCF iterations per step and
+    the total-energy excursion."""
+    import numpy as np
+    import synth
+    from paper_2407_19614_amd.aimd import FS, NVE
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    s = synth.config_system(name)
+    md = NVE(s, 1.0 * FS)
+    out = md.run(n_steps, log=log)
+    st = np.array(out["step_s"][1:])
+    Et = np.array(out["E_tot"])
+    return {"workload": f"{name}: {s.n_centres} He-like centres (N={s.N}, N_aux={s.n_aux}), at rest, NVE, "
+                        f"1 fs steps, previous-step orbitals as the SCF start",
+            "steps": n_steps, "steps_per_s": round(1.0 / st.mean(), 3), "step_s_mean": round(float(st.mean()), 4),
+            "first_step_s": round(out["step_s"][0], 4), "ps_per_day": round(86400.0 / st.mean() * 1e-3, 1),
+            "scf_iters_first": out["scf_iters"][0], "scf_iters_mean_after": round(float(np.mean(out["scf_iters"][1:])), 2),
+            "E_tot_excursion_Eh": float(np.abs(Et - Et[0]).max()), "E_kin_final_Eh": out["E_kin"][-1]}
 
 
 def learned_leg(n_steps):

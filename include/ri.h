@@ -333,6 +333,21 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
                           const ri_scf_opts* opts, int32_t use_graph, const ri_batch_tuning* tuning,
                           ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ri_md_verlet - one half of a velocity-Verlet step of the nuclei
+ * (Born-Oppenheimer dynamics in the NVE ensemble; paper: Ab Initio Molecular
+ * Dynamics subsection).  With a = -grad / mass (atomic units: bohr, electron
+ * masses, Eh/bohr; dt in atomic time units):
+ *   stage 0: vel += (dt/2) a, then xyz += dt vel   (before the new forces)
+ *   stage 1: vel += (dt/2) a                       (with the new forces)
+ *   mass [n_atoms], grad/xyz/vel [n_atoms][3]: device FP64.  xyz and vel are
+ *   updated in place.  RI_E_ARG if dt <= 0 or stage is not 0 or 1. */
+int32_t ri_md_verlet(int32_t n_atoms, double dt, const double* mass, const double* grad, double* xyz,
+                     double* vel, int32_t stage, hipStream_t stream);
+
+/* ri_md_kinetic - *ekin (device FP64, out) = sum_a 1/2 mass_a |vel_a|^2,
+ * summed in a fixed order. */
+int32_t ri_md_kinetic(int32_t n_atoms, const double* mass, const double* vel, double* ekin, hipStream_t stream);
+
 /* Operation codes for ri_workspace_bytes.  For RI_OP_MLP, n_pairs is the
  * number of feature rows per call. */
 enum { RI_OP_BUILD_3C = 0, RI_OP_METRIC = 1, RI_OP_FOCK = 2, RI_OP_ENERGY = 3,

@@ -112,6 +112,8 @@ _SIGS = {
     "ri_batch_autotune": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_energy_batched": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, POINTER(SCFOpts), c_int32, c_void_p,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ri_md_verlet": (c_int32, [c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "ri_md_kinetic": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
 }

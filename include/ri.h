@@ -62,6 +62,15 @@ typedef enum {
                      /* part orders add to at most 2 (about FP32 accuracy)    */
 } ri_precision;
 
+/* Flag OR-ed into a precision argument (with RI_FP64 or RI_FP32 only): B is
+ * not resident.  Every call that needs B decompresses the fitted tensor B_c
+ * into packed tiles, RI_COMPRESSED_SLAB auxiliary functions at a time, in its
+ * workspace (the per-iteration decompression of Algorithm 1), and B is passed
+ * as NULL.  Results are identical to the resident form; workspace sizes from
+ * ri_workspace_bytes with the same flag. */
+#define RI_COMPRESSED 0x10
+#define RI_COMPRESSED_SLAB 256
+
 /* Molecular system.  The struct lives in host memory; every array is a
  * device pointer.  Positions in bohr. */
 typedef struct {
@@ -117,7 +126,8 @@ int32_t ri_build_3c(const ri_system* sys, double tau, int32_t* pairs, int64_t ca
  *   T_inout [n_aux][n_pairs] in: (mu nu|P); out: Bc.
  *   L       [n_aux][n_aux] out: lower factor (upper triangle zeroed).
  *   Linv    [n_aux][n_aux] out: L^{-1} (lower).
- *   B       packed B (see above), out; may be NULL to skip packing.
+ *   B       packed B (see above), out; may be NULL to skip packing (as for
+ *           the compressed form, prec | RI_COMPRESSED).
  *   bad_pivot (host, out): -1, or the first auxiliary index whose pivot is
  *           not positive (then RI_E_NOT_PD is returned).
  * Synchronises `stream` once (pivot check). */
@@ -131,7 +141,9 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
  * eq. k_ri_2 and eq. tp (X^P = B^P C_occ, K = sum_P X^P X^P^T), Algorithm 1
  * Fock-build loop, symmetric GEMM for the lower triangle of K (Symmetry
  * utilisation section).
- *   B       packed B in precision `prec` (from ri_metric_factor).
+ *   B       packed B in precision `prec` (from ri_metric_factor), or NULL
+ *           with prec | RI_COMPRESSED: X^P is then formed slab by slab from
+ *           Bc (Algorithm 1's per-iteration decompression).
  *   Bc      [n_aux][n_pairs] FP64 fitted tensor on compressed pairs, and
  *   pairs   [n_pairs][2]: gamma and J are formed from these in FP64 for
  *           every precision.
@@ -179,6 +191,7 @@ typedef struct {
  * The occupied space of each extrapolated Fock matrix (the n_occ lowest
  * orbitals of F C = S C eps) is obtained as the spectral projector by
  * trace-correcting purification, all on the GPU.
+ *   B, prec   as for ri_fock_jk (B may be NULL with prec | RI_COMPRESSED).
  *   guess     device C_occ [N][n_occ] (guess_kind 1) or D [N][N] (guess_kind 2),
  *             else NULL.
  *   C_occ     [N][n_occ] out: orthonormal (C^T S C = 1) occupied orbitals
@@ -201,7 +214,8 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
  *   Y^P = c_P D - 2 C Xi^P C^T,  Z = c c^T - 2 sum_ij Xi_ij Xi_ij^T,
  *   W = (1/2) D F D (= 2 C eps C^T at convergence),
  *   g = sum D h' - sum W S' + sum Y (mu nu|P)' - 1/2 sum Z (P|Q)' + E_nn'.
- *   B, prec, Bc, pairs, Linv as returned by ri_metric_factor.
+ *   B, prec, Bc, pairs, Linv as returned by ri_metric_factor (B may be NULL
+ *            with prec | RI_COMPRESSED; prec RI_FP64 or RI_FP32).
  *   C_occ, F  converged orbitals and Fock matrix from ri_energy.
  *   grad     [n_centres][3] out, Eh/bohr, including nuclear repulsion.
  * Asynchronous. */

@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libri.so")
 
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
+COMPRESSED = 0x10          # flag: B not resident, decompressed per auxiliary slab each call
+COMPRESSED_SLAB = 256
 OP_BUILD_3C, OP_METRIC, OP_FOCK, OP_ENERGY, OP_GRADIENT = range(5)
 STATUS = {0: "RI_OK", 1: "RI_E_ARG", 2: "RI_E_NOT_PD", 3: "RI_E_NO_CONV", 4: "RI_E_WORKSPACE",
           5: "RI_E_CAPACITY", 6: "RI_E_HIP", 7: "RI_E_UNSUPPORTED"}
@@ -170,12 +172,13 @@ class RIProblem:
     tensors on the current HIP device, and calls the five entry points.
     """
 
-    def __init__(self, system, device="cuda", prec=FP64):
+    def __init__(self, system, device="cuda", prec=FP64, compressed=False):
         import torch
         self.torch = torch
         self.system = system
         self.device = torch.device(device)
         self.prec = prec
+        self.compressed = bool(compressed)
         dev = self.device
         f64 = dict(dtype=torch.float64, device=dev)
         i32 = dict(dtype=torch.int32, device=dev)
@@ -202,8 +205,15 @@ class RIProblem:
             self._ws = self.torch.empty(max(int(nbytes), 256), dtype=self.torch.uint8, device=self.device)
         return self._ws
 
+    @property
+    def pflag(self):
+        """The precision argument of the calls that take B (with the compressed flag)."""
+        return self.prec | (COMPRESSED if self.compressed else 0)
+
     def _ws_for(self, op, prec=None):
         prec = self.prec if prec is None else prec
+        if self.compressed and op in (OP_FOCK, OP_ENERGY, OP_GRADIENT):
+            prec |= COMPRESSED
         nb = workspace_bytes(op, self.N, self.n_aux, self.n_occ, max(self.n_pairs or 0, 0), prec)
         if nb == 0:
             raise RIError(1, "ri_workspace_bytes")
@@ -235,7 +245,7 @@ class RIProblem:
         self.L = torch.empty((self.n_aux, self.n_aux), dtype=torch.float64, device=self.device)
         self.Linv = torch.empty_like(self.L)
         self.B = None
-        if pack:
+        if pack and not self.compressed:
             self.B = torch.empty(packed_b_bytes(self.N, self.n_aux, prec), dtype=torch.uint8, device=self.device)
         ws, nb = self._ws_for(OP_METRIC, prec)
         bad = c_int64(-1)
@@ -258,7 +268,7 @@ class RIProblem:
         K = torch.empty_like(J) if K is None else K
         gamma = torch.empty(self.n_aux, dtype=torch.float64, device=self.device) if gamma is None else gamma
         ws, nb = self._ws_for(OP_FOCK)
-        code = lib().ri_fock_jk(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.prec, _ptr(self.T),
+        code = lib().ri_fock_jk(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.pflag, _ptr(self.T),
                                 _ptr(self.pairs), self.n_pairs, _ptr(C_occ), _ptr(J), _ptr(K), _ptr(gamma),
                                 _ptr(ws), nb, self.stream())
         _check(code, "ri_fock_jk")
@@ -270,7 +280,7 @@ class RIProblem:
         C_occ = C_occ.contiguous()
         ws, nb = self._ws_for(OP_FOCK)
         arr = (c_void_p * 4)(*[ctypes.c_void_p(e.cuda_event) for e in events])
-        code = lib().ri_fock_jk_timed(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.prec, _ptr(self.T),
+        code = lib().ri_fock_jk_timed(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.pflag, _ptr(self.T),
                                       _ptr(self.pairs), self.n_pairs, _ptr(C_occ), _ptr(J), _ptr(K), _ptr(gamma),
                                       _ptr(ws), nb, self.stream(), arr)
         _check(code, "ri_fock_jk_timed")
@@ -309,7 +319,7 @@ class RIProblem:
         res = SCFResult()
         ws, nb = self._ws_for(OP_ENERGY)
         g = None if guess is None else guess.contiguous()
-        code = lib().ri_energy(ctypes.byref(self.c_sys), _ptr(self.B), self.prec, _ptr(self.T), _ptr(self.pairs),
+        code = lib().ri_energy(ctypes.byref(self.c_sys), _ptr(self.B), self.pflag, _ptr(self.T), _ptr(self.pairs),
                                self.n_pairs, ctypes.byref(opts), _ptr(g), _ptr(C), _ptr(F), _ptr(D),
                                ctypes.byref(res), _ptr(ws), nb, self.stream())
         if code == 3 and not raise_on_noconv:
@@ -324,7 +334,7 @@ class RIProblem:
         F = self.F if F is None else F
         g = torch.empty((self.system.n_centres, 3), dtype=torch.float64, device=self.device)
         ws, nb = self._ws_for(OP_GRADIENT)
-        code = lib().ri_gradient(ctypes.byref(self.c_sys), _ptr(self.pairs), self.n_pairs, _ptr(self.B), self.prec,
+        code = lib().ri_gradient(ctypes.byref(self.c_sys), _ptr(self.pairs), self.n_pairs, _ptr(self.B), self.pflag,
                                  _ptr(self.T), _ptr(self.Linv), _ptr(C_occ), _ptr(F), _ptr(g), _ptr(ws), nb,
                                  self.stream())
         _check(code, "ri_gradient")

@@ -2,6 +2,7 @@
 // sequencing of kernels on the caller's stream.
 #include "kernels.h"
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -49,6 +50,19 @@ bool valid_sys(const ri_system* s) {
 size_t elem_size(int prec) { return prec == RI_FP64 ? 8 : (prec == RI_FP32 ? 4 : 2); }
 bool is_bf16(int prec) { return prec == RI_BF16X3 || prec == RI_BF16X6; }
 
+// A precision argument: an ri_precision, optionally with RI_COMPRESSED (FP64 / FP32 only).
+struct Prec {
+    int base;
+    bool comp, ok;
+};
+Prec split_prec(int32_t p) {
+    Prec r{p & ~RI_COMPRESSED, (p & RI_COMPRESSED) != 0, true};
+    if (r.base < 0 || r.base > 3) r.ok = false;
+    if (r.comp && r.base != RI_FP64 && r.base != RI_FP32) r.ok = false;
+    return r;
+}
+int comp_slab(int n_aux) { return std::min(RI_COMPRESSED_SLAB, (n_aux + 1) / 2 * 2); }
+
 // ---------------------------------------------------------------- layouts
 struct BuildWS { int32_t* counts; int64_t* offsets; };
 BuildWS carve_build(Arena& a, int N) { return {a.take<int32_t>(N), a.take<int64_t>(N + 1)}; }
@@ -64,9 +78,42 @@ MetricWS carve_metric(Arena& a, int N, int n_aux, int64_t n_pairs) {
     return w;
 }
 
-struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* gamma; double* Cp; int ks, js; };
-FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec) {
+// Slab buffers of the compressed form: pair map and one slab of packed tiles.
+struct SlabWS {
+    int32_t* map = nullptr;
+    void* Bs = nullptr;
+    int slab = 0;
+};
+SlabWS carve_slab(Arena& a, int N, int n_aux, int prec, bool comp) {
+    SlabWS w;
+    if (!comp) return w;
+    w.slab = comp_slab(n_aux);
+    w.map = a.take<int32_t>((int64_t)N * N);
+    w.Bs = a.take<char>((int64_t)w.slab * ri::tile_elems(N) * (int64_t)elem_size(prec));
+    return w;
+}
+
+// X^T = (B^P C)^T for all P; from resident packed B, or (B == nullptr) slab by
+// slab from B_c: unpack RI_COMPRESSED_SLAB auxiliaries into packed tiles, then
+// transform them into their rows of X^T.
+hipError_t x_any(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, double* Cp, void* Xt,
+                 const double* Bc, const int32_t* pairs, int64_t n_pairs, const SlabWS& sw, hipStream_t st) {
+    if (B) return ri::x_transform(B, prec, N, n_aux, n_occ, C, Cp, Xt, st);
+    if (!sw.Bs) return hipErrorInvalidValue;
+    RI_TRY(ri::pair_map(pairs, n_pairs, N, sw.map, st));
+    const int64_t row_bytes = (int64_t)ri::xt_ld(N) * (int64_t)elem_size(prec);
+    for (int P0 = 0; P0 < n_aux; P0 += sw.slab) {
+        const int ns = std::min(sw.slab, n_aux - P0);
+        RI_TRY(ri::pack_b(Bc + (int64_t)P0 * n_pairs, n_pairs, sw.map, N, ns, sw.Bs, prec, st));
+        RI_TRY(ri::x_transform(sw.Bs, prec, N, ns, n_occ, C, Cp, (char*)Xt + (int64_t)P0 * n_occ * row_bytes, st));
+    }
+    return hipSuccess;
+}
+
+struct FockWS { void* Xt; double* part; double* dpair; double* jpart; double* gamma; double* Cp; int ks, js; SlabWS sw; };
+FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec, bool comp = false) {
     FockWS w;
+    w.sw = carve_slab(a, N, n_aux, prec, comp);
     const int Npad = ri::xt_ld(N);
     w.js = ri::j_split_count(n_aux);
     if (is_bf16(prec)) {
@@ -97,7 +144,8 @@ struct EnergyWS {
     int* bad;
     FockWS fock;
 };
-EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec, int diis_n) {
+EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec, int diis_n,
+                      bool comp = false) {
     EnergyWS w;
     const int64_t n2 = (int64_t)N * N;
     double** mats[] = {&w.S, &w.H, &w.Ls, &w.LinvS, &w.J, &w.K, &w.F, &w.D, &w.T1, &w.T2, &w.E, &w.Fx, &w.X, &w.X2};
@@ -118,13 +166,15 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     w.dinvM = a.take<double>((int64_t)((n_occ + 63) / 64) * 4096);
     w.scal = a.take<double>(32);
     w.bad = a.take<int>(2);
-    w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
+    w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, comp);
     return w;
 }
 
-struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part, *Cp; void* Xt; float* Xt32; };
-GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec) {
+struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part, *Cp; void* Xt; float* Xt32; SlabWS sw; };
+GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec,
+                  bool comp = false) {
     GradWS w;
+    w.sw = carve_slab(a, N, n_aux, prec, comp);
     const int Npad = ri::xt_ld(N);
     const int64_t n2 = (int64_t)N * N, o2 = (int64_t)n_occ * n_occ;
     w.D = a.take<double>(n2);
@@ -158,7 +208,7 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
         if (ev) HIPC(hipEventRecord(ev[3], st));
         return RI_OK;
     }
-    HIPC(ri::x_transform(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
+    HIPC(x_any(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, Bc, pairs, n_pairs, w.sw, st));
     if (ev) HIPC(hipEventRecord(ev[2], st));
     HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
     if (ev) HIPC(hipEventRecord(ev[3], st));
@@ -244,15 +294,17 @@ size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec) {
     return (size_t)n_aux * ri::tile_elems(N) * elem_size(prec);
 }
 
-size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, int64_t n_pairs, int32_t prec) {
-    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_pairs < 0 || prec < 0 || prec > 3) return 0;
+size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, int64_t n_pairs, int32_t prec_arg) {
+    const Prec pp = split_prec(prec_arg);
+    const int prec = pp.base;
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_pairs < 0 || !pp.ok) return 0;
     Arena a{nullptr, 0, 0, true};
     switch (op) {
         case RI_OP_BUILD_3C: carve_build(a, N); break;
         case RI_OP_METRIC: carve_metric(a, N, n_aux, n_pairs); break;
-        case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec); break;
-        case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8); break;
-        case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec); break;
+        case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp); break;
+        case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8, pp.comp); break;
+        case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec, pp.comp); break;
         case RI_OP_MLP: {
             size_t off = 0;
             ri::carve_mlp(nullptr, 0, off, std::max<int64_t>(n_pairs, 1));
@@ -281,11 +333,13 @@ int32_t ri_build_3c(const ri_system* sys, double tau, int32_t* pairs, int64_t ca
 }
 
 int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, double* T, double* L,
-                         double* Linv, void* B, int32_t prec, int64_t* bad_pivot, void* ws, size_t ws_bytes,
+                         double* Linv, void* B, int32_t prec_arg, int64_t* bad_pivot, void* ws, size_t ws_bytes,
                          hipStream_t st) {
     if (!valid_sys(sys) || n_pairs < 0 || (n_pairs > 0 && (!pairs || !T)) || !L || !Linv || !bad_pivot || !ws)
         return RI_E_ARG;
-    if (prec < 0 || prec > 3) return RI_E_UNSUPPORTED;
+    const Prec pp = split_prec(prec_arg);
+    if (!pp.ok) return RI_E_UNSUPPORTED;
+    const int prec = pp.base;
     const int na = sys->n_aux, N = sys->n_fn;
     Arena a{(char*)ws, ws_bytes, 0, false};
     MetricWS w = carve_metric(a, N, na, n_pairs);
@@ -311,48 +365,57 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
     return RI_OK;
 }
 
-int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec, const double* Bc,
+int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec_arg, const double* Bc,
                    const int32_t* pairs, int64_t n_pairs, const double* C, double* J, double* K, double* gamma,
                    void* ws, size_t ws_bytes, hipStream_t st) {
-    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
-        (n_pairs > 0 && (!Bc || !pairs)))
+    const Prec pp = split_prec(prec_arg);
+    const int prec = pp.base;
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || (!B && !pp.comp) || !C || !J || !K ||
+        !ws || (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec < 0 || prec > 3 || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
+    if (!pp.ok || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
+    if (pp.comp) B = nullptr;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
+    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp);
     if (!a.ok()) return RI_E_WORKSPACE;
     return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st);
 }
 
-int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec, const double* Bc,
-                         const int32_t* pairs, int64_t n_pairs, const double* C, double* J, double* K,
-                         double* gamma, void* ws, size_t ws_bytes, hipStream_t st, hipEvent_t* events) {
+int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec_arg,
+                         const double* Bc, const int32_t* pairs, int64_t n_pairs, const double* C, double* J,
+                         double* K, double* gamma, void* ws, size_t ws_bytes, hipStream_t st, hipEvent_t* events) {
     if (!events || !events[0] || !events[1] || !events[2] || !events[3]) return RI_E_ARG;
-    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || !B || !C || !J || !K || !ws ||
-        (n_pairs > 0 && (!Bc || !pairs)))
+    const Prec pp = split_prec(prec_arg);
+    const int prec = pp.base;
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || (!B && !pp.comp) || !C || !J || !K ||
+        !ws || (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec < 0 || prec > 3 || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
+    if (!pp.ok || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
+    if (pp.comp) B = nullptr;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec);
+    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp);
     if (!a.ok()) return RI_E_WORKSPACE;
     return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st, events);
 }
 
-int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const double* Bc, const int32_t* pairs,
+int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const ri_scf_opts* opts, const double* guess, double* C_occ, double* F_out,
                   double* D_out, ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t st) {
-    if (!valid_sys(sys) || !B || !opts || !C_occ || !F_out || !res || !ws || n_pairs < 0 ||
+    const Prec pp = split_prec(prec_arg);
+    const int prec = pp.base;
+    if (!valid_sys(sys) || (!B && !pp.comp) || !opts || !C_occ || !F_out || !res || !ws || n_pairs < 0 ||
         (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
+    if (pp.comp) B = nullptr;
     if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0))
         return RI_E_ARG;
     if (opts->guess_kind != 0 && !guess) return RI_E_ARG;
     if (opts->guess_kind < 0 || opts->guess_kind > 2) return RI_E_UNSUPPORTED;
-    if (prec < 0 || prec > 3 || (is_bf16(prec) && sys->n_occ > 128)) return RI_E_UNSUPPORTED;
+    if (!pp.ok || (is_bf16(prec) && sys->n_occ > 128)) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    EnergyWS w = carve_energy(a, N, na, no, n_pairs, prec, 8);
+    EnergyWS w = carve_energy(a, N, na, no, n_pairs, prec, 8, pp.comp);
     if (!a.ok()) return RI_E_WORKSPACE;
     std::memset(res, 0, sizeof(*res));
 
@@ -455,18 +518,22 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
     return converged ? RI_OK : RI_E_NO_CONV;
 }
 
-int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, const void* B, int32_t prec,
+int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs, const void* B, int32_t prec_arg,
                     const double* Bc, const double* Linv, const double* C, const double* F, double* grad, void* ws,
                     size_t ws_bytes, hipStream_t st) {
-    if (!valid_sys(sys) || !B || !Linv || !C || !F || !grad || !ws || n_pairs < 0 || (n_pairs > 0 && (!Bc || !pairs)))
+    const Prec pp = split_prec(prec_arg);
+    const int prec = pp.base;
+    if (!valid_sys(sys) || (!B && !pp.comp) || !Linv || !C || !F || !grad || !ws || n_pairs < 0 ||
+        (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    if (!pp.ok || (prec != RI_FP64 && prec != RI_FP32)) return RI_E_UNSUPPORTED;
+    if (pp.comp) B = nullptr;
     if (sys->n_centres > 2048) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, nc = sys->n_centres;
     const int Npad = ri::xt_ld(N);
     const int64_t o2 = (int64_t)no * no;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    GradWS w = carve_grad(a, N, na, no, n_pairs, 2048, prec);
+    GradWS w = carve_grad(a, N, na, no, n_pairs, 2048, prec, pp.comp);
     if (!a.ok()) return RI_E_WORKSPACE;
     // D = 2 C C^T, W = 1/2 D F D
     HIPC(ri::gemm_f64(false, true, N, N, no, 2.0, C, no, 0, C, no, 0, 0.0, w.D, N, 0, 1, 0, 0, st));
@@ -477,10 +544,10 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     HIPC(ri::gemm_f64(true, false, na, 1, na, 1.0, Linv, na, 0, w.gamma, 1, 0, 0.0, w.c, 1, 0, 1, 2, 0, st));
     // B_ij^P = (C^T B^P C)_ij from X^P = B^P C
     if (prec == RI_FP32) {
-        HIPC(ri::x_transform(B, prec, N, na, no, C, w.Cp, w.Xt32, st));
+        HIPC(x_any(B, prec, N, na, no, C, w.Cp, w.Xt32, Bc, pairs, n_pairs, w.sw, st));
         HIPC(ri::widen(w.Xt32, (double*)w.Xt, (int64_t)na * no * Npad, st));
     } else {
-        HIPC(ri::x_transform(B, prec, N, na, no, C, w.Cp, w.Xt, st));
+        HIPC(x_any(B, prec, N, na, no, C, w.Cp, w.Xt, Bc, pairs, n_pairs, w.sw, st));
     }
     HIPC(ri::gemm_f64(false, false, no, no, N, 1.0, (const double*)w.Xt, Npad, (int64_t)no * Npad, C, no, 0, 0.0,
                       w.Bij, no, o2, na, 0, 0, st));

@@ -45,6 +45,11 @@ def test_workspace_and_packed_sizes():
         assert P.workspace_bytes(op, 32, 80, 8, 528, P.FP64) > 0
     assert P.workspace_bytes(0, 0, 80, 8, 528, P.FP64) == 0
     assert P.workspace_bytes(2, 32, 80, 8, -1, P.FP64) == 0
+    # the compressed form adds the pair map and one slab of packed tiles
+    plain = P.workspace_bytes(2, 1000, 3000, 100, 68799, P.FP64)
+    comp = P.workspace_bytes(2, 1000, 3000, 100, 68799, P.FP64 | P.COMPRESSED)
+    assert comp >= plain + 1000 * 1000 * 4 + 256 * 136 * 4096 * 8
+    assert P.workspace_bytes(2, 1000, 3000, 100, 68799, P.BF16X6 | P.COMPRESSED) == 0
     # the Fock workspace holds X^T (n_aux * n_occ * Npad doubles)
     assert P.workspace_bytes(2, 1000, 3000, 100, 68799, P.FP64) >= 3000 * 100 * 1024 * 8
 
@@ -57,6 +62,11 @@ def test_bad_arguments_rejected_before_device_work():
     assert lib.ri_build_3c(ctypes.byref(s), 0.0, None, 0, ctypes.byref(n), None, None, 0, None) == 1
     assert lib.ri_fock_jk(0, 10, 2, None, 0, None, None, 0, None, None, None, None, None, 0, None) == 1
     assert lib.ri_fock_jk(10, 10, 20, None, 0, None, None, 0, None, None, None, None, None, 0, None) == 1
+    # B may be NULL only with the compressed flag; the flag needs FP64 or FP32
+    ws = ctypes.create_string_buffer(64)
+    assert lib.ri_fock_jk(10, 10, 2, None, 0, None, None, 0, ws, ws, ws, None, ws, 64, None) == 1
+    assert lib.ri_fock_jk(10, 10, 2, None, P.BF16X6 | P.COMPRESSED, None, None, 0, ws, ws, ws, None, ws, 64,
+                          None) not in (0, 1)
     bad = ctypes.c_int64(0)
     assert lib.ri_metric_factor(ctypes.byref(s), None, 0, None, None, None, None, 0, ctypes.byref(bad), None, 0,
                                 None) == 1

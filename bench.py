@@ -160,6 +160,7 @@ def main():
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
     out["precision"] = precision_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
     out["compressed"] = compressed_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
+    out["density_fock"] = density_leg(pr, C, torch, np)
     if args.batched:
         out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec, autotune=not args.no_autotune)
     if args.learned:
@@ -234,6 +235,28 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64):
                               "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
         del pr, J, K, g   # blocks stay in torch's cache for the next leg (see batched_leg)
     return out
+
+
+def density_leg(pr, C, torch, np, reps=3):
+    """Fock build from the density alone at the same workload (as a density
+    start needs): K = 1/2 sum_P B^P D B^P on FP64 MFMA GEMMs, 4 N^3 N_aux
+    flops.  Reports its time, rate, and the largest difference of its J and
+    K from the orbital build for D = 2 C C^T."""
+    N, na = pr.N, pr.n_aux
+    D = 2.0 * C @ C.T
+    J0, K0, _ = pr.fock_jk(C)
+    pr.fock_jk_density(D)                       # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        J1, K1 = pr.fock_jk_density(D)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    fl = 4.0 * N ** 3 * na
+    return {"ms_per_build": round(dt * 1e3, 2), "flops": fl, "tflops": round(fl / dt / 1e12, 2),
+            "frac_fp64_peak": round(fl / dt / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "max_abs_dJ_vs_orbital": float((J1 - J0).abs().max()),
+            "max_abs_dK_vs_orbital": float((K1 - K0).abs().max())}
 
 
 def compressed_leg(s, C, res64, args, P, torch, np, ms_fp64):

@@ -175,7 +175,10 @@ typedef struct {
     double tol_err;        /* max |F D S - S D F| threshold (default 1e-8)      */
     int32_t guess_kind;    /* 0 core Hamiltonian; 1 C_occ [N][n_occ] in `guess`;*/
                            /* 2 density D [N][N] in `guess`: start from the    */
-                           /*   n_occ largest solutions of (S D S) v = l S v   */
+                           /*   n_occ largest solutions of (S D S) v = l S v;  */
+                           /* 3 density D [N][N] in `guess`: start from the    */
+                           /*   occupied space of F(D) = h + J(D) - K(D), the  */
+                           /*   Fock matrix of the density itself             */
 } ri_scf_opts;
 
 typedef struct {
@@ -183,6 +186,24 @@ typedef struct {
     int32_t n_iter, converged;
     double last_dE, max_err;
 } ri_scf_result;
+
+/* ri_fock_jk_density - Coulomb J and exchange K of a density matrix D
+ * given without orbitals (a density start such as a superposition of atomic
+ * densities, or a predicted density).
+ * Paper: eq. j_ri for J (gamma_P = sum B^P_mu_nu D_mu_nu); exchange in its
+ * density form, eq. k with the RI factorisation eq. ri_eri, which reads
+ * K = 1/2 sum_P B^P D B^P (the C_occ-factored eq. tp / eq. k_ri_2 needs
+ * orbitals; the Exchange-build remark notes that a density start makes the
+ * first build slower).  Cost 4 N^3 N_aux FP64 MFMA flops, against
+ * 3 N^2 n_occ N_aux for ri_fock_jk.
+ *   Bc, pairs  as from ri_metric_factor (B itself is not used).
+ *   D          [N][N] device FP64, symmetric (its symmetric part is used).
+ *   J, K       [N][N] out; gamma [n_aux] out or NULL.
+ * Workspace: ri_workspace_bytes(RI_OP_FOCK_DENSITY, N, n_aux, 1, n_pairs, RI_FP64).
+ * Asynchronous. */
+int32_t ri_fock_jk_density(int32_t N, int32_t n_aux, const double* Bc, const int32_t* pairs, int64_t n_pairs,
+                           const double* D, double* J, double* K, double* gamma,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ri_energy - closed-shell RI-HF SCF.
  * Paper: Roothaan equations (Energy formulation section), Fock build
@@ -365,7 +386,7 @@ int32_t ri_md_kinetic(int32_t n_atoms, const double* mass, const double* vel, do
 /* Operation codes for ri_workspace_bytes.  For RI_OP_MLP, n_pairs is the
  * number of feature rows per call. */
 enum { RI_OP_BUILD_3C = 0, RI_OP_METRIC = 1, RI_OP_FOCK = 2, RI_OP_ENERGY = 3,
-       RI_OP_GRADIENT = 4, RI_OP_MLP = 5 };
+       RI_OP_GRADIENT = 4, RI_OP_MLP = 5, RI_OP_FOCK_DENSITY = 6 };
 
 /* Bytes of workspace an operation needs (0 on invalid arguments). */
 size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ,

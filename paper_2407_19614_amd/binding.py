@@ -19,6 +19,7 @@ FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 COMPRESSED = 0x10          # flag: B not resident, decompressed per auxiliary slab each call
 COMPRESSED_SLAB = 256
 OP_BUILD_3C, OP_METRIC, OP_FOCK, OP_ENERGY, OP_GRADIENT = range(5)
+OP_FOCK_DENSITY = 6
 STATUS = {0: "RI_OK", 1: "RI_E_ARG", 2: "RI_E_NOT_PD", 3: "RI_E_NO_CONV", 4: "RI_E_WORKSPACE",
           5: "RI_E_CAPACITY", 6: "RI_E_HIP", 7: "RI_E_UNSUPPORTED"}
 
@@ -114,6 +115,8 @@ _SIGS = {
     "ri_batch_autotune": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_energy_batched": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, POINTER(SCFOpts), c_int32, c_void_p,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ri_fock_jk_density": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_md_verlet": (c_int32, [c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ri_md_kinetic": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
@@ -306,12 +309,28 @@ class RIProblem:
                                            self.stream()), "ri_density_from_pairs")
         return D
 
+    def fock_jk_density(self, D, J=None, K=None, gamma=None):
+        """J and K of a density matrix given without orbitals."""
+        torch = self.torch
+        D = D.contiguous()
+        J = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device) if J is None else J
+        K = torch.empty_like(J) if K is None else K
+        nb = workspace_bytes(OP_FOCK_DENSITY, self.N, self.n_aux, 1, self.n_pairs, FP64)
+        ws = self.workspace(nb)
+        code = lib().ri_fock_jk_density(self.N, self.n_aux, _ptr(self.T), _ptr(self.pairs), self.n_pairs, _ptr(D),
+                                        _ptr(J), _ptr(K), _ptr(gamma), _ptr(ws), nb, self.stream())
+        _check(code, "ri_fock_jk_density")
+        return J, K
+
     def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True,
-               guess_density=None):
+               guess_density=None, density_fock=False):
+        """SCF.  guess: C_occ start; guess_density: density start, through its
+        natural orbitals, or (density_fock=True) through the occupied space of
+        its own Fock matrix (J and K built from the density)."""
         torch = self.torch
         kind = 0 if guess is None else 1
         if guess_density is not None:
-            kind, guess = 2, guess_density
+            kind, guess = (3 if density_fock else 2), guess_density
         opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, kind)
         C = torch.empty((self.N, self.n_occ), dtype=torch.float64, device=self.device)
         F = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)

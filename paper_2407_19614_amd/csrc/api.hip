@@ -137,12 +137,42 @@ FockWS carve_fock(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int pr
     return w;
 }
 
+// Fock build from a density matrix (no orbitals): pair weights, gamma/J
+// buffers, and the slab buffers of K = 1/2 sum_P B^P D B^P.
+constexpr int DENSITY_SLAB = 8;
+struct DensityWS {
+    double *dpair, *jpart, *gamma, *Bf, *Y;
+    int32_t* map;
+    int js, slab;
+};
+DensityWS carve_density(Arena& a, int N, int n_aux, int64_t n_pairs) {
+    DensityWS w;
+    const int64_t n2 = (int64_t)N * N;
+    w.js = ri::j_split_count(n_aux);
+    w.slab = std::min(DENSITY_SLAB, n_aux);
+    w.dpair = a.take<double>(std::max<int64_t>(n_pairs, 1));
+    w.jpart = a.take<double>((int64_t)w.js * std::max<int64_t>(n_pairs, 1));
+    w.gamma = a.take<double>(n_aux);
+    w.map = a.take<int32_t>(n2);
+    w.Bf = a.take<double>(w.slab * n2);
+    w.Y = a.take<double>(w.slab * n2);
+    return w;
+}
+
+hipError_t jk_density(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux, const double* D,
+                      double* J, double* K, double* gamma, const DensityWS& w, hipStream_t st) {
+    RI_TRY(ri::dpair_density(pairs, n_pairs, D, N, w.dpair, st));
+    RI_TRY(ri::gamma_j_pairs(Bc, pairs, n_pairs, N, n_aux, w.dpair, gamma ? gamma : w.gamma, w.jpart, w.js, J, st));
+    return ri::k_density(Bc, pairs, n_pairs, N, n_aux, D, w.map, w.Bf, w.Y, w.slab, K, st);
+}
+
 struct EnergyWS {
     double *S, *H, *Ls, *LinvS, *J, *K, *F, *D, *T1, *T2, *E, *Fx, *X, *X2;
     double *dF[8], *dE[8];
     double *Bmat, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal;
     int* bad;
     FockWS fock;
+    DensityWS dens;
 };
 EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec, int diis_n,
                       bool comp = false) {
@@ -167,6 +197,7 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     w.scal = a.take<double>(32);
     w.bad = a.take<int>(2);
     w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, comp);
+    w.dens = carve_density(a, N, n_aux, n_pairs);
     return w;
 }
 
@@ -305,6 +336,7 @@ size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, i
         case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp); break;
         case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8, pp.comp); break;
         case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec, pp.comp); break;
+        case RI_OP_FOCK_DENSITY: carve_density(a, N, n_aux, n_pairs); break;
         case RI_OP_MLP: {
             size_t off = 0;
             ri::carve_mlp(nullptr, 0, off, std::max<int64_t>(n_pairs, 1));
@@ -398,6 +430,18 @@ int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B,
     return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st, events);
 }
 
+int32_t ri_fock_jk_density(int32_t N, int32_t n_aux, const double* Bc, const int32_t* pairs, int64_t n_pairs,
+                           const double* D, double* J, double* K, double* gamma, void* ws, size_t ws_bytes,
+                           hipStream_t st) {
+    if (N <= 0 || n_aux <= 0 || n_pairs < 0 || !D || !J || !K || !ws || (n_pairs > 0 && (!Bc || !pairs)))
+        return RI_E_ARG;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    DensityWS w = carve_density(a, N, n_aux, n_pairs);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    HIPC(jk_density(Bc, pairs, n_pairs, N, n_aux, D, J, K, gamma, w, st));
+    return RI_OK;
+}
+
 int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const ri_scf_opts* opts, const double* guess, double* C_occ, double* F_out,
                   double* D_out, ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -410,7 +454,7 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
     if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0))
         return RI_E_ARG;
     if (opts->guess_kind != 0 && !guess) return RI_E_ARG;
-    if (opts->guess_kind < 0 || opts->guess_kind > 2) return RI_E_UNSUPPORTED;
+    if (opts->guess_kind < 0 || opts->guess_kind > 3) return RI_E_UNSUPPORTED;
     if (!pp.ok || (is_bf16(prec) && sys->n_occ > 128)) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
@@ -432,6 +476,12 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
     int32_t rc;
     if (opts->guess_kind == 0) {
         rc = occupied_space(w.H, N, no, w, false, C_occ, st);
+        if (rc) return rc;
+    } else if (opts->guess_kind == 3) {
+        // Fock matrix of the density itself (J and K from D), then its occupied space
+        HIPC(jk_density(Bc, pairs, n_pairs, N, na, guess, w.J, w.K, nullptr, w.dens, st));
+        HIPC(ri::fock_assemble(w.H, w.J, w.K, w.F, n2, st));
+        rc = occupied_space(w.F, N, no, w, false, C_occ, st);
         if (rc) return rc;
     } else if (opts->guess_kind == 2) {
         // occupied space of the density: lowest solutions of (-S D S) v = l S v

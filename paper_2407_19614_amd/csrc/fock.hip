@@ -567,6 +567,14 @@ __global__ void dpair_kernel(const int32_t* pairs, int64_t n_pairs, const double
     dp[q] = (mu == nu ? 2.0 : 4.0) * s;
 }
 
+// pair weights of a density matrix: D_mu_mu on the diagonal, D_mu_nu + D_nu_mu off it
+__global__ void dpair_density_kernel(const int32_t* pairs, int64_t n_pairs, const double* D, int N, double* dp) {
+    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    const int mu = pairs[2 * q], nu = pairs[2 * q + 1];
+    dp[q] = mu == nu ? D[(int64_t)mu * N + mu] : D[(int64_t)mu * N + nu] + D[(int64_t)nu * N + mu];
+}
+
 __global__ __launch_bounds__(256) void gamma_kernel(const double* Bc, int64_t n_pairs, const double* dp,
                                                     double* gamma) {
     const int P = blockIdx.x;
@@ -721,11 +729,24 @@ int j_split_count(int n_aux) { return n_aux >= 512 ? 16 : 1; }
 hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux, int n_occ,
                    const double* C, double* dpair, double* gamma, double* jpart, int n_jsplit, double* J,
                    hipStream_t st) {
+    if (n_pairs > 0) {
+        dpair_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(pairs, n_pairs, C, n_occ, dpair);
+        RI_TRY(hipGetLastError());
+    }
+    return gamma_j_pairs(Bc, pairs, n_pairs, N, n_aux, dpair, gamma, jpart, n_jsplit, J, st);
+}
+
+hipError_t dpair_density(const int32_t* pairs, int64_t n_pairs, const double* D, int N, double* dpair, hipStream_t st) {
+    if (n_pairs == 0) return hipSuccess;
+    dpair_density_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(pairs, n_pairs, D, N, dpair);
+    return hipGetLastError();
+}
+
+hipError_t gamma_j_pairs(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
+                         const double* dpair, double* gamma, double* jpart, int n_jsplit, double* J, hipStream_t st) {
     RI_TRY(fill(J, 0.0, (int64_t)N * N, st));
     if (n_pairs == 0) return fill(gamma, 0.0, n_aux, st);
     const unsigned pb = (unsigned)((n_pairs + 255) / 256);
-    dpair_kernel<<<pb, 256, 0, st>>>(pairs, n_pairs, C, n_occ, dpair);
-    RI_TRY(hipGetLastError());
     gamma_kernel<<<n_aux, 256, 0, st>>>(Bc, n_pairs, dpair, gamma);
     RI_TRY(hipGetLastError());
     const int per = (n_aux + n_jsplit - 1) / n_jsplit;

@@ -36,6 +36,15 @@ int k_split_count(int N, int n_aux, int n_occ);
 int64_t xt_rows(int n_aux, int n_occ);
 int xt_ld(int N);
 // gamma and J from the compressed FP64 tensor.
+// gamma and J from pair weights dpair (w D_mu_nu, w = 1 on the diagonal, 2 off it)
+hipError_t gamma_j_pairs(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
+                         const double* dpair, double* gamma, double* jpart, int n_jsplit, double* J, hipStream_t st);
+// pair weights of a density matrix D [N][N] (symmetrised)
+hipError_t dpair_density(const int32_t* pairs, int64_t n_pairs, const double* D, int N, double* dpair, hipStream_t st);
+// K = 1/2 sum_P B^P D B^P from B_c, slab of S auxiliaries at a time (workspace map [N*N],
+// Bf [S][N][N], Y [N][S*N]); K symmetrised.
+hipError_t k_density(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux, const double* D,
+                     int32_t* map, double* Bf, double* Y, int S, double* K, hipStream_t st);
 hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
                    int n_occ, const double* C, double* dpair, double* gamma, double* jpart,
                    int n_jsplit, double* J, hipStream_t st);

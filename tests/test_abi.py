@@ -50,6 +50,8 @@ def test_workspace_and_packed_sizes():
     comp = P.workspace_bytes(2, 1000, 3000, 100, 68799, P.FP64 | P.COMPRESSED)
     assert comp >= plain + 1000 * 1000 * 4 + 256 * 136 * 4096 * 8
     assert P.workspace_bytes(2, 1000, 3000, 100, 68799, P.BF16X6 | P.COMPRESSED) == 0
+    # density Fock build: map, pair weights and two slabs of 8 full N x N matrices
+    assert P.workspace_bytes(6, 1000, 3000, 1, 68799, P.FP64) >= 2 * 8 * 1000 * 1000 * 8 + 1000 * 1000 * 4
     # the Fock workspace holds X^T (n_aux * n_occ * Npad doubles)
     assert P.workspace_bytes(2, 1000, 3000, 100, 68799, P.FP64) >= 3000 * 100 * 1024 * 8
 

@@ -91,9 +91,10 @@ typedef struct {
  * 64 x 64 tiles: tile (I, J), I >= J, has index I(I+1)/2 + J and holds
  * B^P[64I + r][64J + c] at offset r*64 + c; entries beyond N are zero.
  * Layout [n_aux][n_tiles][64*64] of the storage type (double or float).
- * The split-BF16 precisions store full square tiles instead, in 2 (BF16X3)
- * or 3 (BF16X6) planes of bfloat16 parts: [part][n_aux][nt][nt][64*64] with
- * tile (I, J) holding B^P[64I + r][64J + c] at r*64 + c for every I and J.
+ * The split-BF16 precisions store full square tiles instead (every I and
+ * J), each as NS = 2 (BF16X3) or 3 (BF16X6) bfloat16 parts:
+ * [n_aux][nt][nt][2][NS][64][32], part k of B^P[64I + r][64J + 32h + c] at
+ * offset (h*NS + k)*2048 + r*32 + c of tile (I, J).
  * ri_packed_b_bytes() returns the size. */
 #define RI_TILE 64
 size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec);

@@ -6,9 +6,11 @@
 // FP64 across chunks.
 //
 // Layouts:
-//   B  [NS][n_aux][nt][nt][2][64][32]  full square tiles (both triangles):
-//      tile (I,J) holds B^P[64I + r][64J + 32h + c] at h*2048 + r*32 + c, so
-//      the 32-deep half h of 16 consecutive rows is one contiguous 1 KB run.
+//   B  [n_aux][nt][nt][2][NS][64][32]  full square tiles (both triangles):
+//      part k of B^P[64I + r][64J + 32h + c] sits in tile (I,J) of P at
+//      (h*NS + k)*2048 + r*32 + c, so the 32-deep half h of 16 consecutive
+//      rows is one contiguous 1 KB run and the NS parts of a tile half are
+//      adjacent.
 //   Ct [NS][W][Npad]   C_occ^T parts, W = 16 * MT occupied rows (zero padded).
 //   Xb [NS][Npad][R]   X parts with mu as the row and (P, i) -> P*n_occ + i
 //      as the contiguous K index, R = n_aux*n_occ rounded up to 64.
@@ -37,8 +39,7 @@ __global__ __launch_bounds__(256) void pack_bf16_kernel(const double* Bc, int64_
     const int t = blockIdx.x, P = blockIdx.y;
     const int I = t / nt, J = t % nt;
     const double* row = Bc + (int64_t)P * n_pairs;
-    const int64_t plane = (int64_t)n_aux * nt * nt * 4096;
-    __bf16* out = B + ((int64_t)P * nt * nt + t) * 4096;
+    __bf16* out = B + ((int64_t)P * nt * nt + t) * NS * 4096;
     for (int e = threadIdx.x; e < 4096; e += 256) {
         int mu = 64 * I + ((e >> 5) & 63), nu = 64 * J + 32 * (e >> 11) + (e & 31);
         double v = 0.0;
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void pack_bf16_kernel(const double* Bc, int64_
         __bf16 p[3];
         split_parts(v, NS, p);
 #pragma unroll
-        for (int k = 0; k < NS; ++k) out[k * plane + e] = p[k];
+        for (int k = 0; k < NS; ++k) out[((e >> 11) * NS + k) * 2048 + (e & 2047)] = p[k];
     }
 }
 
@@ -116,6 +117,16 @@ __device__ __forceinline__ bf8_t lds_frag(const __bf16* base, int row, int lk) {
     return *(const bf8_t*)(base + row * ROWB + 8 * swz(row, lk));
 }
 
+// Buffer resource over `bytes` bytes at `base` (raw buffer, 32-bit offsets).
+// Loads go through buffer instructions with the stage-dependent part of the
+// address in the scalar offset and a loop-invariant lane offset, so no
+// vector register is rewritten between a load's issue and its completion.
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int64_t bytes) {
+    const int n = (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
+}
+
 // One 32-deep split product: leading term into the FP64 accumulator,
 // corrections into the FP32 one (see above).
 template <int NS>
@@ -140,19 +151,22 @@ __device__ __forceinline__ void fold(d4_t& acc, f4_t& corr) {
 // X for items (row block I2 of 128 rows, auxiliary P), item = I2 + nt2 * P,
 // items b, b + G, ... for workgroup b of G (persistent).  D[mu][i] = sum_nu
 // B^P[mu][nu] C[nu][i].  Wave w owns rows 32 (w % 4) .. +31 of the item and
-// column half w / 4 (tiles 0 .. MA-1 or MA .. MT-1).  B fragments go straight
-// to registers (each is used by one wave pair), three buffers deep; C goes
-// through the LDS ring.  Item, stage and slot advance by counters; rows of a
-// tile index >= nt load tile nt - 1 and are never written.
+// column half w / 4 (tiles 0 .. MA-1 or MA .. MT-1).  Both operands stream
+// through the LDS ring: per stage the B parts of the item's 128 rows and the
+// C parts of all columns, 32 deep.  Item, stage and slot advance by
+// counters; rows of a tile index >= nt load tile nt - 1 and are never
+// written.
 template <int NS, int MT>
 __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict__ B, int nt, int n_aux,
                                                         const __bf16* __restrict__ Ct, int Npad, int n_occ,
                                                         __bf16* __restrict__ Xb, int64_t R) {
+#if defined(__HIP_DEVICE_COMPILE__)   // buffer resources exist on the device side only
     constexpr int W = 16 * MT, MA = (MT + 1) / 2;
-    constexpr int SC = NS * W * ROWB;
+    constexpr int SB = NS * 128 * ROWB, SC = NS * W * ROWB, STAGE = SB + SC;
+    constexpr int NB = NS;                             // B instructions per wave per stage (8 NS / 8 waves)
     constexpr int NCI = NS * MT, NC = (NCI + 7) / 8;   // C instructions (total, per wave)
-    constexpr int LOADS = 2 * NS + NC;                 // VMEM ops per wave per stage
-    __shared__ __attribute__((aligned(16))) __bf16 cring[RING * SC];
+    constexpr int LOADS = NB + NC;                     // VMEM ops per wave per stage
+    __shared__ __attribute__((aligned(16))) __bf16 ring[RING * STAGE];
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rg = wave & 3, cg = wave >> 2;
@@ -162,35 +176,50 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
     const int G = gridDim.x;
     const int mine = n_items > (int)blockIdx.x ? (n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
     if (mine == 0) return;
-    const int64_t bplane = (int64_t)n_aux * nt * nt * 4096;
     const int64_t cplane = (int64_t)W * Npad;
     const int lrow = lane >> 2, lch = lane & 3;
-    const int boff = ((rg & 1) * 32 + li) * ROWB + 8 * lk;   // + 16 * ROWB for the second fragment
-    const int btile = rg >> 1;
-    const __bf16* csrc[NC];
-    int cdst[NC];
+    // lane byte offsets of (row lrow, chunk lch) of a 16-row group: B tile halves are 32 wide, C rows Npad
+    const int bvoff = (lrow * ROWB + 8 * swz(lrow, lch)) * 2;
+    const int cvoff = (lrow * Npad + 8 * swz(lrow, lch)) * 2;
+    // B instructions: part p, 16-row group g of the 128 (tile g / 4, rows 16 (g % 4) ..)
+    int bsoff[NB], btl[NB], bdst[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int t = wave + 8 * u, p = t >> 3, g = t & 7;
+        bsoff[u] = (p * 2048 + 16 * (g & 3) * ROWB) * 2;
+        btl[u] = g >> 2;
+        bdst[u] = (p * 128 + 16 * g) * ROWB;
+    }
+    const __amdgpu_buffer_rsrc_t crs = rsrc(Ct, (int64_t)NS * cplane * 2);
+    int csoff[NC], cdst[NC];
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
-        const int t = min(wave + 8 * u, NCI - 1), q = t / MT, mg = t % MT, row = 16 * mg + lrow;
-        csrc[u] = Ct + q * cplane + (int64_t)row * Npad + 8 * swz(row, lch);
-        cdst[u] = (q * W + 16 * mg) * ROWB;
+        const int t = min(wave + 8 * u, NCI - 1), q = t / MT, mg = t % MT;
+        csoff[u] = (int)((q * cplane + (int64_t)16 * mg * Npad) * 2);
+        cdst[u] = SB + (q * W + 16 * mg) * ROWB;
     }
 
-    int ij = 0, is = 0;                                 // next stage to issue
+    int ij = 0, is = 0, islot = 0;                      // next stage to issue
     int iI2 = (int)blockIdx.x % nt2, iP = (int)blockIdx.x / nt2;
-    auto issue = [&](bf8_t (&bf)[2][NS], int slot) {
+    auto issue = [&]() {
         const int J = is >> 1, ks = is & 1;
-        const int I = min(2 * iI2 + btile, nt - 1);
-        const __bf16* tb = B + (((int64_t)iP * nt + I) * nt + J) * 4096 + ks * 2048 + boff;
+        __bf16* st = ring + islot * STAGE;
+        __amdgpu_buffer_rsrc_t brs[2];
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
+        for (int h = 0; h < 2; ++h) {
+            const int I = min(2 * iI2 + h, nt - 1);
+            brs[h] = rsrc(B + (((int64_t)iP * nt + I) * nt + J) * NS * 4096, NS * 4096 * 2);
+        }
+        const int hoff = ks * NS * 2048 * 2;
 #pragma unroll
-            for (int p = 0; p < NS; ++p) bf[f][p] = *(const bf8_t*)(tb + p * bplane + f * 16 * ROWB);
-        __bf16* st = cring + slot * SC;
+        for (int u = 0; u < NB; ++u)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(brs[btl[u]], (lds_void_t)(st + bdst[u]), 16, bvoff,
+                                                     hoff + bsoff[u], 0, 0);
+        const int coff = (64 * J + 32 * ks) * 2;
 #pragma unroll
         for (int u = 0; u < NC; ++u)
-            __builtin_amdgcn_global_load_lds((const void*)(csrc[u] + 64 * J + 32 * ks), (lds_void_t)(st + cdst[u]),
-                                             16, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(crs, (lds_void_t)(st + cdst[u]), 16, cvoff, csoff[u] + coff, 0, 0);
+        islot = islot == RING - 1 ? 0 : islot + 1;
         if (is + 1 < spi) ++is;
         else if (ij + 1 < mine) {
             is = 0;
@@ -198,7 +227,7 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
             const int item = (int)blockIdx.x + ij * G;
             iI2 = item % nt2;
             iP = item / nt2;
-        }   // else: stay on the last stage (tail reloads, never read)
+        }   // else: stay on the last stage (tail reloads land in a slot that is never read)
     };
 
     d4_t acc[2][MA];
@@ -207,18 +236,23 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
     for (int f = 0; f < 2; ++f)
 #pragma unroll
         for (int m = 0; m < MA; ++m) { acc[f][m] = d4_t{0, 0, 0, 0}; corr[f][m] = f4_t{0.f, 0.f, 0.f, 0.f}; }
-    int64_t g = 0;
-    const int64_t total = (int64_t)mine * spi;
-    int cj = 0, cs = 0;
+    int cj = 0, cs = 0, cslot = 0;
     int cI2 = (int)blockIdx.x % nt2, cP = (int)blockIdx.x / nt2;
     const int64_t xplane = (int64_t)Npad * R;
-
-    // compute the stage in registers `cur` / ring slot `slot`; returns true when done
-    auto body = [&](bf8_t (&cur)[2][NS], bf8_t (&nxt)[2][NS], int slot) -> bool {
+    issue();
+    issue();
+    while (true) {
         wait_vm<LOADS>();
         __builtin_amdgcn_s_barrier();
-        issue(nxt, slot == 0 ? 2 : slot - 1);
-        const __bf16* sc = cring + slot * SC;
+        issue();
+        const __bf16* sb = ring + cslot * STAGE;
+        const __bf16* sc = sb + SB;
+        cslot = cslot == RING - 1 ? 0 : cslot + 1;
+        bf8_t a[2][NS];
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int p = 0; p < NS; ++p) a[f][p] = lds_frag(sb + p * 128 * ROWB, 32 * rg + 16 * f + li, lk);
 #pragma unroll
         for (int mi = 0; mi < MA; ++mi) {
             if (mi < mcount) {
@@ -226,7 +260,7 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
 #pragma unroll
                 for (int q = 0; q < NS; ++q) c[q] = lds_frag(sc + q * W * ROWB, 16 * (m0 + mi) + li, lk);
 #pragma unroll
-                for (int f = 0; f < 2; ++f) split_mfma<NS>(cur[f], c, acc[f][mi], corr[f][mi]);
+                for (int f = 0; f < 2; ++f) split_mfma<NS>(a[f], c, acc[f][mi], corr[f][mi]);
             }
         }
         if ((cs & 7) == 7) {
@@ -235,44 +269,34 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
 #pragma unroll
                 for (int mi = 0; mi < MA; ++mi) fold(acc[f][mi], corr[f][mi]);
         }
-        if (++cs == spi) {                               // item complete: write X parts, reset
+        if (++cs < spi) continue;
+        // item complete: write X parts, reset
 #pragma unroll
-            for (int f = 0; f < 2; ++f)
+        for (int f = 0; f < 2; ++f)
 #pragma unroll
-                for (int mi = 0; mi < MA; ++mi) {
+            for (int mi = 0; mi < MA; ++mi) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int mu = 128 * cI2 + 32 * rg + 16 * f + 4 * lk + r, i = 16 * (m0 + mi) + li;
-                        if (mi < mcount && mu < 64 * nt && i < n_occ) {
-                            __bf16 pt[3];
-                            split_parts(acc[f][mi][r] + (double)corr[f][mi][r], NS, pt);
-                            const int64_t o = (int64_t)mu * R + (int64_t)cP * n_occ + i;
+                for (int r = 0; r < 4; ++r) {
+                    const int mu = 128 * cI2 + 32 * rg + 16 * f + 4 * lk + r, i = 16 * (m0 + mi) + li;
+                    if (mi < mcount && mu < 64 * nt && i < n_occ) {
+                        __bf16 pt[3];
+                        split_parts(acc[f][mi][r] + (double)corr[f][mi][r], NS, pt);
+                        const int64_t o = (int64_t)mu * R + (int64_t)cP * n_occ + i;
 #pragma unroll
-                            for (int k = 0; k < NS; ++k) Xb[k * xplane + o] = pt[k];
-                        }
+                        for (int k = 0; k < NS; ++k) Xb[k * xplane + o] = pt[k];
                     }
-                    acc[f][mi] = d4_t{0, 0, 0, 0};
-                    corr[f][mi] = f4_t{0.f, 0.f, 0.f, 0.f};
                 }
-            cs = 0;
-            if (++cj < mine) {
-                const int item = (int)blockIdx.x + cj * G;
-                cI2 = item % nt2;
-                cP = item / nt2;
+                acc[f][mi] = d4_t{0, 0, 0, 0};
+                corr[f][mi] = f4_t{0.f, 0.f, 0.f, 0.f};
             }
-        }
-        return ++g == total;
-    };
-
-    bf8_t b0[2][NS], b1[2][NS], b2[2][NS];
-    issue(b0, 0);
-    issue(b1, 1);
-    while (true) {
-        if (body(b0, b2, 0)) break;
-        if (body(b1, b0, 1)) break;
-        if (body(b2, b1, 2)) break;
+        if (++cj == mine) break;
+        cs = 0;
+        const int item = (int)blockIdx.x + cj * G;
+        cI2 = item % nt2;
+        cP = item / nt2;
     }
     wait_vm<0>();
+#endif
 }
 
 // K partials over lower 128 x 128 tiles, split over the K index in multiples
@@ -281,6 +305,7 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
 template <int NS>
 __global__ __launch_bounds__(512, 1) void syrk_bf16_kernel(const __bf16* __restrict__ Xb, int Npad, int64_t R,
                                                            int64_t chunk, int ntile, double* __restrict__ part) {
+#if defined(__HIP_DEVICE_COMPILE__)   // buffer resources exist on the device side only
     constexpr int SA = NS * 128 * ROWB, STAGE = 2 * SA;
     constexpr int LOADS = 2 * NS * 8 / 8;
     __shared__ __attribute__((aligned(16))) __bf16 ring[RING * STAGE];
@@ -371,6 +396,7 @@ __global__ __launch_bounds__(512, 1) void syrk_bf16_kernel(const __bf16* __restr
             for (int r = 0; r < 4; ++r)
                 out[(int64_t)(ti * 128 + wm + 16 * i + 4 * lk + r) * Npad + tj * 128 + wn + 16 * j + li] =
                     acc[i][j][r] + (double)corr[i][j][r];
+#endif
 }
 
 __global__ void kreduce_bf_kernel(const double* part, int n_split, int Npad, int N, double* K) {

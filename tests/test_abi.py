@@ -66,6 +66,8 @@ def test_bad_arguments_rejected_before_device_work():
     assert lib.ri_fock_jk(10, 10, 20, None, 0, None, None, 0, None, None, None, None, None, 0, None) == 1
     # B may be NULL only with the compressed flag; the flag needs FP64 or FP32
     ws = ctypes.create_string_buffer(64)
+    # split BF16 keeps n_occ <= 128 (eight 16-column MFMA tiles)
+    assert lib.ri_fock_jk(200, 10, 129, ws, P.BF16X6, None, None, 0, ws, ws, ws, None, ws, 64, None) == 7
     assert lib.ri_fock_jk(10, 10, 2, None, 0, None, None, 0, ws, ws, ws, None, ws, 64, None) == 1
     assert lib.ri_fock_jk(10, 10, 2, None, P.BF16X6 | P.COMPRESSED, None, None, 0, ws, ws, ws, None, ws, 64,
                           None) not in (0, 1)

@@ -1,0 +1,96 @@
+"""Edge cases of the method on the GPU path against the oracle: no
+significant pairs, a single atom (one occupied orbital), basis sizes on and
+just past a 64-function tile boundary with an odd auxiliary count, and the
+reduced-precision and compressed forms on the same shapes."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import gradient as G
+from oracle import ri as R
+from oracle import scf as S
+from tests.gpu_common import need_gpu, problem, to_np, dev
+
+pytestmark = pytest.mark.gpu
+
+ORB4 = [0.3, 1.0, 3.5, 12.0]
+ORB5 = [0.2, 0.6, 1.8, 5.4, 16.2]
+AUX5 = [0.15, 0.5, 1.7, 5.8, 20.0]
+AUX7 = [0.1, 0.3, 0.9, 2.7, 8.1, 24.3, 72.9]
+
+
+def test_no_significant_pairs():
+    need_gpu()
+    import paper_2407_19614_amd as P
+    print("case: edge, tau removes every pair", flush=True)
+    s = synth.make_system(synth.cube_cluster(3, 8.0, 2.5, 7), [0.3, 1.0, 3.5], [0.2, 0.6, 2.0, 7.0], tau=1e3)
+    ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
+    for prec, comp in ((P.FP64, False), (P.BF16X6, False), (P.FP64, True)):
+        pr = P.RIProblem(s, prec=prec, compressed=comp)
+        assert pr.build_3c() == 0
+        pr.metric_factor(prec)
+        J, K, g = (to_np(t) for t in pr.fock_jk(dev(synth.random_coeffs(s.N, s.n_occ, 1))))
+        assert not J.any() and not K.any() and not g.any()
+        r, *_ = pr.energy(tol_E=1e-11, tol_err=1e-9)
+        assert r["converged"] and abs(r["E_total"] - ref.E) < 1e-10, (prec, comp)
+
+
+def test_single_atom():
+    need_gpu()
+    import paper_2407_19614_amd as P
+    print("case: edge, one helium centre (N=4, n_occ=1)", flush=True)
+    s = synth.make_system(np.zeros((1, 3)), ORB4, list(0.1 * 2.5 ** np.arange(10)), tau=0.0)
+    ri = R.RIData(s)
+    ref = S.run_scf(s, ri, tol_E=1e-12, tol_e=1e-10)
+    pr = problem(s)
+    r, C, F, _ = pr.energy(tol_E=1e-12, tol_err=1e-10)
+    assert abs(r["E_total"] - ref.E) < 1e-10
+    g = to_np(pr.gradient(C, F))
+    assert np.abs(g).max() < 1e-10                         # one atom: no force
+    for prec in (P.FP32, P.BF16X6):
+        p2 = problem(s, prec)
+        # thresholds above the reduced-precision exchange's noise floor
+        r2, *_ = p2.energy(tol_E=1e-8, tol_err=1e-6)
+        assert abs(r2["E_total"] - ref.E) < 1e-6, prec
+
+
+@pytest.mark.parametrize("nc,orb,aux", [(16, ORB4, AUX5), (13, ORB5, AUX7)])
+def test_tile_boundary_and_odd_aux(nc, orb, aux):
+    need_gpu()
+    import paper_2407_19614_amd as P
+    s = synth.make_system(synth.cube_cluster(nc, 12.0, 2.5, 40 + nc), orb, aux, tau=1e-12)
+    print(f"case: edge, N={s.N} n_aux={s.n_aux} n_occ={s.n_occ}", flush=True)
+    assert s.N in (64, 65)
+    ri = R.RIData(s)
+    C = synth.random_coeffs(s.N, s.n_occ, 2)
+    Jr, Kr = ri.JK(C)
+    pr = problem(s)
+    J, K, _ = (to_np(t) for t in pr.fock_jk(dev(C)))
+    assert np.abs(J - Jr).max() < 1e-11 * np.abs(Jr).max()
+    assert np.abs(K - Kr).max() < 1e-11 * np.abs(Kr).max()
+    ref = S.run_scf(s, ri, tol_E=1e-12, tol_e=1e-10)
+    r, C1, F1, _ = pr.energy(tol_E=1e-12, tol_err=1e-10)
+    assert abs(r["E_total"] - ref.E) < 1e-10
+    gr = G.analytic_gradient(s, ref, ri)
+    assert np.abs(to_np(pr.gradient(C1, F1)) - gr).max() < 1e-8
+    # split BF16 and the compressed form on the same shape
+    pb = problem(s, P.BF16X6)
+    _, Kb, _ = (to_np(t) for t in pb.fock_jk(dev(C)))
+    assert np.abs(Kb - Kr).max() < 1e-6 * np.abs(Kr).max()
+    pc = P.RIProblem(s, compressed=True)
+    pc.build_3c()
+    pc.metric_factor(P.FP64)
+    Jc, Kc, _ = (to_np(t) for t in pc.fock_jk(dev(C)))
+    assert np.array_equal(Jc, J) and np.array_equal(Kc, K)
+
+
+def test_batched_single_molecule():
+    need_gpu()
+    import paper_2407_19614_amd as P
+    from paper_2407_19614_amd.binding import energy_batched
+    print("case: edge, batch of one", flush=True)
+    s = synth.make_system(synth.cube_cluster(5, 9.0, 2.5, 77), ORB4, AUX5, tau=1e-12)
+    pr = problem(s)
+    res, _, _ = energy_batched([pr], P.FP64, tol_E=1e-11, tol_err=1e-9)
+    ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
+    assert res[0]["converged"] and abs(res[0]["E_total"] - ref.E) < 1e-9

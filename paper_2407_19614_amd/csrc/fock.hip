@@ -45,14 +45,20 @@ __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_p
 }
 
 // X^T for (row-block I, auxiliary pair P0, P0+1): each wave owns one P and
-// 32 columns mu (2 MFMA column tiles) over all MT occupied row tiles, so the
-// staged C_occ slice serves both P.  Next-slice global loads are held in
-// registers while the current slice is multiplied.
-template <int MT>
+// 32 columns mu (2 MFMA column tiles) over MF full 16-row occupied tiles and
+// TQ trailing 4-row quads, so the staged C_occ slice serves both P.  The
+// quads run on the 4-block 4x4x4 FP64 MFMA, whose B operand takes the same
+// lane mapping as the 16x16x4 one (block = lane/4 % 4 covers columns
+// 4*block .. 4*block+3 of the 16), so a row count that is not a multiple of
+// 16 does not pay for a whole padded tile: one quad costs a quarter of a
+// 16x16x4 issue.  Next-slice global loads are held in registers while the
+// current slice is multiplied.
+template <int MF, int TQ>
 __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double* __restrict__ B, int nt, int64_t ntl,
                                             const double* __restrict__ C, int N, int n_occ, int n_aux,
                                             double* __restrict__ Xt, int Npad) {
-    constexpr int W = MT * 16;
+    constexpr int W = MF * 16 + TQ * 4;            // occupied columns staged per slice
+    constexpr int NCR = (16 * W + 255) / 256;      // C elements per thread per slice
     __shared__ double Bs[2][16][65];
     __shared__ double Cs[16][W + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -60,7 +66,7 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
     const bool has1 = P0 + 1 < n_aux;
     const double* Bp0 = B + (int64_t)P0 * ntl * 4096;
     const double* Bp1 = B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096;
-    double rb[8], rc[MT];
+    double rb[8], rc[NCR];
     auto load = [&](int J, int k0) {
         const bool lower = J <= I;
         const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
@@ -73,10 +79,10 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
             rb[4 + r] = has1 ? Bp1[toff + off] : 0.0;
         }
 #pragma unroll
-        for (int r = 0; r < MT; ++r) {
+        for (int r = 0; r < NCR; ++r) {
             int e = tid + 256 * r, k = e / W, i = e % W;
             int nu = 64 * J + k0 + k, gi = i0 + i;
-            rc[r] = (nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
+            rc[r] = (e < 16 * W && nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
         }
     };
     auto store = [&](int J) {
@@ -90,14 +96,17 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
             Bs[1][k][m] = rb[4 + r];
         }
 #pragma unroll
-        for (int r = 0; r < MT; ++r) {
+        for (int r = 0; r < NCR; ++r) {
             int e = tid + 256 * r;
-            Cs[e / W][e % W] = rc[r];
+            if (16 * W % 256 == 0 || e < 16 * W) Cs[e / W][e % W] = rc[r];
         }
     };
-    d4_t acc[MT][2];
+    d4_t acc[MF > 0 ? MF : 1][2];
+    double accq[TQ > 0 ? TQ : 1][2];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) { acc[m][0] = d4_t{0, 0, 0, 0}; acc[m][1] = d4_t{0, 0, 0, 0}; }
+    for (int m = 0; m < MF; ++m) { acc[m][0] = d4_t{0, 0, 0, 0}; acc[m][1] = d4_t{0, 0, 0, 0}; }
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) { accq[q][0] = 0.0; accq[q][1] = 0.0; }
     const int nsl = nt * 4;
     load(0, 0);
     for (int sl = 0; sl < nsl; ++sl) {
@@ -110,17 +119,24 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
         for (int kk = 0; kk < 16; kk += 4) {
             double b0 = Bs[ps][kk + lk][h * 32 + li], b1 = Bs[ps][kk + lk][h * 32 + 16 + li];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
+            for (int m = 0; m < MF; ++m) {
                 double a = Cs[kk + lk][m * 16 + li];
                 acc[m][0] = mfma_f64(a, b0, acc[m][0]);
                 acc[m][1] = mfma_f64(a, b1, acc[m][1]);
+            }
+            // 4x4x4 block operands: A row = lane % 4, k = lane / 16
+#pragma unroll
+            for (int q = 0; q < TQ; ++q) {
+                double a = Cs[kk + lk][MF * 16 + 4 * q + (lane & 3)];
+                accq[q][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b0, accq[q][0], 0, 0, 0);
+                accq[q][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b1, accq[q][1], 0, 0, 0);
             }
         }
     }
     const int P = P0 + ps;
     if (P >= n_aux) return;
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MF; ++m)
 #pragma unroll
         for (int n = 0; n < 2; ++n)
 #pragma unroll
@@ -128,14 +144,23 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
                 int i = i0 + m * 16 + 4 * r + lk;
                 if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = acc[m][n][r];
             }
+    // 4x4x4 result: row = lane / 16, column = lane % 16 (block-major)
+#pragma unroll
+    for (int q = 0; q < TQ; ++q)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            int i = i0 + MF * 16 + 4 * q + lk;
+            if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = accq[q][n];
+        }
 }
 
-template <int MT>
+template <int MF, int TQ>
 __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
                                                      const double* __restrict__ C, int N, int n_occ, int n_aux,
                                                      double* __restrict__ Xt, int Npad) {
     const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    x2_body_f64<MT>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt, Npad);
+    x2_body_f64<MF, TQ>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt,
+                        Npad);
 }
 
 
@@ -671,9 +696,19 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
         }
         return hipGetLastError();
     }
-    switch (mt) {
-#define XCASE(k) case k: x2_kernel_f64<k><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
-        XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
+    // occupied rows of one 128-wide chunk: whole 16-row tiles plus, when the
+    // last tile would hold 12 rows or fewer, 4-row quads in its place
+    int mf = mt, tq = 0;
+    if (n_occ <= 128) {
+        const int rem = n_occ - 16 * (mt - 1);
+        if (rem <= 12) { mf = mt - 1; tq = (rem + 3) / 4; }
+    }
+    switch (mf * 4 + tq) {
+#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
+#define XROW(f) XCASE(f, 1) XCASE(f, 2) XCASE(f, 3)
+        XROW(0) XROW(1) XROW(2) XROW(3) XROW(4) XROW(5) XROW(6) XROW(7)
+        XCASE(1, 0) XCASE(2, 0) XCASE(3, 0) XCASE(4, 0) XCASE(5, 0) XCASE(6, 0) XCASE(7, 0) XCASE(8, 0)
+#undef XROW
 #undef XCASE
         default: return hipErrorInvalidValue;
     }
@@ -769,7 +804,7 @@ __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const
     if (!m.state[0] || m.mt != MT) return;
     const int I = loc % m.nt, P0 = 2 * (loc / m.nt);
     if (PREC == RI_FP64)
-        x2_body_f64<MT>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
+        x2_body_f64<MT, 0>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
     else
         x2_body_f32<MT>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
 }

@@ -84,6 +84,28 @@ def test_tile_boundary_and_odd_aux(nc, orb, aux):
     assert np.array_equal(Jc, J) and np.array_equal(Kc, K)
 
 
+# Occupied counts around every 16-row tile and 4-row quad boundary of the
+# exchange half-transform, one and two 128-wide occupied chunks.
+N_OCC_SWEEP = [1, 2, 3, 4, 5, 8, 9, 12, 13, 16, 17, 20, 28, 29, 36, 100, 116, 117, 128, 129, 141, 160]
+
+
+def test_exchange_occupied_count_sweep():
+    need_gpu()
+    import paper_2407_19614_amd as P
+    xyz = synth.cube_cluster(40, 16.0, 2.5, 77)
+    base = synth.make_system(xyz, ORB4, AUX5, tau=1e-12)
+    assert base.N == 160
+    ri = R.RIData(base)
+    for n_occ in N_OCC_SWEEP:
+        print(f"case: edge, exchange N=160 n_aux=200 n_occ={n_occ}", flush=True)
+        s = synth.make_system(xyz, ORB4, AUX5, tau=1e-12, n_occ=n_occ)
+        C = synth.random_coeffs(s.N, n_occ, 10 + n_occ)
+        Kr = ri.K(C)
+        pr = problem(s)
+        _, K, _ = (to_np(t) for t in pr.fock_jk(dev(C)))
+        assert np.abs(K - Kr).max() < 1e-11 * np.abs(Kr).max(), n_occ
+
+
 def test_batched_single_molecule():
     need_gpu()
     import paper_2407_19614_amd as P

@@ -52,22 +52,28 @@ __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_p
 // 4*block .. 4*block+3 of the 16), so a row count that is not a multiple of
 // 16 does not pay for a whole padded tile: one quad costs a quarter of a
 // 16x16x4 issue.  Next-slice global loads are held in registers while the
-// current slice is multiplied.
-template <int MF, int TQ>
+// current slice is multiplied, issued between the first two k-steps so the
+// MFMA pipe is not left idle while they go out.
+//
+// CPAD: C is the zero-padded copy [64 * nt rows][cld >= i0 + 16*ceil(W/16)],
+// so every load is unconditional; otherwise C is [N][n_occ] with bounds
+// tests.  With a single auxiliary index left (P0 + 1 == n_aux) the second
+// half reads P0's tiles again and its results are not stored.
+template <int MF, int TQ, bool CPAD>
 __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double* __restrict__ B, int nt, int64_t ntl,
-                                            const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                            const double* __restrict__ C, int cld, int N, int n_occ, int n_aux,
                                             double* __restrict__ Xt, int Npad) {
-    constexpr int W = MF * 16 + TQ * 4;            // occupied columns staged per slice
-    constexpr int NCR = (16 * W + 255) / 256;      // C elements per thread per slice
+    constexpr int W = MF * 16 + TQ * 4;            // occupied columns used per slice
+    constexpr int WS = CPAD ? (W + 15) / 16 * 16 : W;   // columns staged per slice
+    constexpr int NCR = (16 * WS + 255) / 256;     // C elements per thread per slice
     __shared__ double Bs[2][16][65];
-    __shared__ double Cs[16][W + 1];
+    __shared__ double Cs[16][WS + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int ps = wave >> 1, h = wave & 1;
-    const bool has1 = P0 + 1 < n_aux;
     const double* Bp0 = B + (int64_t)P0 * ntl * 4096;
-    const double* Bp1 = B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096;
+    const double* Bp1 = B + (int64_t)(P0 + 1 < n_aux ? P0 + 1 : P0) * ntl * 4096;
     double rb[8], rc[NCR];
-    auto load = [&](int J, int k0) {
+    auto load_b = [&](int J, int k0) {
         const bool lower = J <= I;
         const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
 #pragma unroll
@@ -76,13 +82,19 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
             if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
             else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
             rb[r] = Bp0[toff + off];
-            rb[4 + r] = has1 ? Bp1[toff + off] : 0.0;
+            rb[4 + r] = Bp1[toff + off];
         }
+    };
+    auto load_c = [&](int J, int k0) {
 #pragma unroll
         for (int r = 0; r < NCR; ++r) {
-            int e = tid + 256 * r, k = e / W, i = e % W;
+            int e = tid + 256 * r, k = e / WS, i = e % WS;
             int nu = 64 * J + k0 + k, gi = i0 + i;
-            rc[r] = (e < 16 * W && nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
+            if (CPAD) {
+                if (16 * WS % 256 == 0 || e < 16 * WS) rc[r] = C[(int64_t)nu * cld + gi];
+            } else {
+                rc[r] = (e < 16 * WS && nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
+            }
         }
     };
     auto store = [&](int J) {
@@ -98,7 +110,7 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
 #pragma unroll
         for (int r = 0; r < NCR; ++r) {
             int e = tid + 256 * r;
-            if (16 * W % 256 == 0 || e < 16 * W) Cs[e / W][e % W] = rc[r];
+            if (16 * WS % 256 == 0 || e < 16 * WS) Cs[e / WS][e % WS] = rc[r];
         }
     };
     d4_t acc[MF > 0 ? MF : 1][2];
@@ -108,13 +120,15 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
 #pragma unroll
     for (int q = 0; q < TQ; ++q) { accq[q][0] = 0.0; accq[q][1] = 0.0; }
     const int nsl = nt * 4;
-    load(0, 0);
+    load_b(0, 0);
+    load_c(0, 0);
     for (int sl = 0; sl < nsl; ++sl) {
         const int J = sl >> 2;
         __syncthreads();
         store(J);
         __syncthreads();
-        if (sl + 1 < nsl) load((sl + 1) >> 2, ((sl + 1) & 3) * 16);
+        const bool more = sl + 1 < nsl;
+        const int Jn = (sl + 1) >> 2, kn = ((sl + 1) & 3) * 16;
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             double b0 = Bs[ps][kk + lk][h * 32 + li], b1 = Bs[ps][kk + lk][h * 32 + 16 + li];
@@ -131,6 +145,8 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
                 accq[q][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b0, accq[q][0], 0, 0, 0);
                 accq[q][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b1, accq[q][1], 0, 0, 0);
             }
+            if (kk == 0 && more) load_b(Jn, kn);
+            if (kk == 4 && more) load_c(Jn, kn);
         }
     }
     const int P = P0 + ps;
@@ -156,11 +172,11 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
 
 template <int MF, int TQ>
 __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
-                                                     const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                                     const double* __restrict__ Cp, int cld, int n_occ, int n_aux,
                                                      double* __restrict__ Xt, int Npad) {
     const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    x2_body_f64<MF, TQ>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt,
-                        Npad);
+    x2_body_f64<MF, TQ, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, Cp, cld, 0, n_occ,
+                              n_aux, Xt, Npad);
 }
 
 
@@ -703,8 +719,11 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
         const int rem = n_occ - 16 * (mt - 1);
         if (rem <= 12) { mf = mt - 1; tq = (rem + 3) / 4; }
     }
+    const int cld = cpad_ld(n_occ), rows = nt * 64;
+    cpad_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cp);
+    RI_TRY(hipGetLastError());
     switch (mf * 4 + tq) {
-#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
+#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, n_occ, n_aux, x, Npad); break;
 #define XROW(f) XCASE(f, 1) XCASE(f, 2) XCASE(f, 3)
         XROW(0) XROW(1) XROW(2) XROW(3) XROW(4) XROW(5) XROW(6) XROW(7)
         XCASE(1, 0) XCASE(2, 0) XCASE(3, 0) XCASE(4, 0) XCASE(5, 0) XCASE(6, 0) XCASE(7, 0) XCASE(8, 0)
@@ -804,7 +823,7 @@ __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const
     if (!m.state[0] || m.mt != MT) return;
     const int I = loc % m.nt, P0 = 2 * (loc / m.nt);
     if (PREC == RI_FP64)
-        x2_body_f64<MT, 0>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
+        x2_body_f64<MT, 0, false>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, 0, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
     else
         x2_body_f32<MT>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
 }

@@ -56,8 +56,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_p
 // MFMA pipe is not left idle while they go out.
 //
 // CPAD: C is the zero-padded copy [64 * nt rows][cld >= i0 + 16*ceil(W/16)],
-// so every load is unconditional; otherwise C is [N][n_occ] with bounds
-// tests.  With a single auxiliary index left (P0 + 1 == n_aux) the second
+// so every load is unconditional, and loads go through buffer resources;
+// otherwise C is [N][n_occ] with bounds tests.  With a single auxiliary index left (P0 + 1 == n_aux) the second
 // half reads P0's tiles again and its results are not stored.
 template <int MF, int TQ, bool CPAD>
 __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double* __restrict__ B, int nt, int64_t ntl,
@@ -73,26 +73,72 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
     const double* Bp0 = B + (int64_t)P0 * ntl * 4096;
     const double* Bp1 = B + (int64_t)(P0 + 1 < n_aux ? P0 + 1 : P0) * ntl * 4096;
     double rb[8], rc[NCR];
-    auto load_b = [&](int J, int k0) {
-        const bool lower = J <= I;
-        const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
+#if defined(__HIP_DEVICE_COMPILE__)
+    // CPAD form: buffer loads whose lane offsets are fixed per orientation
+    // and whose slice offset is a scalar, so a slice's loads need no vector
+    // address arithmetic.  One auxiliary index's tiles span ntl * 32 KiB.
+    __amdgpu_buffer_rsrc_t rs0, rs1, rsc;
+    int boffL[4], boffU[4], coff[NCR];
+    if constexpr (CPAD) {
+        const int tb = (int)(ntl * 4096 * 8);
+        rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Bp0), (short)0, tb, 0x00020000);
+        rs1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Bp1), (short)0, tb, 0x00020000);
+        rsc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(C), (short)0, nt * 64 * cld * 8, 0x00020000);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int off;
-            if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
-            else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
-            rb[r] = Bp0[toff + off];
-            rb[4 + r] = Bp1[toff + off];
+            boffL[r] = (((tid >> 4) + 16 * r) * 64 + (tid & 15)) * 8;     // tile row m, column k
+            boffU[r] = (((tid >> 6) + 4 * r) * 64 + (tid & 63)) * 8;      // tile row k, column m
+        }
+#pragma unroll
+        for (int r = 0; r < NCR; ++r) {
+            const int e = tid + 256 * r;
+            coff[r] = ((e / WS) * cld + e % WS) * 8;
+        }
+    }
+    auto ldb = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+    };
+#endif
+    auto load_b = [&](int J, int k0) {
+        const bool lower = J <= I;
+        const int tile = lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I);
+        if constexpr (CPAD) {
+#if defined(__HIP_DEVICE_COMPILE__)
+            if (lower) {
+                const int so = (tile * 4096 + k0) * 8;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { rb[r] = ldb(rs0, boffL[r], so); rb[4 + r] = ldb(rs1, boffL[r], so); }
+            } else {
+                const int so = (tile * 4096 + k0 * 64) * 8;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { rb[r] = ldb(rs0, boffU[r], so); rb[4 + r] = ldb(rs1, boffU[r], so); }
+            }
+#endif
+        } else {
+            const int64_t toff = (int64_t)tile * 4096;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int off;
+                if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
+                else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
+                rb[r] = Bp0[toff + off];
+                rb[4 + r] = Bp1[toff + off];
+            }
         }
     };
     auto load_c = [&](int J, int k0) {
+        if constexpr (CPAD) {
+#if defined(__HIP_DEVICE_COMPILE__)
+            const int so = ((64 * J + k0) * cld + i0) * 8;
 #pragma unroll
-        for (int r = 0; r < NCR; ++r) {
-            int e = tid + 256 * r, k = e / WS, i = e % WS;
-            int nu = 64 * J + k0 + k, gi = i0 + i;
-            if (CPAD) {
-                if (16 * WS % 256 == 0 || e < 16 * WS) rc[r] = C[(int64_t)nu * cld + gi];
-            } else {
+            for (int r = 0; r < NCR; ++r)
+                if (16 * WS % 256 == 0 || tid + 256 * r < 16 * WS) rc[r] = ldb(rsc, coff[r], so);
+#endif
+        } else {
+#pragma unroll
+            for (int r = 0; r < NCR; ++r) {
+                int e = tid + 256 * r, k = e / WS, i = e % WS;
+                int nu = 64 * J + k0 + k, gi = i0 + i;
                 rc[r] = (e < 16 * WS && nu < N && gi < n_occ) ? C[(int64_t)nu * n_occ + gi] : 0.0;
             }
         }
@@ -720,6 +766,9 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
         if (rem <= 12) { mf = mt - 1; tq = (rem + 3) / 4; }
     }
     const int cld = cpad_ld(n_occ), rows = nt * 64;
+    // buffer-resource offsets are 32-bit: one auxiliary index's packed tiles
+    // and the padded C must each stay under 2 GiB (N below about 22,000)
+    if (ntl * 4096 * 8 > INT32_MAX || (int64_t)rows * cld * 8 > INT32_MAX) return hipErrorInvalidValue;
     cpad_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cp);
     RI_TRY(hipGetLastError());
     switch (mf * 4 + tq) {

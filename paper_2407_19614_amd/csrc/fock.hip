@@ -463,6 +463,7 @@ __device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restr
     const int nsteps = (int)((r1 - r0) / 16);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const bool upper = ti == tj && wn > wm;      // quadrant the reduction never reads
     // wave w moves row pairs 2w and 2w+1 (rows 4w .. 4w+3) of A and of B
     auto issue = [&](int step, int buf) {
         int64_t rb = r0 + (int64_t)step * 16;
@@ -506,6 +507,7 @@ __device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restr
         issue(k + S - 1, (k + S - 1) % S);
         const float* as = As[k % S];
         const float* bs = Bs[k % S];
+        if (!upper)
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             const int row = kk + lk, sw = (row & 3) << 2;
@@ -572,8 +574,38 @@ __device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __rest
     const int nsteps = (int)((r1 - r0) / 16);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    // each wave moves rows 4*wave .. 4*wave+3 of the A and B 16-row slabs
+    // on a diagonal tile the strictly-upper 64 x 64 quadrant is never read
+    // by the reduction: that wave only moves data
+    const bool upper = ti == tj && wn > wm;
+    // each wave moves rows 4*wave .. 4*wave+3 of the A and B 16-row slabs.
+    // A split's rows plus one 16-row look-ahead (the next split's rows or the
+    // zero rows) are reached through buffer resources when their extent fits
+    // a 32-bit offset: lane offsets fixed, the step offset a scalar.
+    const bool bufok = (r1 - r0 + 16) * Npad * 8 <= INT32_MAX;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int nrec = bufok ? (int)((r1 - r0 + 16) * Npad * 8) : 0;
+    const __amdgpu_buffer_rsrc_t rsa =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + r0 * Npad + m0), (short)0, nrec, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsb =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + r0 * Npad + n0), (short)0, nrec, 0x00020000);
+    const int vrow = ((4 * wave) * Npad + 2 * lane) * 8;
+    const int last = (int)(r1 - r0);
+#endif
     auto issue = [&](int step, int buf) {
+        if (bufok) {
+#if defined(__HIP_DEVICE_COMPILE__)
+            const int so = min(step * 16, last) * Npad * 8;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 4 * wave + q;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsa, (lds_void_t)(&As[buf][row * LDR]), 16, vrow + q * Npad * 8,
+                                                         so, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsb, (lds_void_t)(&Bs[buf][row * LDR]), 16, vrow + q * Npad * 8,
+                                                         so, 0, 0);
+            }
+#endif
+            return;
+        }
         int64_t rb = r0 + (int64_t)step * 16;
         if (rb >= rows_pad) rb = rows_pad;          // zero tail rows
 #pragma unroll
@@ -599,6 +631,7 @@ __device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __rest
         issue(k + S - 1, (k + S - 1) % S);
         const double* as = As[k % S];
         const double* bs = Bs[k % S];
+        if (!upper)
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             double a[4], b[4];

@@ -338,35 +338,85 @@ __device__ __forceinline__ f4_t mfma_f32(float a, float b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int MT>
+template <int MT, bool CPAD>
 __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* __restrict__ B, int nt, int64_t ntl,
-                                            const double* __restrict__ C, int N, int n_occ, int n_aux,
-                                            float* __restrict__ Xt, int Npad) {
+                                            const double* __restrict__ C, const float* __restrict__ Cf, int cld,
+                                            int N, int n_occ, int n_aux, float* __restrict__ Xt, int Npad) {
+    // CPAD: C_occ arrives as the FP32 zero-padded copy Cf [64 * nt][cld] and
+    // every load goes through a buffer resource (as in the FP64 form);
+    // otherwise C is FP64 [N][n_occ] with bounds tests.
     constexpr int W = MT * 16;
     __shared__ float Bs[2][16][65];
     __shared__ float Cs[16][W + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int ps = wave >> 1, h = wave & 1;
-    const bool has1 = P0 + 1 < n_aux;
     const float* Bp0 = B + (int64_t)P0 * ntl * 4096;
-    const float* Bp1 = B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096;
+    const float* Bp1 = B + (int64_t)(P0 + 1 < n_aux ? P0 + 1 : P0) * ntl * 4096;
     float rb[8], rc[MT];
-    auto load = [&](int J, int k0) {
-        const bool lower = J <= I;
-        const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
+#if defined(__HIP_DEVICE_COMPILE__)
+    __amdgpu_buffer_rsrc_t rs0, rs1, rsc;
+    int boffL[4], boffU[4], coff[MT];
+    if constexpr (CPAD) {
+        const int tb = (int)(ntl * 4096 * 4);
+        rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bp0), (short)0, tb, 0x00020000);
+        rs1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bp1), (short)0, tb, 0x00020000);
+        rsc = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Cf), (short)0, nt * 64 * cld * 4, 0x00020000);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int off;
-            if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
-            else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
-            rb[r] = Bp0[toff + off];
-            rb[4 + r] = has1 ? Bp1[toff + off] : 0.0f;
+            boffL[r] = (((tid >> 4) + 16 * r) * 64 + (tid & 15)) * 4;
+            boffU[r] = (((tid >> 6) + 4 * r) * 64 + (tid & 63)) * 4;
         }
 #pragma unroll
         for (int r = 0; r < MT; ++r) {
-            int e = tid + 256 * r, k = e / W, i = e % W;
-            int nu = 64 * J + k0 + k, gi = i0 + i;
-            rc[r] = (nu < N && gi < n_occ) ? (float)C[(int64_t)nu * n_occ + gi] : 0.0f;
+            const int e = tid + 256 * r;
+            coff[r] = ((e / W) * cld + e % W) * 4;
+        }
+    }
+    auto ldf = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+    };
+#endif
+    auto load_b = [&](int J, int k0) {
+        const bool lower = J <= I;
+        const int tile = lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I);
+        if constexpr (CPAD) {
+#if defined(__HIP_DEVICE_COMPILE__)
+            if (lower) {
+                const int so = (tile * 4096 + k0) * 4;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { rb[r] = ldf(rs0, boffL[r], so); rb[4 + r] = ldf(rs1, boffL[r], so); }
+            } else {
+                const int so = (tile * 4096 + k0 * 64) * 4;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { rb[r] = ldf(rs0, boffU[r], so); rb[4 + r] = ldf(rs1, boffU[r], so); }
+            }
+#endif
+        } else {
+            const int64_t toff = (int64_t)tile * 4096;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int off;
+                if (lower) { int k = tid & 15, m = (tid >> 4) + 16 * r; off = m * 64 + k0 + k; }
+                else       { int m = tid & 63, k = (tid >> 6) + 4 * r; off = (k0 + k) * 64 + m; }
+                rb[r] = Bp0[toff + off];
+                rb[4 + r] = Bp1[toff + off];
+            }
+        }
+    };
+    auto load_c = [&](int J, int k0) {
+        if constexpr (CPAD) {
+#if defined(__HIP_DEVICE_COMPILE__)
+            const int so = ((64 * J + k0) * cld + i0) * 4;
+#pragma unroll
+            for (int r = 0; r < MT; ++r) rc[r] = ldf(rsc, coff[r], so);
+#endif
+        } else {
+#pragma unroll
+            for (int r = 0; r < MT; ++r) {
+                int e = tid + 256 * r, k = e / W, i = e % W;
+                int nu = 64 * J + k0 + k, gi = i0 + i;
+                rc[r] = (nu < N && gi < n_occ) ? (float)C[(int64_t)nu * n_occ + gi] : 0.0f;
+            }
         }
     };
     auto store = [&](int J) {
@@ -393,13 +443,15 @@ __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* 
         acc64[m][0] = acc64[m][1] = d4_t{0, 0, 0, 0};
     }
     const int nsl = nt * 4;
-    load(0, 0);
+    load_b(0, 0);
+    load_c(0, 0);
     for (int sl = 0; sl < nsl; ++sl) {
         const int J = sl >> 2;
         __syncthreads();
         store(J);
         __syncthreads();
-        if (sl + 1 < nsl) load((sl + 1) >> 2, ((sl + 1) & 3) * 16);
+        const bool more = sl + 1 < nsl;
+        const int Jn = (sl + 1) >> 2, kn = ((sl + 1) & 3) * 16;
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             float b0 = Bs[ps][kk + lk][h * 32 + li], b1 = Bs[ps][kk + lk][h * 32 + 16 + li];
@@ -409,6 +461,8 @@ __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* 
                 acc[m][0] = mfma_f32(a, b0, acc[m][0]);
                 acc[m][1] = mfma_f32(a, b1, acc[m][1]);
             }
+            if (kk == 0 && more) load_b(Jn, kn);
+            if (kk == 4 && more) load_c(Jn, kn);
         }
         if ((sl & 3) == 3) {   // FP32 over one 64-wide nu tile, FP64 across tiles
 #pragma unroll
@@ -437,10 +491,18 @@ __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* 
 
 template <int MT>
 __global__ __launch_bounds__(256, 2) void x2_kernel_f32(const float* __restrict__ B, int nt, int64_t ntl,
-                                                        const double* __restrict__ C, int N, int n_occ, int n_aux,
+                                                        const float* __restrict__ Cf, int cld, int n_occ, int n_aux,
                                                         float* __restrict__ Xt, int Npad) {
     const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    x2_body_f32<MT>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, C, N, n_occ, n_aux, Xt, Npad);
+    x2_body_f32<MT, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, nullptr, Cf, cld, 0,
+                          n_occ, n_aux, Xt, Npad);
+}
+
+__global__ void cpad_f32_kernel(const double* C, int N, int n_occ, int rows, int cld, float* Cf) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cld) return;
+    int r = e / cld, c = e % cld;
+    Cf[e] = (r < N && c < n_occ) ? (float)C[(int64_t)r * n_occ + c] : 0.0f;
 }
 
 // FP32 exchange SYRK on the direct-LDS ring: one wave instruction moves two
@@ -767,8 +829,13 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
         const float* b = (const float*)B;
         float* x = (float*)Xt;
         const int64_t ntl = n_tiles(N);
+        const int cld = cpad_ld(n_occ), rows = nt * 64;
+        if (ntl * 4096 * 4 > INT32_MAX || (int64_t)rows * cld * 4 > INT32_MAX) return hipErrorInvalidValue;
+        float* Cf = (float*)Cp;      // the C workspace holds twice as many floats as the padded FP64 copy
+        cpad_f32_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cf);
+        RI_TRY(hipGetLastError());
         switch (mt) {
-#define XCASE(k) case k: x2_kernel_f32<k><<<grid, 256, 0, st>>>(b, nt, ntl, C, N, n_occ, n_aux, x, Npad); break;
+#define XCASE(k) case k: x2_kernel_f32<k><<<grid, 256, 0, st>>>(b, nt, ntl, Cf, cld, n_occ, n_aux, x, Npad); break;
             XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
 #undef XCASE
             default: return hipErrorInvalidValue;
@@ -907,7 +974,7 @@ __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const
     if (PREC == RI_FP64)
         x2_body_f64<MT, 0, false>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, 0, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
     else
-        x2_body_f32<MT>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, m.N, m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
+        x2_body_f32<MT, false>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, nullptr, 0, m.N, m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
 }
 
 template <int PREC>

@@ -226,105 +226,6 @@ __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict
 }
 
 
-// X^T via direct global->LDS loads: same work split as x2_kernel_f64 (one
-// row-block I, two auxiliary indices per workgroup), but the B^P tile slices
-// and the C_occ slice are moved by global_load_lds into an S-stage LDS ring,
-// 16 B per lane.  That copy cannot transpose, so layouts are chosen per
-// orientation and XOR-swizzled at 16 B granularity to keep fragment reads
-// off shared banks:
-//   tile (I,J), J <= I, rows mu: slot(mu, chunk c) = mu*8 + (c ^ (mu & 7))
-//   tile (J,I), J > I, rows nu:  slot(nu, c)       = nu*32 + (c ^ ((nu & 1) << 3))
-//   C slice, rows nu:            slot(nu, c)       = nu*64 + (c ^ ((nu & 1) << 3))
-// Cp is C_occ zero-padded to [Npad][128 * zc] (zc = occupied chunks of 128).
-template <int MT, int S>
-__global__ __launch_bounds__(256, 2) void x3_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
-                                                        const double* __restrict__ Cp, int cld, int n_occ,
-                                                        int n_aux, double* __restrict__ Xt, int Npad) {
-    __shared__ double Bs[S][2][1024];     // 2 x (64 x 16) per stage
-    __shared__ double Cs[S][2048];        // 16 x 128 per stage
-    const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int I = L % gridDim.x, P0 = 2 * (L / gridDim.x), i0 = blockIdx.z * 128;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-    const int ps = wave >> 1, h = wave & 1;
-    const bool has1 = P0 + 1 < n_aux;
-    const double* Bp[2] = {B + (int64_t)P0 * ntl * 4096, B + (int64_t)(has1 ? P0 + 1 : P0) * ntl * 4096};
-    const int nsl = nt * 4;
-    // wave w issues: B slice of P (w >> 1), instructions 4*(w&1) .. +3; C rows 4w .. 4w+3
-    auto issue = [&](int sl, int buf) {
-        if (sl >= nsl) sl = nsl - 1;                  // look-ahead past the end: reload the last slice
-        const int J = sl >> 2, k0 = (sl & 3) * 16;
-        const bool lower = J <= I;
-        const int64_t toff = (int64_t)(lower ? (I * (I + 1) / 2 + J) : (J * (J + 1) / 2 + I)) * 4096;
-        const double* tp = Bp[ps] + toff;
-#pragma unroll
-        for (int q = 4 * h; q < 4 * h + 4; ++q) {
-            const int slot = q * 64 + lane;
-            const double* g;
-            if (lower) {
-                const int mu = slot >> 3, c = (slot & 7) ^ (mu & 7);
-                g = tp + mu * 64 + k0 + 2 * c;
-            } else {
-                const int nu = slot >> 5, c = (slot & 31) ^ ((nu & 1) << 3);
-                g = tp + (k0 + nu) * 64 + 2 * c;
-            }
-            __builtin_amdgcn_global_load_lds((const void*)g, (lds_void_t)(&Bs[buf][ps][q * 128]), 16, 0, 0);
-        }
-#pragma unroll
-        for (int q = 4 * wave; q < 4 * wave + 4; ++q) {
-            const int c = lane ^ ((q & 1) << 3);
-            const double* g = Cp + (int64_t)(64 * J + k0 + q) * cld + i0 + 2 * c;
-            __builtin_amdgcn_global_load_lds((const void*)g, (lds_void_t)(&Cs[buf][q * 128]), 16, 0, 0);
-        }
-    };
-    d4_t acc[MT][2];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) { acc[m][0] = d4_t{0, 0, 0, 0}; acc[m][1] = d4_t{0, 0, 0, 0}; }
-#pragma unroll
-    for (int s = 0; s < S - 1; ++s) issue(s, s);
-    for (int sl = 0; sl < nsl; ++sl) {
-        __builtin_amdgcn_s_waitcnt(((S - 2) * 8 & 0xF) | ((((S - 2) * 8) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-        __builtin_amdgcn_s_barrier();
-        issue(sl + S - 1, (sl + S - 1) % S);
-        const int buf = sl % S;
-        const bool lower = (sl >> 2) <= I;
-        const double* bs = Bs[buf][ps];
-        const double* cs = Cs[buf];
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            const int nu = kk + lk;
-            double b[2];
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                const int mu = h * 32 + n * 16 + li;
-                int addr;
-                if (lower) addr = 2 * (mu * 8 + ((nu >> 1) ^ (mu & 7))) + (nu & 1);
-                else       addr = 2 * (nu * 32 + ((mu >> 1) ^ ((nu & 1) << 3))) + (mu & 1);
-                b[n] = bs[addr];
-            }
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                const int i = m * 16 + li;
-                const double a = cs[2 * (nu * 64 + ((i >> 1) ^ ((nu & 1) << 3))) + (i & 1)];
-                acc[m][0] = mfma_f64(a, b[0], acc[m][0]);
-                acc[m][1] = mfma_f64(a, b[1], acc[m][1]);
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0)
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    const int P = P0 + ps;
-    if (P >= n_aux) return;
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int n = 0; n < 2; ++n)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int i = i0 + m * 16 + 4 * r + lk;
-                if (i < n_occ) Xt[((int64_t)P * n_occ + i) * Npad + 64 * I + h * 32 + n * 16 + li] = acc[m][n][r];
-            }
-}
-
 __global__ void cpad_kernel(const double* C, int N, int n_occ, int rows, int cld, double* Cp) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= (int64_t)rows * cld) return;
@@ -817,8 +718,6 @@ hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, 
 int cpad_ld(int n_occ) { return (n_occ + 127) / 128 * 128; }
 int64_t cpad_elems(int N, int n_occ) { return (int64_t)n_tiles_1d(N) * 64 * cpad_ld(n_occ); }
 
-int g_x_variant = 0;   // 0: register-staged x2 kernel, 1: direct-LDS x3 kernel
-void set_x_variant(int v) { g_x_variant = v; }
 
 hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, double* Cp, void* Xt,
                        hipStream_t st) {
@@ -846,18 +745,6 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
     const double* b = (const double*)B;
     double* x = (double*)Xt;
     const int64_t ntl = n_tiles(N);
-    if (g_x_variant == 1) {
-        const int cld = cpad_ld(n_occ), rows = nt * 64;
-        cpad_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cp);
-        RI_TRY(hipGetLastError());
-        switch (mt) {
-#define XCASE(k) case k: x3_kernel_f64<k, 2><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, n_occ, n_aux, x, Npad); break;
-            XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
-#undef XCASE
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
     // occupied rows of one 128-wide chunk: whole 16-row tiles plus, when the
     // last tile would hold 12 rows or fewer, 4-row quads in its place
     int mf = mt, tq = 0;

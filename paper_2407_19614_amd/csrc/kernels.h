@@ -25,7 +25,6 @@ hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, 
 // Xt[P][i][mu] (row stride Npad = 64 * tiles) = (B^P C_occ)^T
 // Cp: workspace for C_occ zero-padded to [64 * tiles][cpad_ld(n_occ)].
 int cpad_ld(int n_occ);
-void set_x_variant(int v);
 int64_t cpad_elems(int N, int n_occ);
 hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C,
                        double* Cp, void* Xt, hipStream_t st);

@@ -151,7 +151,11 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
  *   C_occ   [N][n_occ] row-major.
  *   J, K    [N][N] out, full symmetric.
  *   gamma   [n_aux] out (may be NULL).
- * Asynchronous: no host synchronisation. */
+ * Asynchronous: no host synchronisation.  The gamma/J part runs on a
+ * library-owned side stream of the current device (one per device, default
+ * priority, created on first use), concurrently with the exchange; `stream`
+ * waits for it before any later work on `stream`, so the outputs are ordered
+ * on `stream` as if all work ran there.  Also used by ri_energy's SCF loop. */
 int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
                    const double* Bc, const int32_t* pairs, int64_t n_pairs,
                    const double* C_occ, double* J, double* K, double* gamma,
@@ -163,7 +167,9 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
  *   events[0] before the gamma/J contraction, events[1] before the exchange
  *   half-transform X^P = B^P C_occ, events[2] before the K = sum X X^T SYRK
  *   and its reduction, events[3] after the last kernel.
- * events: four events created by the caller (host array). */
+ * events: four events created by the caller (host array).  Every phase
+ * runs on `stream`, in order (no side stream), so the events bracket each
+ * phase alone. */
 int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
                          const double* Bc, const int32_t* pairs, int64_t n_pairs,
                          const double* C_occ, double* J, double* K, double* gamma,

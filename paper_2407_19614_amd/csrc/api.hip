@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -225,23 +226,65 @@ GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_
     return w;
 }
 
+// One non-blocking side stream per device (default priority), created on
+// first use and kept for the life of the process.
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
+// Fork/join of the caller's stream with the side stream: events are made per
+// call, so concurrent callers never wait on each other's records.
+struct Fork {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool open(hipStream_t st) {
+        side = side_stream();
+        if (!side || hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(fork, st) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess) {
+            side = nullptr;
+            return false;
+        }
+        return true;
+    }
+    ~Fork() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
+// The Coulomb part (pair densities, gamma, J) reads only B_c and C_occ and
+// is bound by HBM bandwidth; the exchange contractions are bound by MFMA
+// throughput and touch none of its buffers.  Outside the phase-timed form the
+// Coulomb part runs on the side stream, concurrently with the exchange, and
+// the caller's stream waits for it before the call returns.
 int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const double* C, double* J, double* K, double* gamma, const FockWS& w,
                   hipStream_t st, hipEvent_t* ev = nullptr) {
     double* g = gamma ? gamma : w.gamma;
+    Fork fk;
+    const bool overlap = !ev && fk.open(st);
     if (ev) HIPC(hipEventRecord(ev[0], st));
-    HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, st));
+    HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, overlap ? fk.side : st));
+    if (overlap) HIPC(hipEventRecord(fk.join, fk.side));
     if (ev) HIPC(hipEventRecord(ev[1], st));
     if (is_bf16(prec)) {
         HIPC(ri::x_transform_bf16(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
         if (ev) HIPC(hipEventRecord(ev[2], st));
         HIPC(ri::k_syrk_bf16(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
-        if (ev) HIPC(hipEventRecord(ev[3], st));
-        return RI_OK;
+    } else {
+        HIPC(x_any(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, Bc, pairs, n_pairs, w.sw, st));
+        if (ev) HIPC(hipEventRecord(ev[2], st));
+        HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
     }
-    HIPC(x_any(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, Bc, pairs, n_pairs, w.sw, st));
-    if (ev) HIPC(hipEventRecord(ev[2], st));
-    HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
+    if (overlap) HIPC(hipStreamWaitEvent(st, fk.join, 0));
     if (ev) HIPC(hipEventRecord(ev[3], st));
     return RI_OK;
 }

@@ -326,7 +326,7 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True)
     import torch
     import synth
     import paper_2407_19614_amd as P
-    from paper_2407_19614_amd.binding import batch_autotune, energy_batched
+    from paper_2407_19614_amd.binding import batch_autotune, energy_batched, prepare_batch
     systems = synth.batched_systems(n_mol)
     prec = P.FP32 if prec_name == "fp32" else P.FP64
     tol = dict(tol_E=1e-7, tol_err=1e-5) if prec == P.FP32 else dict(tol_E=1e-10, tol_err=1e-8)
@@ -340,12 +340,8 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True)
     tune = None
     for w0 in range(0, len(systems), wave):
         ts = time.perf_counter()
-        probs = []
-        for s in systems[w0:w0 + wave]:
-            pr = P.RIProblem(s, prec=prec)
-            pr.build_3c()
-            pr.metric_factor(prec)
-            probs.append(pr)
+        # per-molecule 3c, metric factor and B, four molecules' launches in flight at once
+        probs = prepare_batch(systems[w0:w0 + wave], prec, workers=4)
         torch.cuda.synchronize()
         t_setup += time.perf_counter() - ts
         if tune is None and autotune:

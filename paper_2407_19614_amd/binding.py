@@ -440,6 +440,51 @@ def _batch_ws(n, sysarr, mols, prec, dev):
     return torch.empty(nb, dtype=torch.uint8, device=dev), nb
 
 
+_PREP_STREAMS = {}
+
+
+def prepare_batch(systems, prec=FP64, workers=4, device="cuda"):
+    """RIProblem objects for independent systems, each after build_3c and
+    metric_factor in `prec`.  The setups of different systems share no data,
+    and each is a chain of small launches with host reads of sizes, so
+    `workers` host threads each issue their share on a stream of their own
+    and the launches of several systems overlap on the device.  The streams
+    are made once per device and reused, so memory freed by one batch is
+    found again by the next (the caching allocator keeps freed blocks per
+    stream).  Returns when every system's data is complete on the device."""
+    import threading
+    import torch
+    dev = torch.device(device)
+    key = (dev.index if dev.index is not None else torch.cuda.current_device(), int(workers))
+    if key not in _PREP_STREAMS:
+        _PREP_STREAMS[key] = [torch.cuda.Stream(device=dev) for _ in range(workers)]
+    streams = _PREP_STREAMS[key]
+    out = [None] * len(systems)
+    errors = []
+
+    def work(k):
+        try:
+            with torch.cuda.stream(streams[k]):
+                for i in range(k, len(systems), workers):
+                    pr = RIProblem(systems[i], device=dev, prec=prec)
+                    pr.build_3c()
+                    pr.metric_factor(prec)
+                    out[i] = pr
+        except BaseException as e:        # re-raised on the calling thread
+            errors.append(e)
+        finally:
+            streams[k].synchronize()
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(workers)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
+    return out
+
+
 def batch_autotune(problems, prec=FP64):
     """Times the candidate launch shapes of the batched SCF on these problems
     (each after build_3c and metric_factor in `prec`) and returns the chosen

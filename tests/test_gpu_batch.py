@@ -102,3 +102,28 @@ def test_batched_autotune_and_forced_shapes_agree():
         for k, r in enumerate(res):
             assert r["converged"]
             assert abs(r["E_total"] - E0[k]) < 1e-9, (k, r["E_total"], E0[k])
+
+
+def test_prepare_batch_matches_sequential_setup():
+    """Setups issued from several host threads on their own streams give the
+    same pairs, fitted tensors, factors and packed B as one-by-one setup, and
+    the batched SCF on them the same energies."""
+    need_gpu()
+    import torch
+    import paper_2407_19614_amd as P
+    from paper_2407_19614_amd.binding import energy_batched, prepare_batch
+    print("case: prepare_batch, 6 molecules, 4 workers", flush=True)
+    systems = small_batch()
+    par = prepare_batch(systems, P.FP64, workers=4)
+    for s, pp in zip(systems, par):
+        pr = P.RIProblem(s)
+        pr.build_3c()
+        pr.metric_factor(P.FP64)
+        torch.cuda.synchronize()
+        assert pp.n_pairs == pr.n_pairs
+        for name in ("pairs", "T", "L", "Linv", "B"):
+            assert torch.equal(getattr(pp, name), getattr(pr, name)), name
+    res, _, _ = energy_batched(par, P.FP64, tol_E=1e-11, tol_err=1e-9)
+    for s, r in zip(systems, res):
+        ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
+        assert r["converged"] and abs(r["E_total"] - ref.E) < 1e-9

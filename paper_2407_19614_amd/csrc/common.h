@@ -64,38 +64,42 @@ __device__ __forceinline__ double boys_f1(double t) {
 }
 
 // Lower Cholesky of an nb x nb (nb <= 64) block held in LDS as L[64][65]
-// (rows/columns beyond nb set to the identity by the caller), in place, and
-// its inverse: thread t (64 threads) writes column t of L^{-1} through
-// store(i, t, value).  A pivot that is not positive is reported through
+// (rows/columns beyond nb set to the identity by the caller), in place on
+// and below the diagonal, and its inverse, written through store(i, c, value)
+// for all 64 x 64 entries (zero above the diagonal, identity beyond nb).  A
+// workgroup of NT threads (NT / 64 waves) runs it: at step j the pivot and
+// column j are finished, row j of the inverse is scaled, and then every wave
+// takes rows i > j of both the trailing Cholesky update and the forward
+// elimination X_i -= L_ij X_j, one column per lane, so each step is two
+// barriers of uniform work.  A pivot that is not positive is reported through
 // bad(j) and replaced by 1.
-template <class Bad, class Store>
+template <int NT, class Bad, class Store>
 __device__ __forceinline__ void potrf_inv_block64(double (*L)[65], int nb, Bad bad, Store store) {
-    const int t = threadIdx.x;
+    static_assert(NT % 64 == 0, "whole waves");
+    constexpr int NW = NT / 64;
+    __shared__ double X[64][65];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int i = wv; i < 64; i += NW) X[i][lane] = i == lane ? 1.0 : 0.0;
+    __syncthreads();
     for (int j = 0; j < nb; ++j) {
-        if (t == j) {
-            double d = L[j][j];
-            if (!(d > 0.0)) {
-                bad(j);
-                d = 1.0;
-            }
-            L[j][j] = sqrt(d);
+        const double d = L[j][j];
+        const double piv = sqrt(d > 0.0 ? d : 1.0);
+        if (wv == 0) {
+            if (lane == 0 && !(d > 0.0)) bad(j);
+            if (lane > j && lane < nb) L[lane][j] /= piv;      // column j of the factor
+            if (lane <= j) X[j][lane] /= piv;                   // row j of the inverse
         }
         __syncthreads();
-        if (t > j && t < nb) L[t][j] /= L[j][j];
-        __syncthreads();
-        if (t > j && t < nb)
-            for (int c = j + 1; c <= t; ++c) L[t][c] -= L[t][j] * L[c][j];
+        if (t == 0) L[j][j] = piv;
+        const double lcj = lane > j ? L[lane][j] : 0.0, xjc = X[j][lane];
+        for (int i = j + 1 + wv; i < nb; i += NW) {
+            const double lij = L[i][j];
+            if (lane > j && lane <= i) L[i][lane] -= lij * lcj;
+            if (lane <= j) X[i][lane] -= lij * xjc;
+        }
         __syncthreads();
     }
-    // column t of L^{-1} by forward substitution; thread t owns column t of X
-    // (kept in LDS: a per-thread array indexed from t would live in scratch)
-    __shared__ double X[64][65];
-    for (int i = 0; i < 64; ++i) {
-        double s = (i == t) ? 1.0 : 0.0;
-        for (int k = t; k < i; ++k) s -= L[i][k] * X[k][t];
-        X[i][t] = (i >= t) ? s / L[i][i] : 0.0;
-    }
-    for (int i = 0; i < 64; ++i) store(i, t, X[i][t]);
+    for (int i = wv; i < 64; i += NW) store(i, lane, X[i][lane]);
 }
 
 // ------------------------------------------------------------ launch helpers

@@ -240,17 +240,18 @@ __global__ __launch_bounds__(256, 2) void gemm_grouped128_kernel(const ri::GemmD
 
 // Factor one 64x64 diagonal block in place (lower Cholesky) and write the
 // inverse of its factor to Dinv (64x64, lower, identity padding beyond n).
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int n, int64_t lda, int kb,
-                                                         double* Dinv, int* bad) {
+// One workgroup of 4 waves; rows move with lanes along columns (coalesced).
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int n, int64_t lda, int kb,
+                                                          double* Dinv, int* bad) {
     __shared__ double L[64][65];
-    const int t = threadIdx.x, o = kb * 64, nb = min(64, n - o);
-    for (int c = 0; c < 64; ++c)
-        L[t][c] = (t < nb && c < nb) ? A[(int64_t)(o + t) * lda + o + c] : (t == c ? 1.0 : 0.0);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, o = kb * 64, nb = min(64, n - o);
+    for (int r = wv; r < 64; r += 4)
+        L[r][lane] = (r < nb && lane < nb) ? A[(int64_t)(o + r) * lda + o + lane] : (r == lane ? 1.0 : 0.0);
     __syncthreads();
-    potrf_inv_block64(L, nb, [&](int j) { atomicMin(bad, o + j); },
-                      [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
-    for (int c = 0; c < 64; ++c)
-        if (t < nb && c < nb) A[(int64_t)(o + t) * lda + o + c] = (c <= t) ? L[t][c] : 0.0;
+    potrf_inv_block64<256>(L, nb, [&](int j) { atomicMin(bad, o + j); },
+                           [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
+    for (int r = wv; r < nb; r += 4)
+        if (lane < nb) A[(int64_t)(o + r) * lda + o + lane] = (lane <= r) ? L[r][lane] : 0.0;
 }
 
 __global__ void zero_upper_kernel(double* A, int n, int64_t lda) {
@@ -379,7 +380,7 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
     const int nb = (n + 63) / 64;
     for (int k = 0; k < nb; ++k) {
         const int o = k * 64, w = min(64, n - o), rest = n - o - w;
-        potrf_diag_kernel<<<1, 64, 0, s>>>(A, n, lda, k, dwork + (int64_t)k * 4096, d_bad);
+        potrf_diag_kernel<<<1, 256, 0, s>>>(A, n, lda, k, dwork + (int64_t)k * 4096, d_bad);
         RI_TRY(hipGetLastError());
         if (rest > 0) {
             double* panel = A + (int64_t)(o + w) * lda + o;

@@ -309,7 +309,7 @@ struct Table {
 struct Plan {
     int n_mol = 0, prec = 0, tc2_iters = 48;
     MolDesc* d = nullptr;
-    Table n2, rows, pairs, aux, syrk, tail, x[9];
+    Table n2, rows, pairs, aux, syrk, tail, cq, x[33];   // x[xs], xs = 4 * tiles + quads
     // members on 64 x 64 tiles in t, on 128 x 128 tiles in t128
     struct G { ri::GemmDesc* d = nullptr; Table t, t128; bool ta = false, tb = false; };
     G g_lfx, g_t2, g_x2, g_y, g_mo, g_cp, g_c, g_d, g_fd, g_fds;
@@ -358,8 +358,9 @@ hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
     // Fock build
     HC(ri::zero_tail_b(d, p.tail.prefix, nm, p.tail.total, p.prec, st));
     HC(ri::gamma_j_b(d, nm, p.pairs.prefix, p.pairs.total, p.aux.prefix, p.aux.total, p.n2.prefix, p.n2.total, st));
-    for (int mt = 1; mt <= 8; ++mt)
-        if (p.x[mt].total > 0) HC(ri::x_transform_b(d, p.x[mt].prefix, nm, p.x[mt].total, mt, p.prec, st));
+    if (p.prec == RI_FP64) HC(ri::cpad_b(d, p.cq.prefix, nm, p.cq.total, st));
+    for (int xs = 1; xs <= 32; ++xs)
+        if (p.x[xs].total > 0) HC(ri::x_transform_b(d, p.x[xs].prefix, nm, p.x[xs].total, xs, p.prec, st));
     HC(ri::syrk_b(d, p.syrk.prefix, nm, p.syrk.total, p.prec, st));
     HC(ri::kreduce_b(d, p.rows.prefix, nm, p.rows.total, st));
     // F, D, energy, error, convergence
@@ -447,7 +448,12 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         m.npad = ri::xt_ld(N);
         m.ntl = ri::n_tiles(N);
         m.n_pairs = mol[i].n_pairs;
-        m.mt = (no + 15) / 16;
+        {
+            // FP64: whole 16-row tiles, and 4-row quads in place of a last tile of 12 rows or
+            // fewer; FP32: whole tiles only
+            const int mt = (no + 15) / 16, rem = no - 16 * (mt - 1);
+            m.xs = (prec == RI_FP64 && rem <= 12) ? 4 * (mt - 1) + (rem + 3) / 4 : 4 * mt;
+        }
         const int64_t rows = (int64_t)na * no;
         m.rows_pad = (rows + 15) / 16 * 16;
         if (tune) {
@@ -474,6 +480,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         }
         m.Y = cv.take<double>((int64_t)N * no);
         m.Cp = cv.take<double>((int64_t)N * no);
+        m.Cq = prec == RI_FP64 ? cv.take<double>((int64_t)m.nt * 64 * 64) : nullptr;
         m.Mo = cv.take<double>((int64_t)no * no);
         m.LinvM = cv.take<double>(64 * 64);
         m.dinvM = cv.take<double>(((N + 63) / 64) * 4096);   // Cholesky diagonal blocks of S
@@ -507,10 +514,12 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
     mk(c, p.syrk);
     for (int i = 0; i < n_mol; ++i) c[i] = 16;
     mk(c, p.tail);
-    for (int mt = 1; mt <= 8; ++mt) {
+    for (int i = 0; i < n_mol; ++i) c[i] = hp.mols[i].nt;
+    mk(c, p.cq);
+    for (int xs = 1; xs <= 32; ++xs) {
         for (int i = 0; i < n_mol; ++i)
-            c[i] = hp.mols[i].mt == mt ? hp.mols[i].nt * ((hp.mols[i].n_aux + 1) / 2) : 0;
-        mk(c, p.x[mt]);
+            c[i] = hp.mols[i].xs == xs ? hp.mols[i].nt * ((hp.mols[i].n_aux + 1) / 2) : 0;
+        mk(c, p.x[xs]);
     }
     // grouped GEMMs: member i of each
     // tunable: the member runs on the molecule's tuned tile (else on 64 x 64)

@@ -851,17 +851,33 @@ hipError_t gamma_j_pairs(const double* Bc, const int32_t* pairs, int64_t n_pairs
 // ------------------------------------------------------------ batched forms
 namespace {
 
-template <int MT, int PREC>
+// xs = 4 MF + TQ: FP64 takes MF whole tiles and TQ quads from the padded Cq
+// ([64 nt][64], buffer loads); FP32 (TQ = 0) reads C directly.
+template <int MF, int TQ, int PREC>
 __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
     int mol, loc;
     ri::decode_item(prefix, n_mol, blockIdx.x, mol, loc);
     const ri::MolDesc& m = d[mol];
-    if (!m.state[0] || m.mt != MT) return;
+    if (!m.state[0] || m.xs != 4 * MF + TQ) return;
     const int I = loc % m.nt, P0 = 2 * (loc / m.nt);
-    if (PREC == RI_FP64)
-        x2_body_f64<MT, 0, false>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.C, 0, m.N, m.n_occ, m.n_aux, (double*)m.Xt, m.npad);
+    if constexpr (PREC == RI_FP64)
+        x2_body_f64<MF, TQ, true>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.Cq, 64, m.N, m.n_occ, m.n_aux,
+                                  (double*)m.Xt, m.npad);
     else
-        x2_body_f32<MT, false>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, nullptr, 0, m.N, m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
+        x2_body_f32<MF, false>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, nullptr, 0, m.N, m.n_occ, m.n_aux,
+                               (float*)m.Xt, m.npad);
+}
+
+// one block per 64-row block of each active molecule: Cq = C zero-padded
+__global__ void cpad_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
+    int mol, blk;
+    ri::decode_item(prefix, n_mol, blockIdx.x, mol, blk);
+    const ri::MolDesc& m = d[mol];
+    if (!m.state[0]) return;
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int r = 64 * blk + (e >> 6), c = e & 63;
+        m.Cq[(int64_t)r * 64 + c] = (r < m.N && c < m.n_occ) ? m.C[(int64_t)r * m.n_occ + c] : 0.0;
+    }
 }
 
 template <int PREC>
@@ -963,18 +979,30 @@ __global__ void jpair_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mo
 
 namespace ri {
 
-hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int mt, int prec, hipStream_t st) {
+hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int xs, int prec, hipStream_t st) {
     if (total <= 0) return hipSuccess;
-#define XB(k)                                                                                           \
-    case k:                                                                                             \
-        if (prec == RI_FP64) x_b_kernel<k, RI_FP64><<<total, 256, 0, st>>>(d, prefix, n_mol);         \
-        else x_b_kernel<k, RI_FP32><<<total, 256, 0, st>>>(d, prefix, n_mol);                          \
-        break;
-    switch (mt) {
-        XB(1) XB(2) XB(3) XB(4) XB(5) XB(6) XB(7) XB(8)
-        default: return hipErrorInvalidValue;
-    }
+    if (prec == RI_FP64) {
+        switch (xs) {
+#define XB(f, q) case 4 * f + q: x_b_kernel<f, q, RI_FP64><<<total, 256, 0, st>>>(d, prefix, n_mol); break;
+            XB(0, 1) XB(0, 2) XB(0, 3) XB(1, 0) XB(1, 1) XB(1, 2) XB(1, 3) XB(2, 0)
+            XB(2, 1) XB(2, 2) XB(2, 3) XB(3, 0) XB(3, 1) XB(3, 2) XB(3, 3) XB(4, 0)
 #undef XB
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (xs) {
+#define XB(f) case 4 * f: x_b_kernel<f, 0, RI_FP32><<<total, 256, 0, st>>>(d, prefix, n_mol); break;
+            XB(1) XB(2) XB(3) XB(4)
+#undef XB
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t cpad_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    cpad_b_kernel<<<total, 256, 0, st>>>(d, prefix, n_mol);
     return hipGetLastError();
 }
 

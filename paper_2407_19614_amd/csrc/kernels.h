@@ -103,7 +103,8 @@ void set_hip_error(const char* text);   // text returned by ri_last_hip_error
 // kernels run over work items of all molecules: a per-kernel prefix table
 // (device, n_mol + 1 ints) maps each linear block index to (molecule, local).
 struct MolDesc {
-    int N, n_aux, n_occ, nt, npad, ks, mt, diis_n;
+    int N, n_aux, n_occ, nt, npad, ks, diis_n;
+    int xs;       // X launch shape: 4 * (whole 16-row occupied tiles) + (trailing 4-row quads)
     int64_t n_pairs, ntl, rows_pad, chunk;
     double tol_E, tol_err;
     const int32_t* pairs;
@@ -112,6 +113,7 @@ struct MolDesc {
     double *C, *J, *K, *gamma, *dpair, *part;
     void* Xt;
     double *S, *H, *LinvS, *F, *D, *T1, *T2, *E, *Fx, *X, *X2, *Y, *Cp, *Mo, *LinvM, *dinvM;
+    double* Cq;   // C_occ zero-padded to [64 * nt][64] (FP64 exchange)
     double *dF[8], *dE[8];
     double *Bmat, *coef, *scal;
     int* state;   // 0 active, 1 iteration, 2 DIIS pushes, 3 converged, 4.. DIIS slot order [8]
@@ -142,7 +144,10 @@ __device__ __forceinline__ void decode_item(const int* prefix, int n_mol, int L,
 }
 
 // batched Fock build pieces (fock.hip); `prec` is RI_FP64 or RI_FP32 for all molecules
-hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int mt, int prec, hipStream_t st);
+// X for the molecules whose xs equals `xs` (one launch per shape present)
+hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int xs, int prec, hipStream_t st);
+// Cq of every active molecule from its C (prefix counts 64-row blocks)
+hipError_t cpad_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st);
 hipError_t syrk_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);
 hipError_t kreduce_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st);
 hipError_t zero_tail_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);

@@ -202,7 +202,7 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     return w;
 }
 
-struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part, *Cp; void* Xt; float* Xt32; SlabWS sw; };
+struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part, *Cp, *WY; void* Xt; float* Xt32; SlabWS sw; };
 GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec,
                   bool comp = false) {
     GradWS w;
@@ -220,6 +220,7 @@ GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_
     w.Zx = a.take<double>((int64_t)n_aux * n_aux);
     w.part = a.take<double>((int64_t)(3 * ri::GRAD_BLOCKS + 1) * 3 * std::max(n_centres, 1));
     w.Cp = a.take<double>(ri::cpad_elems(N, n_occ));
+    w.WY = a.take<double>((int64_t)ri::grad_slab(N, n_aux) * N * N);   // U^P C^T, one slab of P
     // X^T for B_ij, reused afterwards for U^P = C Xi^P ([n_aux][N][n_occ])
     w.Xt = a.take<char>((int64_t)n_aux * n_occ * Npad * 8 + 8);
     w.Xt32 = prec == RI_FP32 ? a.take<float>((int64_t)n_aux * n_occ * Npad) : nullptr;
@@ -656,7 +657,7 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     const int64_t rowlen = 3 * (int64_t)nc;
     HIPC(ri::grad_one_electron(sys, w.D, w.W, w.part, st));
     HIPC(ri::grad_metric(sys, w.Zx, w.c, w.part + GB * rowlen, st));
-    HIPC(ri::grad_three_centre(sys, pairs, n_pairs, U, C, no, w.D, w.c, w.part + 2 * GB * rowlen, st));
+    HIPC(ri::grad_three_centre(sys, pairs, n_pairs, U, C, no, w.D, w.c, w.WY, w.part + 2 * GB * rowlen, st));
     HIPC(ri::grad_nuclear(sys, w.part + 3 * GB * rowlen, st));
     HIPC(ri::grad_reduce(w.part, 3 * GB + 1, nc, grad, st));
     return RI_OK;

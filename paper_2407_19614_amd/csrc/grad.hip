@@ -5,6 +5,8 @@
 // block, then a deterministic row reduction.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace {
 
 constexpr double TWO_PI_52 = 34.98683665524972;   // 2 pi^{5/2}
@@ -20,6 +22,13 @@ __device__ void flush(double* g, int nc3, double* part) {
     __syncthreads();
     double* row = part + (int64_t)blockIdx.x * nc3;
     for (int i = threadIdx.x; i < nc3; i += blockDim.x) row[i] = g[i];
+}
+
+// as flush, adding to the block's row (launches over several slabs)
+__device__ void flush_add(double* g, int nc3, double* part) {
+    __syncthreads();
+    double* row = part + (int64_t)blockIdx.x * nc3;
+    for (int i = threadIdx.x; i < nc3; i += blockDim.x) row[i] += g[i];
 }
 
 // sum over all (mu, nu) of D h'_mu_nu - W S'_mu_nu.
@@ -105,23 +114,21 @@ __global__ __launch_bounds__(256) void g2c_kernel(const double* xyz, const int32
 
 // sum_P sum_pairs w Y^P_mu_nu (mu nu|P)',  Y = c_P D_mu_nu - 2 (U^P C^T)_mu_nu,
 // U^P = C Xi^P.  Work items are (P, pair) with pairs fastest.
+// Auxiliary indices P0 .. P0 + np - 1: WY[P - P0][mu][nu] = (U^P C^T)_mu_nu
+// (mu >= nu); contributions are added to the block's partial row.
 __global__ __launch_bounds__(256) void g3c_kernel(const double* xyz, const int32_t* fc, const double* fe,
-                                                  const int32_t* ac, const double* ae, int na, int nc,
-                                                  const int32_t* pairs, int64_t n_pairs, const double* U,
-                                                  const double* C, int n_occ, const double* D, int N,
-                                                  const double* cv, double* part) {
+                                                  const int32_t* ac, const double* ae, int P0, int np, int nc,
+                                                  const int32_t* pairs, int64_t n_pairs, const double* WY,
+                                                  const double* D, int N, const double* cv, double* part) {
     __shared__ double g[3 * MAXC];
     for (int i = threadIdx.x; i < 3 * nc; i += 256) g[i] = 0.0;
     __syncthreads();
-    const int64_t total = (int64_t)na * n_pairs;
+    const int64_t total = (int64_t)np * n_pairs;
     for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        int P = e / n_pairs;
+        const int pl = (int)(e / n_pairs), P = P0 + pl;
         int64_t q = e % n_pairs;
         int mu = pairs[2 * q], nu = pairs[2 * q + 1];
-        const double* u = U + ((int64_t)P * N + mu) * n_occ;
-        const double* cr = C + (int64_t)nu * n_occ;
-        double v = 0.0;
-        for (int i = 0; i < n_occ; ++i) v += u[i] * cr[i];
+        const double v = WY[((int64_t)pl * N + mu) * N + nu];
         double y = (cv[P] * D[(int64_t)mu * N + nu] - 2.0 * v) * (mu == nu ? 1.0 : 2.0);
         double a = fe[mu], b = fe[nu];
         int ca = fc[mu], cb = fc[nu], cp = ac[P];
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(256) void g3c_kernel(const double* xyz, const int32
         lds_add3(g, cb, Bx, By, Bz);
         lds_add3(g, cp, -(Ax + Bx), -(Ay + By), -(Az + Bz));
     }
-    flush(g, 3 * nc, part);
+    flush_add(g, 3 * nc, part);
 }
 
 __global__ __launch_bounds__(256) void gnuc_kernel(const double* xyz, const double* Z, int nc, double* part) {
@@ -206,13 +213,28 @@ hipError_t grad_metric(const ri_system* s, const double* Zx, const double* c, do
     g2c_kernel<<<GRAD_BLOCKS, 256, 0, st>>>(s->xyz, s->aux_centre, s->aux_exp, s->n_aux, s->n_centres, Zx, c, part);
     return hipGetLastError();
 }
+int grad_slab(int N, int n_aux) {
+    const int64_t per = (int64_t)N * N * 8;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n_aux, (int64_t(1) << 30) / per));
+}
+
 hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n_pairs, const double* U,
-                             const double* C, int n_occ, const double* D, const double* c, double* part,
-                             hipStream_t st) {
+                             const double* C, int n_occ, const double* D, const double* c, double* WY,
+                             double* part, hipStream_t st) {
     if (s->n_centres > MAXC) return hipErrorInvalidValue;
-    g3c_kernel<<<GRAD_BLOCKS, 256, 0, st>>>(s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, s->n_aux,
-                                            s->n_centres, pairs, n_pairs, U, C, n_occ, D, s->n_fn, c, part);
-    return hipGetLastError();
+    const int N = s->n_fn, na = s->n_aux, ns = grad_slab(N, na);
+    RI_TRY(fill(part, 0.0, (int64_t)GRAD_BLOCKS * 3 * s->n_centres, st));
+    if (n_pairs == 0) return hipSuccess;
+    for (int P0 = 0; P0 < na; P0 += ns) {
+        const int np = std::min(ns, na - P0);
+        // WY[p] = U^{P0+p} C^T on the tiles holding mu >= nu
+        RI_TRY(gemm_f64(false, true, N, N, n_occ, 1.0, U + (int64_t)P0 * N * n_occ, n_occ, (int64_t)N * n_occ, C,
+                        n_occ, 0, 0.0, WY, N, (int64_t)N * N, np, 0, 1, st));
+        g3c_kernel<<<GRAD_BLOCKS, 256, 0, st>>>(s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, P0, np,
+                                                s->n_centres, pairs, n_pairs, WY, D, N, c, part);
+        RI_TRY(hipGetLastError());
+    }
+    return hipSuccess;
 }
 hipError_t grad_nuclear(const ri_system* s, double* part, hipStream_t st) {
     gnuc_kernel<<<1, 256, 0, st>>>(s->xyz, s->Z, s->n_centres, part);

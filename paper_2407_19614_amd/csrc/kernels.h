@@ -74,9 +74,14 @@ namespace ri {
 constexpr int GRAD_BLOCKS = 1024;
 hipError_t grad_one_electron(const ri_system* s, const double* D, const double* W, double* part, hipStream_t st);
 hipError_t grad_metric(const ri_system* s, const double* Z, const double* c, double* part, hipStream_t st);
+// Three-centre term.  (U^P C^T)_mu_nu (U^P = C Xi^P, [n_aux][N][n_occ]) is formed
+// on MFMA for the lower 64 x 64 tiles, grad_slab(N, n_aux) auxiliary indices at
+// a time, into WY (workspace of grad_slab * N * N doubles), and the derivative
+// kernel reads it at the significant pairs.
+int grad_slab(int N, int n_aux);
 hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n_pairs, const double* U,
-                             const double* C, int n_occ, const double* D, const double* c, double* part,
-                             hipStream_t st);
+                             const double* C, int n_occ, const double* D, const double* c, double* WY,
+                             double* part, hipStream_t st);
 hipError_t grad_nuclear(const ri_system* s, double* part, hipStream_t st);
 hipError_t grad_reduce(const double* part, int rows, int n_centres, double* grad, hipStream_t st);
 hipError_t gamma_only(const double* Bc, const int32_t* pairs, int64_t n_pairs, int n_aux, int n_occ,

@@ -170,7 +170,7 @@ hipError_t jk_density(const double* Bc, const int32_t* pairs, int64_t n_pairs, i
 struct EnergyWS {
     double *S, *H, *Ls, *LinvS, *J, *K, *F, *D, *T1, *T2, *E, *Fx, *X, *X2;
     double *dF[8], *dE[8];
-    double *Bmat, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal;
+    double *Bmat, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal, *red;
     int* bad;
     FockWS fock;
     DensityWS dens;
@@ -196,6 +196,7 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     w.dinvS = a.take<double>((int64_t)((N + 63) / 64) * 4096);
     w.dinvM = a.take<double>((int64_t)((n_occ + 63) / 64) * 4096);
     w.scal = a.take<double>(32);
+    w.red = a.take<double>(ri::red_elems(N));   // reduction partials
     w.bad = a.take<int>(2);
     w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, comp);
     w.dens = carve_density(a, N, n_aux, n_pairs);
@@ -299,7 +300,7 @@ int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool hav
     const int64_t n2 = (int64_t)N * N;
     HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.LinvS, N, 0, Fx, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
     HIPC(ri::gemm_f64(false, true, N, N, N, 1.0, w.T1, N, 0, w.LinvS, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
-    HIPC(ri::gershgorin(w.T2, N, w.scal + 16, st));
+    HIPC(ri::gershgorin(w.T2, N, w.scal + 16, w.red, st));
     HIPC(ri::tc2_init(w.T2, w.scal + 16, N, w.X, st));
     double idem = 1.0;
     int it = 0, extra = -1;
@@ -550,11 +551,11 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
         if (rc) return rc;
         HIPC(ri::fock_assemble(w.H, w.J, w.K, w.F, n2, st));
         HIPC(ri::gemm_f64(false, true, N, N, no, 2.0, C_occ, no, 0, C_occ, no, 0, 0.0, w.D, N, 0, 1, 0, 0, st));
-        HIPC(ri::energy_terms(w.D, w.H, w.J, w.K, n2, w.scal + 8, w.scal, st));
+        HIPC(ri::energy_terms(w.D, w.H, w.J, w.K, n2, w.scal + 8, w.scal, w.red, st));
         HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.F, N, 0, w.D, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
         HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.T1, N, 0, w.S, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
         HIPC(ri::commutator(w.T2, w.E, N, st));
-        HIPC(ri::max_abs(w.E, n2, w.scal + 5, st));
+        HIPC(ri::max_abs(w.E, n2, w.scal + 5, w.red, st));
         HIPC(hipMemcpyAsync(host, w.scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPC(hipStreamSynchronize(st));
         res->E_total = host[0];
@@ -584,7 +585,7 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
         {
             const double* es[8];
             for (int k = 0; k < m; ++k) es[k] = w.dE[slots[k]];
-            HIPC(ri::diis_dots(es, m, w.dE[s], w.row, n2, st));
+            HIPC(ri::diis_dots(es, m, w.dE[s], w.row, n2, w.red, st));
             double row[8];
             HIPC(hipMemcpyAsync(row, w.row, m * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPC(hipStreamSynchronize(st));

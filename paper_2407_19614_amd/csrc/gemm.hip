@@ -317,11 +317,13 @@ __global__ __launch_bounds__(1024) void dot_kernel(const double* x, const double
     s = block_sum(s);
     if (threadIdx.x == 0) *out = s;
 }
+// max |x| in two stages: 256 workgroups over grid-stride shares, then one
 __global__ __launch_bounds__(1024) void maxabs_kernel(const double* x, int64_t n, double* out) {
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s = fmax(s, fabs(x[i]));
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s = fmax(s, fabs(x[i]));
     s = block_max(s);
-    if (threadIdx.x == 0) *out = s;
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 inline unsigned nblk(int64_t n, int b = 256) {
@@ -469,8 +471,10 @@ hipError_t dot(const double* x, const double* y, int64_t n, double* out, hipStre
     dot_kernel<<<1, 1024, 0, s>>>(x, y, n, out);
     return hipGetLastError();
 }
-hipError_t max_abs(const double* x, int64_t n, double* out, hipStream_t s) {
-    maxabs_kernel<<<1, 1024, 0, s>>>(x, n, out);
+hipError_t max_abs(const double* x, int64_t n, double* out, double* red, hipStream_t s) {
+    maxabs_kernel<<<256, 1024, 0, s>>>(x, n, red);
+    RI_TRY(hipGetLastError());
+    maxabs_kernel<<<1, 1024, 0, s>>>(red, 256, out);
     return hipGetLastError();
 }
 hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {

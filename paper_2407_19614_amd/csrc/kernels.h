@@ -55,16 +55,19 @@ namespace ri {
 // ---- SCF helpers (scf.hip)
 hipError_t fock_assemble(const double* h, const double* J, const double* K, double* F, int64_t n, hipStream_t st);
 hipError_t commutator(const double* M, double* e, int N, hipStream_t st);   // e = M - M^T
-hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, hipStream_t st);
+// Reductions over N x N matrices take a scratch `red` of red_elems(N) doubles.
+int red_elems(int N);
+hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, double* red,
+                     hipStream_t st);
 hipError_t diis_solve(const double* Bmat, int m, int ld, double* coef, hipStream_t st);
 hipError_t diis_combine(const double* const* Fs, const double* coef, int m, double* out, int64_t n, hipStream_t st);
-hipError_t gershgorin(const double* F, int N, double* bounds, hipStream_t st);
+hipError_t gershgorin(const double* F, int N, double* bounds, double* red, hipStream_t st);
 hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st);
 hipError_t traces(const double* X, const double* X2, int N, double* tr, hipStream_t st);
 hipError_t tc2_update(double* X, const double* X2, const double* tr, int n_occ, int64_t n, hipStream_t st);
 hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st);
 hipError_t energy_terms(const double* D, const double* h, const double* J, const double* K, int64_t n,
-                        const double* enuc, double* out, hipStream_t st);
+                        const double* enuc, double* out, double* red, hipStream_t st);
 }  // namespace ri
 
 namespace ri {

@@ -4,6 +4,8 @@
 // orthogonalised Fock matrix, and the energy terms.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace {
 
 inline unsigned nb(int64_t n) { int64_t g = (n + 255) / 256; return (unsigned)(g > 1048576 ? 1048576 : g); }
@@ -21,15 +23,45 @@ __global__ void comm_kernel(const double* M, double* e, int N) {
 
 struct Ptrs { const double* p[8]; };
 
-__global__ __launch_bounds__(256) void multi_dot_kernel(Ptrs es, const double* enew, double* row, int64_t n) {
-    const double* x = es.p[blockIdx.x];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i] * enew[i];
-    __shared__ double sh[4];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+// Two-stage, deterministic reductions over N^2-element matrices: RED_BLOCKS
+// workgroups each reduce a fixed grid-stride share into a partial row of
+// `red`, then one workgroup combines the partials in order.
+constexpr int RED_BLOCKS = 256;
+
+// sum of v over the 256 threads of a workgroup (fixed order)
+__device__ __forceinline__ double wg_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
     __syncthreads();
-    if (threadIdx.x == 0) row[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// partial[b][k] = sum over block b's share of x_k * enew (k < m)
+__global__ __launch_bounds__(256) void multi_dot_part_kernel(Ptrs es, const double* enew, int m, int64_t n,
+                                                             double* red) {
+    __shared__ double sh[4];
+    double s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.0;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double e = enew[i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < m) s[k] += es.p[k][i] * e;
+    }
+    for (int k = 0; k < m; ++k) {
+        const double t = wg_sum(s[k], sh);
+        if (threadIdx.x == 0) red[blockIdx.x * 8 + k] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void multi_dot_final_kernel(const double* red, int m, double* row) {
+    __shared__ double sh[4];
+    for (int k = 0; k < m; ++k) {
+        const double t = wg_sum(threadIdx.x < RED_BLOCKS ? red[threadIdx.x * 8 + k] : 0.0, sh);
+        if (threadIdx.x == 0) row[k] = t;
+    }
 }
 
 // Solve [B -1; -1 0] [c; l] = [0; -1] by Gaussian elimination with partial
@@ -76,29 +108,38 @@ __global__ void combine_kernel(Ptrs Fs, const double* coef, int m, double* out, 
     }
 }
 
-__global__ __launch_bounds__(1024) void gersh_kernel(const double* F, int N, double* bounds) {
-    double lo = 1e300, hi = -1e300;
-    for (int r = threadIdx.x; r < N; r += 1024) {
-        const double* row = F + (int64_t)r * N;
-        double off = 0.0;
-        for (int c = 0; c < N; ++c)
-            if (c != r) off += fabs(row[c]);
-        lo = fmin(lo, row[r] - off);
-        hi = fmax(hi, row[r] + off);
+// Gershgorin interval of each row r (one wave per row): red[2r] = F_rr - sum
+// |F_rc|, red[2r + 1] = F_rr + sum |F_rc| over c != r.
+__global__ __launch_bounds__(256) void gersh_rows_kernel(const double* F, int N, double* red) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (r >= N) return;
+    const double* row = F + (int64_t)r * N;
+    double off = 0.0;
+    for (int c = lane; c < N; c += 64)
+        if (c != r) off += fabs(row[c]);
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_down(off, o);
+    if (lane == 0) {
+        red[2 * r] = row[r] - off;
+        red[2 * r + 1] = row[r] + off;
     }
-    __shared__ double sl[16], sh[16];
+}
+
+__global__ __launch_bounds__(256) void gersh_final_kernel(const double* red, int N, double* bounds) {
+    double lo = 1e300, hi = -1e300;
+    for (int r = threadIdx.x; r < N; r += 256) {
+        lo = fmin(lo, red[2 * r]);
+        hi = fmax(hi, red[2 * r + 1]);
+    }
     for (int o = 32; o > 0; o >>= 1) {
         lo = fmin(lo, __shfl_down(lo, o));
         hi = fmax(hi, __shfl_down(hi, o));
     }
+    __shared__ double sl[4], sh[4];
     if ((threadIdx.x & 63) == 0) { sl[threadIdx.x >> 6] = lo; sh[threadIdx.x >> 6] = hi; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < 16; ++i) { lo = fmin(lo, sl[i]); hi = fmax(hi, sh[i]); }
-        lo = fmin(lo, sl[0]);
-        hi = fmax(hi, sh[0]);
-        bounds[0] = lo;
-        bounds[1] = hi;
+        bounds[0] = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
+        bounds[1] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
     }
 }
 
@@ -148,24 +189,35 @@ __global__ void hash_kernel(double* R, int64_t n, uint32_t seed) {
     }
 }
 
-__global__ __launch_bounds__(1024) void energy_kernel(const double* D, const double* h, const double* J,
-                                                       const double* K, int64_t n, const double* enuc,
-                                                       double* out) {
+// partial[b] = (D.h, D.J, D.K) over block b's share
+__global__ __launch_bounds__(256) void energy_part_kernel(const double* D, const double* h, const double* J,
+                                                          const double* K, int64_t n, double* red) {
+    __shared__ double sh[4];
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
-        double d = D[i];
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double d = D[i];
         a += d * h[i];
         b += d * J[i];
         c += d * K[i];
     }
-    __shared__ double s[3][16];
-    for (int o = 32; o > 0; o >>= 1) { a += __shfl_down(a, o); b += __shfl_down(b, o); c += __shfl_down(c, o); }
-    if ((threadIdx.x & 63) == 0) { s[0][threadIdx.x >> 6] = a; s[1][threadIdx.x >> 6] = b; s[2][threadIdx.x >> 6] = c; }
-    __syncthreads();
+    a = wg_sum(a, sh);
+    b = wg_sum(b, sh);
+    c = wg_sum(c, sh);
     if (threadIdx.x == 0) {
-        a = b = c = 0.0;
-        for (int i = 0; i < 16; ++i) { a += s[0][i]; b += s[1][i]; c += s[2][i]; }
-        double en = *enuc;
+        red[blockIdx.x * 3 + 0] = a;
+        red[blockIdx.x * 3 + 1] = b;
+        red[blockIdx.x * 3 + 2] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void energy_final_kernel(const double* red, const double* enuc, double* out) {
+    __shared__ double sh[4];
+    const bool in = threadIdx.x < RED_BLOCKS;
+    const double a = wg_sum(in ? red[threadIdx.x * 3 + 0] : 0.0, sh);
+    const double b = wg_sum(in ? red[threadIdx.x * 3 + 1] : 0.0, sh);
+    const double c = wg_sum(in ? red[threadIdx.x * 3 + 2] : 0.0, sh);
+    if (threadIdx.x == 0) {
+        const double en = *enuc;
         out[0] = a + 0.5 * b - 0.5 * c + en;   // E_total
         out[1] = en;
         out[2] = a;                            // E_1e
@@ -186,10 +238,14 @@ hipError_t commutator(const double* M, double* e, int N, hipStream_t st) {
     comm_kernel<<<dim3((N + 255) / 256, N), 256, 0, st>>>(M, e, N);
     return hipGetLastError();
 }
-hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, hipStream_t st) {
+hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, double* red,
+                     hipStream_t st) {
+    if (m < 1 || m > 8) return hipErrorInvalidValue;
     Ptrs p{};
     for (int i = 0; i < m; ++i) p.p[i] = es[i];
-    multi_dot_kernel<<<m, 256, 0, st>>>(p, enew, row, n);
+    multi_dot_part_kernel<<<RED_BLOCKS, 256, 0, st>>>(p, enew, m, n, red);
+    RI_TRY(hipGetLastError());
+    multi_dot_final_kernel<<<1, 256, 0, st>>>(red, m, row);
     return hipGetLastError();
 }
 hipError_t diis_solve(const double* Bmat, int m, int ld, double* coef, hipStream_t st) {
@@ -202,8 +258,10 @@ hipError_t diis_combine(const double* const* Fs, const double* coef, int m, doub
     combine_kernel<<<nb(n), 256, 0, st>>>(p, coef, m, out, n);
     return hipGetLastError();
 }
-hipError_t gershgorin(const double* F, int N, double* bounds, hipStream_t st) {
-    gersh_kernel<<<1, 1024, 0, st>>>(F, N, bounds);
+hipError_t gershgorin(const double* F, int N, double* bounds, double* red, hipStream_t st) {
+    gersh_rows_kernel<<<(N + 3) / 4, 256, 0, st>>>(F, N, red);
+    RI_TRY(hipGetLastError());
+    gersh_final_kernel<<<1, 256, 0, st>>>(red, N, bounds);
     return hipGetLastError();
 }
 hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st) {
@@ -223,9 +281,13 @@ hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st) {
     return hipGetLastError();
 }
 hipError_t energy_terms(const double* D, const double* h, const double* J, const double* K, int64_t n,
-                        const double* enuc, double* out, hipStream_t st) {
-    energy_kernel<<<1, 1024, 0, st>>>(D, h, J, K, n, enuc, out);
+                        const double* enuc, double* out, double* red, hipStream_t st) {
+    energy_part_kernel<<<RED_BLOCKS, 256, 0, st>>>(D, h, J, K, n, red);
+    RI_TRY(hipGetLastError());
+    energy_final_kernel<<<1, 256, 0, st>>>(red, enuc, out);
     return hipGetLastError();
 }
+
+int red_elems(int N) { return std::max(RED_BLOCKS * 8, 2 * N); }
 
 }  // namespace ri

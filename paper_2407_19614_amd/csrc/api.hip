@@ -305,10 +305,23 @@ int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool hav
     double idem = 1.0;
     int it = 0, extra = -1;
     const int max_it = 200;
+    // When the 64 x 64 tiles of X^2 are fewer than two per compute unit, the
+    // square is formed as two K-halves in one batched launch into T1 and T2
+    // (free here) and summed, so twice as many workgroups share the work.
+    const int t64 = (N + 63) / 64;
+    const bool halves = N % 2 == 0 && N >= 256 && t64 * t64 < 2 * ri::device_cus();
+    double* X2 = halves ? w.T1 : w.X2;
     while (it < max_it) {
-        HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.X, N, 0, w.X, N, 0, 0.0, w.X2, N, 0, 1, 0, 0, st));
-        HIPC(ri::traces(w.X, w.X2, N, w.scal + 20, st));
-        HIPC(ri::tc2_update(w.X, w.X2, w.scal + 20, n_occ, n2, st));
+        if (halves) {
+            const int h = N / 2;
+            HIPC(ri::gemm_f64(false, false, N, N, h, 1.0, w.X, N, h, w.X, N, (int64_t)h * N, 0.0, w.T1, N,
+                              (int64_t)(w.T2 - w.T1), 2, 0, 0, st));
+            HIPC(ri::axpby(w.T1, w.T2, 1.0, 1.0, n2, st));
+        } else {
+            HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.X, N, 0, w.X, N, 0, 0.0, w.X2, N, 0, 1, 0, 0, st));
+        }
+        HIPC(ri::traces(w.X, X2, N, w.scal + 20, st));
+        HIPC(ri::tc2_update(w.X, X2, w.scal + 20, n_occ, n2, st));
         ++it;
         if (extra > 0) {
             if (--extra == 0) break;

@@ -10,11 +10,14 @@
  *   phi(r) = (2a/pi)^{3/4} exp(-a |r - A|^2); auxiliary functions likewise.
  *   One function per shell.
  * - All device pointers are allocated and owned by the caller; the library
- *   never allocates device memory and keeps no global state.  Scratch memory
- *   comes from `ws` (device, >= 256-byte aligned) of `ws_bytes` bytes, sized
- *   by ri_workspace_bytes().  Calls that take a `hipStream_t` enqueue all
- *   their work on that stream; only calls that return host scalars
- *   synchronise that stream.
+ *   never allocates device memory.  Its only state is a cached compute-unit
+ *   count per device, one side stream per device (made on first use, default
+ *   priority) and the last HIP error text.  Scratch memory comes from `ws`
+ *   (device, >= 256-byte aligned) of `ws_bytes` bytes, sized by
+ *   ri_workspace_bytes().  Calls that take a `hipStream_t` enqueue their work
+ *   on that stream (ri_fock_jk and ri_energy also fork part of it to the
+ *   side stream and join it back into `stream`); only calls that return host
+ *   scalars synchronise that stream.
  * - Matrices are row-major FP64 unless stated.  N = number of orbital basis
  *   functions, n_aux = number of auxiliary functions, n_occ = number of doubly
  *   occupied orbitals.

@@ -358,7 +358,7 @@ hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
     // Fock build
     HC(ri::zero_tail_b(d, p.tail.prefix, nm, p.tail.total, p.prec, st));
     HC(ri::gamma_j_b(d, nm, p.pairs.prefix, p.pairs.total, p.aux.prefix, p.aux.total, p.n2.prefix, p.n2.total, st));
-    if (p.prec == RI_FP64) HC(ri::cpad_b(d, p.cq.prefix, nm, p.cq.total, st));
+    HC(ri::cpad_b(d, p.cq.prefix, nm, p.cq.total, p.prec, st));
     for (int xs = 1; xs <= 32; ++xs)
         if (p.x[xs].total > 0) HC(ri::x_transform_b(d, p.x[xs].prefix, nm, p.x[xs].total, xs, p.prec, st));
     HC(ri::syrk_b(d, p.syrk.prefix, nm, p.syrk.total, p.prec, st));
@@ -480,7 +480,8 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         }
         m.Y = cv.take<double>((int64_t)N * no);
         m.Cp = cv.take<double>((int64_t)N * no);
-        m.Cq = prec == RI_FP64 ? cv.take<double>((int64_t)m.nt * 64 * 64) : nullptr;
+        // padded C for the X launch: FP64 [64 nt][64] doubles, FP32 the same shape in floats
+        m.Cq = cv.take<double>((int64_t)m.nt * 64 * (prec == RI_FP64 ? 64 : 32));
         m.Mo = cv.take<double>((int64_t)no * no);
         m.LinvM = cv.take<double>(64 * 64);
         m.dinvM = cv.take<double>(((N + 63) / 64) * 4096);   // Cholesky diagonal blocks of S

@@ -851,8 +851,8 @@ hipError_t gamma_j_pairs(const double* Bc, const int32_t* pairs, int64_t n_pairs
 // ------------------------------------------------------------ batched forms
 namespace {
 
-// xs = 4 MF + TQ: FP64 takes MF whole tiles and TQ quads from the padded Cq
-// ([64 nt][64], buffer loads); FP32 (TQ = 0) reads C directly.
+// xs = 4 MF + TQ: FP64 takes MF whole tiles and TQ quads, FP32 (TQ = 0) MF
+// whole tiles, both from the padded Cq ([64 nt][64], buffer loads).
 template <int MF, int TQ, int PREC>
 __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
     int mol, loc;
@@ -864,19 +864,21 @@ __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const
         x2_body_f64<MF, TQ, true>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.Cq, 64, m.N, m.n_occ, m.n_aux,
                                   (double*)m.Xt, m.npad);
     else
-        x2_body_f32<MF, false>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.C, nullptr, 0, m.N, m.n_occ, m.n_aux,
-                               (float*)m.Xt, m.npad);
+        x2_body_f32<MF, true>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, nullptr, (const float*)m.Cq, 64, m.N,
+                              m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
 }
 
 // one block per 64-row block of each active molecule: Cq = C zero-padded
+template <typename T>
 __global__ void cpad_b_kernel(const ri::MolDesc* d, const int* prefix, int n_mol) {
     int mol, blk;
     ri::decode_item(prefix, n_mol, blockIdx.x, mol, blk);
     const ri::MolDesc& m = d[mol];
     if (!m.state[0]) return;
+    T* q = (T*)m.Cq;
     for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
         const int r = 64 * blk + (e >> 6), c = e & 63;
-        m.Cq[(int64_t)r * 64 + c] = (r < m.N && c < m.n_occ) ? m.C[(int64_t)r * m.n_occ + c] : 0.0;
+        q[(int64_t)r * 64 + c] = (T)((r < m.N && c < m.n_occ) ? m.C[(int64_t)r * m.n_occ + c] : 0.0);
     }
 }
 
@@ -1000,9 +1002,10 @@ hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int tot
     return hipGetLastError();
 }
 
-hipError_t cpad_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st) {
+hipError_t cpad_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st) {
     if (total <= 0) return hipSuccess;
-    cpad_b_kernel<<<total, 256, 0, st>>>(d, prefix, n_mol);
+    if (prec == RI_FP64) cpad_b_kernel<double><<<total, 256, 0, st>>>(d, prefix, n_mol);
+    else cpad_b_kernel<float><<<total, 256, 0, st>>>(d, prefix, n_mol);
     return hipGetLastError();
 }
 

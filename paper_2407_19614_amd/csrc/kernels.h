@@ -121,7 +121,7 @@ struct MolDesc {
     double *C, *J, *K, *gamma, *dpair, *part;
     void* Xt;
     double *S, *H, *LinvS, *F, *D, *T1, *T2, *E, *Fx, *X, *X2, *Y, *Cp, *Mo, *LinvM, *dinvM;
-    double* Cq;   // C_occ zero-padded to [64 * nt][64] (FP64 exchange)
+    double* Cq;   // C_occ zero-padded to [64 * nt][64], FP64 (or FP32 for FP32 exchange)
     double *dF[8], *dE[8];
     double *Bmat, *coef, *scal;
     int* state;   // 0 active, 1 iteration, 2 DIIS pushes, 3 converged, 4.. DIIS slot order [8]
@@ -154,8 +154,9 @@ __device__ __forceinline__ void decode_item(const int* prefix, int n_mol, int L,
 // batched Fock build pieces (fock.hip); `prec` is RI_FP64 or RI_FP32 for all molecules
 // X for the molecules whose xs equals `xs` (one launch per shape present)
 hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int xs, int prec, hipStream_t st);
-// Cq of every active molecule from its C (prefix counts 64-row blocks)
-hipError_t cpad_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st);
+// Cq of every active molecule from its C (prefix counts 64-row blocks), in the
+// exchange precision `prec`
+hipError_t cpad_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);
 hipError_t syrk_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);
 hipError_t kreduce_b(const MolDesc* d, const int* prefix, int n_mol, int total, hipStream_t st);
 hipError_t zero_tail_b(const MolDesc* d, const int* prefix, int n_mol, int total, int prec, hipStream_t st);

@@ -165,7 +165,7 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
     for (int m = 0; m < MF; ++m) { acc[m][0] = d4_t{0, 0, 0, 0}; acc[m][1] = d4_t{0, 0, 0, 0}; }
 #pragma unroll
     for (int q = 0; q < TQ; ++q) { accq[q][0] = 0.0; accq[q][1] = 0.0; }
-    const int nsl = nt * 4;
+    const int nsl = (N + 15) / 16;                 // 16-deep k-slices that hold a basis function
     load_b(0, 0);
     load_c(0, 0);
     for (int sl = 0; sl < nsl; ++sl) {
@@ -218,10 +218,10 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
 
 template <int MF, int TQ>
 __global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
-                                                     const double* __restrict__ Cp, int cld, int n_occ, int n_aux,
-                                                     double* __restrict__ Xt, int Npad) {
+                                                     const double* __restrict__ Cp, int cld, int N, int n_occ,
+                                                     int n_aux, double* __restrict__ Xt, int Npad) {
     const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    x2_body_f64<MF, TQ, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, Cp, cld, 0, n_occ,
+    x2_body_f64<MF, TQ, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, Cp, cld, N, n_occ,
                               n_aux, Xt, Npad);
 }
 
@@ -759,7 +759,7 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
     cpad_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cp);
     RI_TRY(hipGetLastError());
     switch (mf * 4 + tq) {
-#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, n_occ, n_aux, x, Npad); break;
+#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, N, n_occ, n_aux, x, Npad); break;
 #define XROW(f) XCASE(f, 1) XCASE(f, 2) XCASE(f, 3)
         XROW(0) XROW(1) XROW(2) XROW(3) XROW(4) XROW(5) XROW(6) XROW(7)
         XCASE(1, 0) XCASE(2, 0) XCASE(3, 0) XCASE(4, 0) XCASE(5, 0) XCASE(6, 0) XCASE(7, 0) XCASE(8, 0)

@@ -406,14 +406,43 @@ __global__ void cpad_f32_kernel(const double* C, int N, int n_occ, int rows, int
     Cf[e] = (r < N && c < n_occ) ? (float)C[(int64_t)r * n_occ + c] : 0.0f;
 }
 
+// Which 16 x 16 sub-tiles (i, j) of a wave's 64 x 64 quadrant of a SYRK tile
+// the K reduction reads: rows i < IM (the rest lie at or past row N) and, on a
+// quadrant centred on the diagonal, only j <= i.  A wave's shape is fixed for
+// the whole launch, so each shape gets its own copy of the k-loop and the
+// MFMA sequence stays branch-free.
+template <bool DIAG, int IM>
+struct SyrkShape {
+    static constexpr bool diag = DIAG;
+    static constexpr int im = IM;
+};
+
+// Runs fn(SyrkShape<...>{}) for the shape of the quadrant at rows qm.., cols
+// qn.. (wave-uniform values).
+template <class F>
+__device__ __forceinline__ void syrk_dispatch(int qm, int qn, int N, F&& fn) {
+    const int im = qn > qm ? 0 : min(4, max(0, (N - qm + 15) / 16));
+    if (im == 0) return fn(SyrkShape<false, 0>{});
+    if (qm == qn) {
+        if (im == 4) return fn(SyrkShape<true, 4>{});
+        if (im == 3) return fn(SyrkShape<true, 3>{});
+        if (im == 2) return fn(SyrkShape<true, 2>{});
+        return fn(SyrkShape<true, 1>{});
+    }
+    if (im == 4) return fn(SyrkShape<false, 4>{});
+    if (im == 3) return fn(SyrkShape<false, 3>{});
+    if (im == 2) return fn(SyrkShape<false, 2>{});
+    return fn(SyrkShape<false, 1>{});
+}
+
 // FP32 exchange SYRK on the direct-LDS ring: one wave instruction moves two
 // 128-float tile rows (lanes 0-31 the first, 32-63 the second); 16 B chunks
 // of row r sit at chunk ^ ((r & 3) << 2) so the four k-rows a fragment read
 // touches map to disjoint banks.  FP32 accumulation within a split, partial
 // tiles written in FP64 and summed across splits in FP64.
 template <int S>
-__device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restrict__ X, int Npad, int64_t rows_pad,
-                                              int64_t chunk, double* __restrict__ part) {
+__device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restrict__ X, int N, int Npad,
+                                              int64_t rows_pad, int64_t chunk, double* __restrict__ part) {
     __shared__ float As[S][16 * 128];
     __shared__ float Bs[S][16 * 128];
     int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -424,9 +453,9 @@ __device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restr
     const int64_t r0 = (int64_t)z * chunk;
     const int64_t r1 = min(rows_pad, r0 + chunk);
     const int nsteps = (int)((r1 - r0) / 16);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    const bool upper = ti == tj && wn > wm;      // quadrant the reduction never reads
     // wave w moves row pairs 2w and 2w+1 (rows 4w .. 4w+3) of A and of B
     auto issue = [&](int step, int buf) {
         int64_t rb = r0 + (int64_t)step * 16;
@@ -453,45 +482,48 @@ __device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restr
         }
 #pragma unroll
     for (int s = 0; s < S - 1; ++s) issue(s, s);
-    for (int k = 0; k < nsteps; ++k) {
-        if ((k & 3) == 0 && k > 0) {   // FP32 over 64 rows, FP64 across
+    syrk_dispatch(m0 + wm, n0 + wn, N, [&](auto shape) {
+        constexpr bool DIAG = decltype(shape)::diag;
+        constexpr int IM = decltype(shape)::im;
+        for (int k = 0; k < nsteps; ++k) {
+            if ((k & 3) == 0 && k > 0) {   // FP32 over 64 rows, FP64 across
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < IM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        acc64[i][j][r] += (double)acc[i][j][r];
-                        acc[i][j][r] = 0.0f;
-                    }
-        }
-        __builtin_amdgcn_s_waitcnt(((S - 2) * 4 & 0xF) | ((((S - 2) * 4) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-        __builtin_amdgcn_s_barrier();
-        issue(k + S - 1, (k + S - 1) % S);
-        const float* as = As[k % S];
-        const float* bs = Bs[k % S];
-        if (!upper)
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            const int row = kk + lk, sw = (row & 3) << 2;
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = wm + 16 * i + li;
-                a[i] = as[row * 128 + 4 * ((m >> 2) ^ sw) + (m & 3)];
+                        for (int r = 0; r < 4; ++r) {
+                            acc64[i][j][r] += (double)acc[i][j][r];
+                            acc[i][j][r] = 0.0f;
+                        }
             }
+            __builtin_amdgcn_s_waitcnt(((S - 2) * 4 & 0xF) | ((((S - 2) * 4) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+            __builtin_amdgcn_s_barrier();
+            issue(k + S - 1, (k + S - 1) % S);
+            const float* as = As[k % S];
+            const float* bs = Bs[k % S];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int n = wn + 16 * j + li;
-                b[j] = bs[row * 128 + 4 * ((n >> 2) ^ sw) + (n & 3)];
+            for (int kk = 0; kk < 16; kk += 4) {
+                const int row = kk + lk, sw = (row & 3) << 2;
+                float a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < IM; ++i) {
+                    const int m = wm + 16 * i + li;
+                    a[i] = as[row * 128 + 4 * ((m >> 2) ^ sw) + (m & 3)];
+                }
+#pragma unroll
+                for (int j = 0; j < (DIAG ? IM : 4); ++j) {
+                    const int n = wn + 16 * j + li;
+                    b[j] = bs[row * 128 + 4 * ((n >> 2) ^ sw) + (n & 3)];
+                }
+#pragma unroll
+                for (int i = 0; i < IM; ++i)
+#pragma unroll
+                    for (int j = 0; j < (DIAG ? i + 1 : 4); ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f32(a[i], b[j], acc[i][j]);
+            __builtin_amdgcn_s_waitcnt(0xC07F);
         }
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-    }
+    });
     __builtin_amdgcn_s_waitcnt(0);
     double* out = part + (int64_t)z * Npad * Npad;
 #pragma unroll
@@ -505,11 +537,12 @@ __device__ __forceinline__ void syrk_body_f32(int z, int t, const float* __restr
 }
 
 template <int S>
-__global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __restrict__ X, int Npad, int64_t rows_pad,
-                                                              int64_t chunk, int ntile, double* __restrict__ part) {
+__global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __restrict__ X, int N, int Npad,
+                                                              int64_t rows_pad, int64_t chunk, int ntile,
+                                                              double* __restrict__ part) {
     const int nlow = ntile * (ntile + 1) / 2;
     const int L = xcd_remap(blockIdx.x, gridDim.x);
-    syrk_body_f32<S>(L / nlow, L % nlow, X, Npad, rows_pad, chunk, part);
+    syrk_body_f32<S>(L / nlow, L % nlow, X, N, Npad, rows_pad, chunk, part);
 }
 
 // Exchange SYRK, K_part[z] = sum over rows r of split z of Xt[r][m] Xt[r][n],
@@ -522,8 +555,8 @@ __global__ __launch_bounds__(256, 2) void syrk_lds_f32_kernel(const float* __res
 // in bounds and contribute nothing.
 
 template <int S>
-__device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __restrict__ X, int Npad, int64_t rows_pad,
-                                              int64_t chunk, double* __restrict__ part) {
+__device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __restrict__ X, int N, int Npad,
+                                              int64_t rows_pad, int64_t chunk, double* __restrict__ part) {
     constexpr int LDR = 128 + 16;                  // LDS row stride (doubles)
     __shared__ double As[S][16 * LDR];
     __shared__ double Bs[S][16 * LDR];
@@ -535,11 +568,9 @@ __device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __rest
     const int64_t r0 = (int64_t)z * chunk;
     const int64_t r1 = min(rows_pad, r0 + chunk);
     const int nsteps = (int)((r1 - r0) / 16);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-    // on a diagonal tile the strictly-upper 64 x 64 quadrant is never read
-    // by the reduction: that wave only moves data
-    const bool upper = ti == tj && wn > wm;
     // each wave moves rows 4*wave .. 4*wave+3 of the A and B 16-row slabs.
     // A split's rows plus one 16-row look-ahead (the next split's rows or the
     // zero rows) are reached through buffer resources when their extent fits
@@ -587,28 +618,33 @@ __device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __rest
         for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < S - 1; ++s) issue(s, s);
-    for (int k = 0; k < nsteps; ++k) {
-        // this wave's loads for step k are done once at most (S-2)*8 younger ones remain
-        __builtin_amdgcn_s_waitcnt(((S - 2) * 8 & 0xF) | ((((S - 2) * 8) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-        __builtin_amdgcn_s_barrier();
-        issue(k + S - 1, (k + S - 1) % S);
-        const double* as = As[k % S];
-        const double* bs = Bs[k % S];
-        if (!upper)
+    // sub-tiles the reduction never reads are skipped (the upper quadrant of
+    // a diagonal tile: its wave only moves data)
+    syrk_dispatch(m0 + wm, n0 + wn, N, [&](auto shape) {
+        constexpr bool DIAG = decltype(shape)::diag;
+        constexpr int IM = decltype(shape)::im;
+        for (int k = 0; k < nsteps; ++k) {
+            // this wave's loads for step k are done once at most (S-2)*8 younger ones remain
+            __builtin_amdgcn_s_waitcnt(((S - 2) * 8 & 0xF) | ((((S - 2) * 8) >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+            __builtin_amdgcn_s_barrier();
+            issue(k + S - 1, (k + S - 1) % S);
+            const double* as = As[k % S];
+            const double* bs = Bs[k % S];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            double a[4], b[4];
+            for (int kk = 0; kk < 16; kk += 4) {
+                double a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = as[(kk + lk) * LDR + wm + 16 * i + li];
+                for (int i = 0; i < IM; ++i) a[i] = as[(kk + lk) * LDR + wm + 16 * i + li];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = bs[(kk + lk) * LDR + wn + 16 * j + li];
+                for (int j = 0; j < (DIAG ? IM : 4); ++j) b[j] = bs[(kk + lk) * LDR + wn + 16 * j + li];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < IM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < (DIAG ? i + 1 : 4); ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+            }
+            __builtin_amdgcn_s_waitcnt(0xC07F);    // lgkmcnt(0): LDS reads of this buffer done
         }
-        __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0): LDS reads of this buffer done
-    }
+    });
     __builtin_amdgcn_s_waitcnt(0);
     double* out = part + (int64_t)z * Npad * Npad;
 #pragma unroll
@@ -621,11 +657,12 @@ __device__ __forceinline__ void syrk_body_f64(int z, int t, const double* __rest
 }
 
 template <int S>
-__global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restrict__ X, int Npad, int64_t rows_pad,
-                                                          int64_t chunk, int ntile, double* __restrict__ part) {
+__global__ __launch_bounds__(256, 2) void syrk_lds_kernel(const double* __restrict__ X, int N, int Npad,
+                                                          int64_t rows_pad, int64_t chunk, int ntile,
+                                                          double* __restrict__ part) {
     const int nlow = ntile * (ntile + 1) / 2;
     const int L = xcd_remap(blockIdx.x, gridDim.x);
-    syrk_body_f64<S>(L / nlow, L % nlow, X, Npad, rows_pad, chunk, part);
+    syrk_body_f64<S>(L / nlow, L % nlow, X, N, Npad, rows_pad, chunk, part);
 }
 
 __global__ void kreduce_kernel(const double* part, int n_split, int Npad, int N, double* K) {
@@ -801,12 +838,12 @@ hipError_t k_syrk(const void* Xt, int prec, int N, int n_aux, int n_occ, double*
         double* x = (double*)Xt;
         // zero the padding rows (real rows .. rows_pad + 16)
         RI_TRY(fill(x + rows * Npad, 0.0, (rows_pad + 16 - rows) * Npad, st));
-        syrk_lds_kernel<2><<<nlow * used, 256, 0, st>>>(x, Npad, rows_pad, chunk, t128, part);
+        syrk_lds_kernel<2><<<nlow * used, 256, 0, st>>>(x, N, Npad, rows_pad, chunk, t128, part);
     } else {
         float* x = (float*)Xt;
         // zero padding rows (the region is 512 B aligned: fill it as doubles)
         RI_TRY(fill((double*)(x + rows * Npad), 0.0, (rows_pad + 16 - rows) * Npad / 2, st));
-        syrk_lds_f32_kernel<4><<<nlow * used, 256, 0, st>>>(x, Npad, rows_pad, chunk, t128, part);
+        syrk_lds_f32_kernel<4><<<nlow * used, 256, 0, st>>>(x, N, Npad, rows_pad, chunk, t128, part);
     }
     RI_TRY(hipGetLastError());
     dim3 grid((N + 255) / 256, N);
@@ -890,9 +927,9 @@ __global__ __launch_bounds__(256, 2) void syrk_b_kernel(const ri::MolDesc* d, co
     if (!m.state[0]) return;
     const int t128 = m.npad / 128, nlow = t128 * (t128 + 1) / 2;
     if (PREC == RI_FP64)
-        syrk_body_f64<2>(loc / nlow, loc % nlow, (const double*)m.Xt, m.npad, m.rows_pad, m.chunk, m.part);
+        syrk_body_f64<2>(loc / nlow, loc % nlow, (const double*)m.Xt, m.N, m.npad, m.rows_pad, m.chunk, m.part);
     else
-        syrk_body_f32<4>(loc / nlow, loc % nlow, (const float*)m.Xt, m.npad, m.rows_pad, m.chunk, m.part);
+        syrk_body_f32<4>(loc / nlow, loc % nlow, (const float*)m.Xt, m.N, m.npad, m.rows_pad, m.chunk, m.part);
 }
 
 // one block per row mu of each molecule: K[mu][nu] = K[nu][mu] = sum_z part[z][mu][nu], nu <= mu

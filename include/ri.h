@@ -338,12 +338,13 @@ size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri
  *   gemm_tile[b]   64 or 128: tile edge of the grouped FP64 GEMMs whose three
  *                  dimensions are N (orthogonalisation, purification squares,
  *                  F D and F D S products).
- *   syrk_split[b]  1 .. 8: pieces the exchange SYRK reduction index
+ *   syrk_split[b]  1 .. RI_TUNE_MAX_SPLIT: pieces the exchange SYRK reduction index
  *                  (n_aux * n_occ) is split into.
  *   gemm_ms[b], syrk_ms[b]  (filled by ri_batch_autotune) the measured time
  *                  of the chosen shape on the bucket's molecules, in ms.
  * Host memory, owned by the caller. */
 #define RI_TUNE_BUCKETS 8
+#define RI_TUNE_MAX_SPLIT 16
 typedef struct {
     int32_t n_buckets;
     int32_t gemm_tile[RI_TUNE_BUCKETS];
@@ -354,7 +355,7 @@ typedef struct {
 
 /* ri_batch_autotune - choose ri_batch_tuning for a batch by timing each
  * candidate shape (GEMM tile 64 / 128 on the purification square X X; SYRK
- * split 8, 4, 2, 1 including its reduction, stopping at the first candidate
+ * split 16, 8, 4, 2, 1 including its reduction, stopping at the first candidate
  * 1.5x slower than the best) with HIP events on the batch's own molecules of
  * each bucket, and keeping the fastest.  Takes the same
  * arguments and workspace as ri_energy_batched (sized by

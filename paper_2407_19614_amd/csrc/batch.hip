@@ -417,7 +417,7 @@ bool tuning_ok(const ri_batch_tuning* t) {
     if (!t) return true;
     if (t->n_buckets < 1 || t->n_buckets > RI_TUNE_BUCKETS) return false;
     for (int b = 0; b < t->n_buckets; ++b)
-        if ((t->gemm_tile[b] != 64 && t->gemm_tile[b] != 128) || t->syrk_split[b] < 1 || t->syrk_split[b] > 8)
+        if ((t->gemm_tile[b] != 64 && t->gemm_tile[b] != 128) || t->syrk_split[b] < 1 || t->syrk_split[b] > RI_TUNE_MAX_SPLIT)
             return false;
     return true;
 }
@@ -470,7 +470,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         const int64_t n2 = (int64_t)N * N;
         m.J = cv.take<double>(n2); m.K = cv.take<double>(n2); m.gamma = cv.take<double>(na);
         m.dpair = cv.take<double>(std::max<int64_t>(1, m.n_pairs));
-        m.part = cv.take<double>((int64_t)8 * m.npad * m.npad);   // the largest split any tuning may choose
+        m.part = cv.take<double>((int64_t)RI_TUNE_MAX_SPLIT * m.npad * m.npad);   // the largest split any tuning may choose
         m.Xt = cv.take<char>((m.rows_pad + 16) * m.npad * (prec == RI_FP64 ? 8 : 4));
         double** mats[] = {&m.S, &m.H, &m.LinvS, &m.F, &m.D, &m.T1, &m.T2, &m.E, &m.Fx, &m.X, &m.X2};
         for (double** q : mats) *q = cv.take<double>(n2);
@@ -659,7 +659,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
         // SYRK split: SYRK partials and their reduction for the bucket's molecules;
         // candidates from the widest down, stopping once one is 1.5x the best
         best = 1e30f;
-        for (int ks : {8, 4, 2, 1}) {
+        for (int ks : {16, 8, 4, 2, 1}) {
             std::vector<int> ps(n_mol + 1, 0), pr(n_mol + 1, 0);
             std::vector<MolDesc> mols = hp.mols;
             for (int i = 0; i < n_mol; ++i) {

@@ -84,7 +84,7 @@ def test_bad_arguments_rejected_before_device_work():
     ws = ctypes.create_string_buffer(256)
     opts6 = Bd.SCFOpts(10, 6, 1e-10, 1e-8, 0)
     res1 = (Bd.SCFResult * 1)()
-    for tile, split, nb in ((96, 2, 1), (64, 0, 1), (128, 9, 1), (64, 2, 0), (64, 2, 9)):
+    for tile, split, nb in ((96, 2, 1), (64, 0, 1), (128, 17, 1), (64, 2, 0), (64, 2, 9)):
         t = Bd.BatchTuning()
         t.n_buckets = nb
         for b in range(Bd.TUNE_BUCKETS):

@@ -85,7 +85,7 @@ def test_batched_autotune_and_forced_shapes_agree():
     print("tuning", d, flush=True)
     assert d["n_buckets"] == 4
     for b in range(4):
-        assert d["gemm_tile"][b] in (64, 128) and d["syrk_split"][b] in (1, 2, 4, 8)
+        assert d["gemm_tile"][b] in (64, 128) and d["syrk_split"][b] in (1, 2, 4, 8, 16)
         assert d["gemm_ms"][b] > 0 and d["syrk_ms"][b] > 0
 
     def forced(tile, split):
@@ -97,7 +97,7 @@ def test_batched_autotune_and_forced_shapes_agree():
 
     kw = dict(tol_E=1e-11, tol_err=1e-9)
     E0 = [r["E_total"] for r in energy_batched(probs, P.FP64, **kw)[0]]
-    for t in (tune, forced(128, 8), forced(64, 1)):
+    for t in (tune, forced(128, 16), forced(64, 1)):
         res = energy_batched(probs, P.FP64, tuning=t, **kw)[0]
         for k, r in enumerate(res):
             assert r["converged"]

@@ -19,6 +19,9 @@ namespace {
 using ri::MolDesc;
 
 constexpr int ST_ACTIVE = 0, ST_IT = 1, ST_PUSH = 2, ST_CONV = 3, ST_NSLOT = 4, ST_SLOT0 = 5, ST_BAD = 13;
+// purification: ST_TC2 1 while squares are still formed, ST_TC2U 1 if this
+// step's update runs, ST_TC2X the steps left once idempotent (-1 before)
+constexpr int ST_TC2 = 14, ST_TC2X = 15, ST_TC2U = 16, ST_N = 32;
 constexpr int SC_E = 0, SC_ERR = 5, SC_EOLD = 6, SC_ENUC = 8, SC_BOUNDS = 16, SC_TR = 20;
 
 #define DECODE()                                         \
@@ -97,6 +100,7 @@ __global__ void tc2_init_b(const MolDesc* d, const int* prefix, int n_mol) {
 
 __global__ void tc2_update_b(const MolDesc* d, const int* prefix, int n_mol) {
     DECODE();
+    if (!m.state[ST_TC2U]) return;
     int64_t e = (int64_t)loc * 256 + threadIdx.x;
     if (e >= (int64_t)m.N * m.N) return;
     const double t1 = m.scal[SC_TR], t2 = m.scal[SC_TR + 1];
@@ -107,7 +111,10 @@ __global__ void tc2_update_b(const MolDesc* d, const int* prefix, int n_mol) {
 // -------------------------------------------------- one block per molecule
 __global__ __launch_bounds__(256) void state_init_b(const MolDesc* d, int n_mol) {
     const MolDesc& m = d[blockIdx.x];
-    if (threadIdx.x < 16) m.state[threadIdx.x] = (threadIdx.x == ST_ACTIVE) ? 1 : 0;
+    if (threadIdx.x < ST_N)
+        m.state[threadIdx.x] = (threadIdx.x == ST_ACTIVE || threadIdx.x == ST_TC2 || threadIdx.x == ST_TC2U) ? 1
+                               : threadIdx.x == ST_TC2X                                                     ? -1
+                                                                                                            : 0;
     if (threadIdx.x < 64) m.Bmat[threadIdx.x] = 0.0;
     if (threadIdx.x == 0) m.scal[SC_EOLD] = 0.0;
 }
@@ -158,8 +165,10 @@ __global__ __launch_bounds__(256) void energy_conv_b(const MolDesc* d, int n_mol
         if (it > 1 && fabs(dE) < m.tol_E && e < m.tol_err) {
             m.state[ST_CONV] = 1;
             m.state[ST_ACTIVE] = 0;
+            m.state[ST_TC2] = 0;
         } else if (it >= max_iter) {
             m.state[ST_ACTIVE] = 0;
+            m.state[ST_TC2] = 0;
         }
         m.scal[SC_EOLD] = E;
     }
@@ -256,12 +265,23 @@ __global__ __launch_bounds__(256) void gersh_b(const MolDesc* d, int n_mol) {
     if (threadIdx.x == 0) {
         m.scal[SC_BOUNDS] = lo;
         m.scal[SC_BOUNDS + 1] = hi;
+        m.state[ST_TC2] = 1;       // a purification starts
+        m.state[ST_TC2U] = 1;
+        m.state[ST_TC2X] = -1;
     }
 }
 
+// tr X and tr X^2 of a purification step, and when to stop: once
+// |tr X - tr X^2| < 1e-11 n_occ, this step's update and three more run (the
+// rule of the single-molecule path); later steps of the fixed launch
+// sequence find ST_TC2 clear and exit at once.
 __global__ __launch_bounds__(256) void traces_b(const MolDesc* d, int n_mol) {
     const MolDesc& m = d[blockIdx.x];
     if (!m.state[ST_ACTIVE]) return;
+    if (!m.state[ST_TC2]) {
+        if (threadIdx.x == 0) m.state[ST_TC2U] = 0;
+        return;
+    }
     __shared__ double sh[4];
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < m.N; i += 256) {
@@ -274,6 +294,15 @@ __global__ __launch_bounds__(256) void traces_b(const MolDesc* d, int n_mol) {
         m.scal[SC_TR] = a;
         m.scal[SC_TR + 1] = b;
         m.scal[SC_TR + 2] = a - b;
+        m.state[ST_TC2U] = 1;
+        int x = m.state[ST_TC2X];
+        if (x < 0) {
+            if (fabs(a - b) < 1e-11 * (double)max(1, m.n_occ)) x = 3;
+        } else if (x > 0) {
+            --x;
+        }
+        if (x == 0) m.state[ST_TC2] = 0;   // this step's update is the last
+        m.state[ST_TC2X] = x;
     }
 }
 
@@ -488,7 +517,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         m.Bmat = cv.take<double>(64);
         m.coef = cv.take<double>(8);
         m.scal = cv.take<double>(32);
-        m.state = cv.take<int>(16);
+        m.state = cv.take<int>(ST_N);
     }
     // tables
     auto mk = [&](std::vector<int> counts, Table& t) {
@@ -524,14 +553,14 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
     }
     // grouped GEMMs: member i of each
     // tunable: the member runs on the molecule's tuned tile (else on 64 x 64)
-    auto mkg = [&](Plan::G& g, bool ta, bool tb, bool tunable, auto fill) {
+    auto mkg = [&](Plan::G& g, bool ta, bool tb, bool tunable, auto fill, int act = ST_ACTIVE) {
         g.ta = ta;
         g.tb = tb;
         std::vector<ri::GemmDesc> v(n_mol);
         std::vector<int> c64(n_mol), c128(n_mol);
         for (int i = 0; i < n_mol; ++i) {
             fill(hp.mols[i], v[i]);
-            v[i].active = hp.mols[i].state;   // state[0]
+            v[i].active = hp.mols[i].state + act;   // runs while this flag is set
             const bool big = tunable && hp.tile[i] == 128;
             c64[i] = big ? 0 : ((v[i].M + 63) / 64) * ((v[i].N + 63) / 64);
             c128[i] = big ? ((v[i].M + 127) / 128) * ((v[i].N + 127) / 128) : 0;
@@ -549,7 +578,8 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
     };
     mkg(p.g_lfx, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.LinvS, m.N, m.Fx, m.N, m.T1, m.N, 1); });
     mkg(p.g_t2, false, true, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.LinvS, m.N, m.T2, m.N, 0); });
-    mkg(p.g_x2, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.X, m.N, m.X, m.N, m.X2, m.N, 0); });
+    mkg(p.g_x2, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.X, m.N, m.X, m.N, m.X2, m.N, 0); },
+        ST_TC2);
     mkg(p.g_y, false, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.X, m.N, m.Cp, m.n_occ, m.Y, m.n_occ, 0); });
     mkg(p.g_mo, true, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.n_occ, m.n_occ, m.N, 1.0, m.Y, m.n_occ, m.Y, m.n_occ, m.Mo, m.n_occ, 0); });
     mkg(p.g_cp, false, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.n_occ, 1.0, m.Y, m.n_occ, m.LinvM, 64, m.Cp, m.n_occ, 0); });

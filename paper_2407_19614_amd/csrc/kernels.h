@@ -124,7 +124,7 @@ struct MolDesc {
     double* Cq;   // C_occ zero-padded to [64 * nt][64], FP64 (or FP32 for FP32 exchange)
     double *dF[8], *dE[8];
     double *Bmat, *coef, *scal;
-    int* state;   // 0 active, 1 iteration, 2 DIIS pushes, 3 converged, 4.. DIIS slot order [8]
+    int* state;   // 0 active, 1 iteration, 2 DIIS pushes, 3 converged, 4.. DIIS slot order [8], 14.. purification
 };
 
 // One member of a grouped FP64 GEMM: C = alpha op(A) op(B) + beta C.

@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="also run the batched workload (256 molecules, 10-60 centres) and report SCF/s")
     ap.add_argument("--batched-n", type=int, default=256, help="molecules in the batched workload")
-    ap.add_argument("--batched-prec", default="fp32", choices=["fp32", "fp64"],
+    ap.add_argument("--batched-prec", default="fp32", choices=["fp32", "fp64", "fp32f64"],
                     help="exchange precision of the batched workload")
     ap.add_argument("--aimd", action="store_true",
                     help="also run Born-Oppenheimer NVE dynamics of the N=1000 workload (1 fs steps)")
@@ -328,8 +328,9 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True)
     import paper_2407_19614_amd as P
     from paper_2407_19614_amd.binding import batch_autotune, energy_batched, prepare_batch
     systems = synth.batched_systems(n_mol)
-    prec = P.FP32 if prec_name == "fp32" else P.FP64
-    tol = dict(tol_E=1e-7, tol_err=1e-5) if prec == P.FP32 else dict(tol_E=1e-10, tol_err=1e-8)
+    prec = {"fp32": P.FP32, "fp64": P.FP64, "fp32f64": P.FP32 | P.FINAL_FP64}[prec_name]
+    # FP32 exchange (with or without the final FP64 exchange build) iterates to its own noise floor
+    tol = dict(tol_E=1e-7, tol_err=1e-5) if prec & 0xF == P.FP32 else dict(tol_E=1e-10, tol_err=1e-8)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     E = np.full(len(systems), np.nan)
     iters = np.zeros(len(systems), dtype=int)
@@ -373,8 +374,9 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True)
         del pr
     torch.cuda.synchronize()
     t_base = time.perf_counter() - tb
-    out = {"workload": f"{len(systems)} He-like clusters, 10-60 centres (N 100-600, N_aux 300-1800), "
-                       f"{prec_name.upper()} exchange",
+    mode = {"fp32": "FP32 exchange", "fp64": "FP64 exchange",
+            "fp32f64": "FP32 exchange, then one FP64 exchange build at the converged density"}[prec_name]
+    out = {"workload": f"{len(systems)} He-like clusters, 10-60 centres (N 100-600, N_aux 300-1800), {mode}",
            "scf_per_s": round(len(systems) / wall, 3), "wall_s": round(wall, 2),
            "scf_per_s_steady": round(len(systems) / (wall - t_tune), 3),
            "setup_s": round(t_setup, 2), "autotune_s": round(t_tune, 3), "batched_scf_s": round(t_scf, 2),

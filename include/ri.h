@@ -126,7 +126,8 @@ int32_t ri_build_3c(const ri_system* sys, double tau, int32_t* pairs, int64_t ca
  * Bc = L^{-1} T (overwrites T in place), and the packed ("decompressed")
  * B tensor in precision `prec`.
  * Paper: eq. symmetric_ri and eq. biap (Cholesky of the metric, B formation);
- * Algorithm 1 lines forming B and decompressing it once when memory allows.
+ * Algorithm 1, the formation of B and its one-time decompression when memory
+ * allows.
  *   T_inout [n_aux][n_pairs] in: (mu nu|P); out: Bc.
  *   L       [n_aux][n_aux] out: lower factor (upper triangle zeroed).
  *   Linv    [n_aux][n_aux] out: L^{-1} (lower).
@@ -138,6 +139,21 @@ int32_t ri_build_3c(const ri_system* sys, double tau, int32_t* pairs, int64_t ca
 int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
                          double* T_inout, double* L, double* Linv, void* B, int32_t prec,
                          int64_t* bad_pivot, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ri_pack_b - the packed B tensor (layout above) in precision `prec` from
+ * the fitted tensor on compressed pairs, as ri_metric_factor writes it: the
+ * same B in a second precision without refactoring the metric.
+ * Paper: Algorithm 1, the one-time decompression of B when memory allows.
+ *   Bc      [n_aux][n_pairs] FP64 fitted tensor and pairs [n_pairs][2], as
+ *           returned by ri_metric_factor / ri_build_3c (device, read).
+ *   B       ri_packed_b_bytes(N, n_aux, prec) bytes (device, out; every byte
+ *           is written).
+ *   prec    RI_FP64, RI_FP32, RI_BF16X3 or RI_BF16X6, no flags
+ *           (RI_E_UNSUPPORTED otherwise).
+ * Workspace: ri_workspace_bytes(RI_OP_METRIC, N, n_aux, 0, n_pairs, prec).
+ * Asynchronous: no host synchronisation. */
+int32_t ri_pack_b(int32_t N, int32_t n_aux, const double* Bc, const int32_t* pairs, int64_t n_pairs,
+                  void* B, int32_t prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ri_fock_jk - one RI Fock build: Coulomb J and exchange K for the density
  * D = 2 C_occ C_occ^T.
@@ -329,8 +345,21 @@ typedef struct {
     double* F;              /* [N][N] out, or NULL                              */
 } ri_batch_mol;
 
+/* Flag OR-ed into the precision of the batched calls, with RI_FP32 only.
+ * The SCF of every molecule runs with FP32 exchange as for RI_FP32; after
+ * the last iteration its exchange matrix is rebuilt once in FP64 arithmetic
+ * (the FP32-stored B widened on load; C, X and K in FP64) at the density of
+ * that iteration, and the reported energy (E_total, E_K) is the one with
+ * this K.  The energy is stationary in the density, so the density's FP32
+ * error enters it only to second order, while FP32 arithmetic in the
+ * exchange shifts it to first order; what remains first order is the FP32
+ * rounding of B.  n_iter, converged, last_dE, max_err and F are those of the
+ * FP32 iterations.  The workspace holds FP64 Xt and C copies. */
+#define RI_FINAL_FP64 0x20
+
 /* Workspace bytes for ri_energy_batched (0 on invalid input).  Supported:
- * prec RI_FP64 or RI_FP32, n_occ <= 64 for every molecule. */
+ * prec RI_FP64, RI_FP32 or RI_FP32 | RI_FINAL_FP64, n_occ <= 64 for every
+ * molecule. */
 size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec);
 
 /* Launch shapes of the batched SCF per size bucket.  Molecule m belongs to
@@ -372,6 +401,7 @@ int32_t ri_batch_autotune(int32_t n_mol, const ri_system* sys, const ri_batch_mo
  *   use_graph  1: capture one iteration as a HIP graph and replay it.
  *   tuning     launch shapes per size bucket (from ri_batch_autotune), or
  *              NULL for the defaults; RI_E_ARG if a value is out of range.
+ *   prec       RI_FP64, RI_FP32, or RI_FP32 | RI_FINAL_FP64.
  *   res        host [n_mol] (out).
  * Returns RI_E_NO_CONV if any molecule did not converge (all results filled).
  * Synchronises the stream once per iteration. */

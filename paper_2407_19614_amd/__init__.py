@@ -5,6 +5,6 @@ package only marshals arguments (PyTorch supplies device memory and streams).
 Importing it does not load the library; the first call does, and raises if
 the library has not been built.
 """
-from .binding import (FP64, FP32, BF16X3, BF16X6, COMPRESSED, RIError, RIProblem, lib, load_library,  # noqa: F401
+from .binding import (FP64, FP32, BF16X3, BF16X6, COMPRESSED, FINAL_FP64, RIError, RIProblem, lib, load_library,  # noqa: F401
                       ri_status_str, workspace_bytes, packed_b_bytes, MLP, MLP_FP32, MLP_BF16,
                       pack_params, unpack_params, NPARAM)

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libri.so")
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 COMPRESSED = 0x10          # flag: B not resident, decompressed per auxiliary slab each call
 COMPRESSED_SLAB = 256
+FINAL_FP64 = 0x20          # batched flag (with FP32): one FP64 exchange build after the FP32 SCF
 OP_BUILD_3C, OP_METRIC, OP_FOCK, OP_ENERGY, OP_GRADIENT = range(5)
 OP_FOCK_DENSITY = 6
 STATUS = {0: "RI_OK", 1: "RI_E_ARG", 2: "RI_E_NOT_PD", 3: "RI_E_NO_CONV", 4: "RI_E_WORKSPACE",
@@ -119,6 +120,8 @@ _SIGS = {
                                      c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_md_verlet": (c_int32, [c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "ri_md_kinetic": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ri_pack_b": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_size_t,
+                            c_void_p]),
     "ri_gradient": (c_int32, [POINTER(RISystem), c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
 }
@@ -259,6 +262,15 @@ class RIProblem:
         if code == 2:
             raise RIError(code, "ri_metric_factor", f": pivot {bad.value}")
         return self
+
+    def pack_b(self, prec):
+        """The packed B of this problem (after metric_factor) in another
+        precision, from the fitted tensor: a new device tensor."""
+        B = self.torch.empty(packed_b_bytes(self.N, self.n_aux, prec), dtype=self.torch.uint8, device=self.device)
+        ws, nb = self._ws_for(OP_METRIC, prec)
+        _check(lib().ri_pack_b(self.N, self.n_aux, _ptr(self.T), _ptr(self.pairs), self.n_pairs, _ptr(B), prec,
+                               _ptr(ws), nb, self.stream()), "ri_pack_b")
+        return B
 
     @property
     def Bc(self):
@@ -445,7 +457,8 @@ _PREP_STREAMS = {}
 
 def prepare_batch(systems, prec=FP64, workers=4, device="cuda"):
     """RIProblem objects for independent systems, each after build_3c and
-    metric_factor in `prec`.  The setups of different systems share no data,
+    metric_factor in `prec` (the FINAL_FP64 flag is ignored here: its batched
+    SCF needs the FP32 B only).  The setups of different systems share no data,
     and each is a chain of small launches with host reads of sizes, so
     `workers` host threads each issue their share on a stream of their own
     and the launches of several systems overlap on the device.  The streams
@@ -466,9 +479,10 @@ def prepare_batch(systems, prec=FP64, workers=4, device="cuda"):
         try:
             with torch.cuda.stream(streams[k]):
                 for i in range(k, len(systems), workers):
-                    pr = RIProblem(systems[i], device=dev, prec=prec)
+                    base = prec & ~FINAL_FP64
+                    pr = RIProblem(systems[i], device=dev, prec=base)
                     pr.build_3c()
-                    pr.metric_factor(prec)
+                    pr.metric_factor(base)
                     out[i] = pr
         except BaseException as e:        # re-raised on the calling thread
             errors.append(e)

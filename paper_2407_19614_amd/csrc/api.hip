@@ -455,6 +455,19 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
     return RI_OK;
 }
 
+int32_t ri_pack_b(int32_t N, int32_t n_aux, const double* Bc, const int32_t* pairs, int64_t n_pairs, void* B,
+                  int32_t prec, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (N <= 0 || n_aux <= 0 || n_pairs < 0 || (n_pairs > 0 && (!Bc || !pairs)) || !B || !ws) return RI_E_ARG;
+    if (prec != RI_FP64 && prec != RI_FP32 && !is_bf16(prec)) return RI_E_UNSUPPORTED;
+    Arena a{(char*)ws, ws_bytes, 0, false};
+    MetricWS w = carve_metric(a, N, n_aux, n_pairs);
+    if (!a.ok()) return RI_E_WORKSPACE;
+    HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
+    if (is_bf16(prec)) HIPC(ri::pack_b_bf16(Bc, n_pairs, w.map, N, n_aux, B, prec, st));
+    else HIPC(ri::pack_b(Bc, n_pairs, w.map, N, n_aux, B, prec, st));
+    return RI_OK;
+}
+
 int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec_arg, const double* Bc,
                    const int32_t* pairs, int64_t n_pairs, const double* C, double* J, double* K, double* gamma,
                    void* ws, size_t ws_bytes, hipStream_t st) {

@@ -174,6 +174,38 @@ __global__ __launch_bounds__(256) void energy_conv_b(const MolDesc* d, int n_mol
     }
 }
 
+// Final FP64 exchange after an FP32 SCF: every molecule takes part once more
+// (its ST_CONV is kept), then the energy is formed from the same D, h and J
+// with the rebuilt K and the molecule is left inactive.
+__global__ void final_begin_b(const MolDesc* d, int n_mol) {
+    if (threadIdx.x == 0) d[blockIdx.x].state[ST_ACTIVE] = 1;
+}
+
+__global__ __launch_bounds__(256) void energy_final_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    __shared__ double sh[4];
+    const int64_t n = (int64_t)m.N * m.N;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double dd = m.D[i];
+        a += dd * m.H[i];
+        b += dd * m.J[i];
+        c += dd * m.K[i];
+    }
+    a = block_sum256(a, sh);
+    b = block_sum256(b, sh);
+    c = block_sum256(c, sh);
+    if (threadIdx.x == 0) {
+        const double en = m.scal[SC_ENUC];
+        m.scal[SC_E + 0] = a + 0.5 * b - 0.5 * c + en;
+        m.scal[SC_E + 1] = en;
+        m.scal[SC_E + 2] = a;
+        m.scal[SC_E + 3] = 0.5 * b;
+        m.scal[SC_E + 4] = -0.5 * c;
+        m.state[ST_ACTIVE] = 0;
+    }
+}
+
 // after the push: advance the ring and keep the slot order (oldest first)
 __global__ void diis_book_b(const MolDesc* d, int n_mol) {
     const MolDesc& m = d[blockIdx.x];
@@ -337,8 +369,10 @@ struct Table {
 
 struct Plan {
     int n_mol = 0, prec = 0, tc2_iters = 48;
+    bool fin = false;                                     // FP64 exchange once after the FP32 SCF
     MolDesc* d = nullptr;
     Table n2, rows, pairs, aux, syrk, tail, cq, x[33];   // x[xs], xs = 4 * tiles + quads
+    Table x64[33];                                        // FP64 shapes of the final exchange (fin)
     // members on 64 x 64 tiles in t, on 128 x 128 tiles in t128
     struct G { ri::GemmDesc* d = nullptr; Table t, t128; bool ta = false, tb = false; };
     G g_lfx, g_t2, g_x2, g_y, g_mo, g_cp, g_c, g_d, g_fd, g_fds;
@@ -411,6 +445,26 @@ hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
 }
 
 
+// The final FP64 exchange of an FP32 SCF.  The descriptors carry xs = xs64
+// (uploaded in place of the FP32 ones); the Fock build's exchange launches
+// then run in FP64 arithmetic on the FP32-stored B and the orbitals C of the
+// last iteration.
+hipError_t final_fp64_b(const Plan& p, hipStream_t st) {
+    const MolDesc* d = p.d;
+    const int nm = p.n_mol;
+    final_begin_b<<<nm, 64, 0, st>>>(d, nm);
+    HC(hipGetLastError());
+    HC(ri::zero_tail_b(d, p.tail.prefix, nm, p.tail.total, RI_FP64, st));
+    HC(ri::cpad_b(d, p.cq.prefix, nm, p.cq.total, RI_FP64, st));
+    for (int xs = 1; xs <= 32; ++xs)
+        if (p.x64[xs].total > 0)
+            HC(ri::x_transform_b(d, p.x64[xs].prefix, nm, p.x64[xs].total, xs, ri::X_F64_B32, st));
+    HC(ri::syrk_b(d, p.syrk.prefix, nm, p.syrk.total, RI_FP64, st));
+    HC(ri::kreduce_b(d, p.rows.prefix, nm, p.rows.total, st));
+    energy_final_b<<<nm, 256, 0, st>>>(d, nm);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 namespace {
@@ -464,7 +518,10 @@ void set_split(MolDesc& m, int ks) {
 static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec, int diis_n,
                             const ri_batch_tuning* tune, Carver& cv, Plan& p, HostPlan& hp) {
     p.n_mol = n_mol;
+    p.fin = (prec & RI_FINAL_FP64) != 0;
+    prec &= ~RI_FINAL_FP64;
     p.prec = prec;
+    const bool wide = prec == RI_FP64 || p.fin;   // Xt and Cq hold FP64 at some point
     hp.mols.assign(n_mol, MolDesc{});
     hp.tile.assign(n_mol, 64);
     for (int i = 0; i < n_mol; ++i) {
@@ -481,7 +538,8 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
             // FP64: whole 16-row tiles, and 4-row quads in place of a last tile of 12 rows or
             // fewer; FP32: whole tiles only
             const int mt = (no + 15) / 16, rem = no - 16 * (mt - 1);
-            m.xs = (prec == RI_FP64 && rem <= 12) ? 4 * (mt - 1) + (rem + 3) / 4 : 4 * mt;
+            m.xs64 = rem <= 12 ? 4 * (mt - 1) + (rem + 3) / 4 : 4 * mt;
+            m.xs = prec == RI_FP64 ? m.xs64 : 4 * mt;
         }
         const int64_t rows = (int64_t)na * no;
         m.rows_pad = (rows + 15) / 16 * 16;
@@ -500,7 +558,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         m.J = cv.take<double>(n2); m.K = cv.take<double>(n2); m.gamma = cv.take<double>(na);
         m.dpair = cv.take<double>(std::max<int64_t>(1, m.n_pairs));
         m.part = cv.take<double>((int64_t)RI_TUNE_MAX_SPLIT * m.npad * m.npad);   // the largest split any tuning may choose
-        m.Xt = cv.take<char>((m.rows_pad + 16) * m.npad * (prec == RI_FP64 ? 8 : 4));
+        m.Xt = cv.take<char>((m.rows_pad + 16) * m.npad * (wide ? 8 : 4));
         double** mats[] = {&m.S, &m.H, &m.LinvS, &m.F, &m.D, &m.T1, &m.T2, &m.E, &m.Fx, &m.X, &m.X2};
         for (double** q : mats) *q = cv.take<double>(n2);
         for (int k = 0; k < 8; ++k) {
@@ -510,7 +568,7 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         m.Y = cv.take<double>((int64_t)N * no);
         m.Cp = cv.take<double>((int64_t)N * no);
         // padded C for the X launch: FP64 [64 nt][64] doubles, FP32 the same shape in floats
-        m.Cq = cv.take<double>((int64_t)m.nt * 64 * (prec == RI_FP64 ? 64 : 32));
+        m.Cq = cv.take<double>((int64_t)m.nt * 64 * (wide ? 64 : 32));
         m.Mo = cv.take<double>((int64_t)no * no);
         m.LinvM = cv.take<double>(64 * 64);
         m.dinvM = cv.take<double>(((N + 63) / 64) * 4096);   // Cholesky diagonal blocks of S
@@ -551,6 +609,12 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
             c[i] = hp.mols[i].xs == xs ? hp.mols[i].nt * ((hp.mols[i].n_aux + 1) / 2) : 0;
         mk(c, p.x[xs]);
     }
+    if (p.fin)
+        for (int xs = 1; xs <= 32; ++xs) {
+            for (int i = 0; i < n_mol; ++i)
+                c[i] = hp.mols[i].xs64 == xs ? hp.mols[i].nt * ((hp.mols[i].n_aux + 1) / 2) : 0;
+            mk(c, p.x64[xs]);
+        }
     // grouped GEMMs: member i of each
     // tunable: the member runs on the molecule's tuned tile (else on 64 x 64)
     auto mkg = [&](Plan::G& g, bool ta, bool tb, bool tunable, auto fill, int act = ST_ACTIVE) {
@@ -602,7 +666,7 @@ namespace {
 
 int32_t check_batch(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec) {
     if (n_mol <= 0 || !sys || !mol) return RI_E_ARG;
-    if (prec != RI_FP64 && prec != RI_FP32) return RI_E_UNSUPPORTED;
+    if (prec != RI_FP64 && prec != RI_FP32 && prec != (RI_FP32 | RI_FINAL_FP64)) return RI_E_UNSUPPORTED;
     for (int i = 0; i < n_mol; ++i) {
         const ri_system& s = sys[i];
         if (s.n_centres <= 0 || s.n_fn <= 0 || s.n_aux <= 0 || s.n_occ <= 0 || !s.xyz || !s.Z || !s.fn_centre ||
@@ -655,7 +719,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
     HIPR(hipGetLastError());
     for (const MolDesc& m : hp.mols) {
         HIPR(ri::fill(m.X, 0.0, (int64_t)m.N * m.N, st));
-        const int64_t xt = (m.rows_pad + 16) * m.npad * (prec == RI_FP64 ? 8 : 4);
+        const int64_t xt = (m.rows_pad + 16) * m.npad * ((prec & ~RI_FINAL_FP64) == RI_FP64 || p.fin ? 8 : 4);
         HIPR(ri::fill((double*)m.Xt, 0.0, xt / 8, st));
     }
     std::memset(out, 0, sizeof(*out));
@@ -704,7 +768,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
             HIPR(hipMemcpyAsync(p.rows.prefix, pr.data(), sizeof(int) * (n_mol + 1), hipMemcpyHostToDevice, st));
             float ms = 0.f;
             rc = time_ms([&] {
-                hipError_t e = ri::syrk_b(p.d, p.syrk.prefix, n_mol, ps[n_mol], prec, st);
+                hipError_t e = ri::syrk_b(p.d, p.syrk.prefix, n_mol, ps[n_mol], p.prec, st);
                 return e == hipSuccess ? ri::kreduce_b(p.d, p.rows.prefix, n_mol, pr[n_mol], st) : e;
             }, st, e0, e1, 2, &ms);
             if (rc != RI_OK) return rc;   // the host vectors stay alive until the timing synchronised
@@ -721,7 +785,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
 extern "C" {
 
 size_t ri_energy_batched_workspace(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec) {
-    if (n_mol <= 0 || !sys || !mol || (prec != RI_FP64 && prec != RI_FP32)) return 0;
+    if (n_mol <= 0 || !sys || !mol || check_batch(n_mol, sys, mol, prec) == RI_E_UNSUPPORTED) return 0;
     Carver cv{nullptr, 0};
     Plan p;
     HostPlan hp;
@@ -823,6 +887,13 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
     if (graph) hipGraphDestroy(graph);
     if (cs != st) hipStreamDestroy(cs);
     HIPR(loop_err);
+    if (p.fin) {
+        std::vector<MolDesc> d64 = hp.mols;
+        for (MolDesc& m : d64) m.xs = m.xs64;
+        HIPR(hipMemcpyAsync(p.d, d64.data(), sizeof(MolDesc) * n_mol, hipMemcpyHostToDevice, st));
+        HIPR(hipStreamSynchronize(st));   // d64 is read by the copy
+        HIPR(final_fp64_b(p, st));
+    }
     // results
     bool all = true;
     for (int i = 0; i < n_mol; ++i) {

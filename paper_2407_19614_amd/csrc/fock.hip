@@ -58,9 +58,11 @@ __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_p
 // CPAD: C is the zero-padded copy [64 * nt rows][cld >= i0 + 16*ceil(W/16)],
 // so every load is unconditional, and loads go through buffer resources;
 // otherwise C is [N][n_occ] with bounds tests.  With a single auxiliary index left (P0 + 1 == n_aux) the second
-// half reads P0's tiles again and its results are not stored.
-template <int MF, int TQ, bool CPAD>
-__device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double* __restrict__ B, int nt, int64_t ntl,
+// half reads P0's tiles again and its results are not stored.  TB is the
+// storage type of B: double, or float widened exactly to FP64 on load (the
+// products and sums stay FP64).
+template <int MF, int TQ, bool CPAD, typename TB = double>
+__device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const TB* __restrict__ B, int nt, int64_t ntl,
                                             const double* __restrict__ C, int cld, int N, int n_occ, int n_aux,
                                             double* __restrict__ Xt, int Npad) {
     constexpr int W = MF * 16 + TQ * 4;            // occupied columns used per slice
@@ -70,8 +72,9 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
     __shared__ double Cs[16][WS + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int ps = wave >> 1, h = wave & 1;
-    const double* Bp0 = B + (int64_t)P0 * ntl * 4096;
-    const double* Bp1 = B + (int64_t)(P0 + 1 < n_aux ? P0 + 1 : P0) * ntl * 4096;
+    const TB* Bp0 = B + (int64_t)P0 * ntl * 4096;
+    const TB* Bp1 = B + (int64_t)(P0 + 1 < n_aux ? P0 + 1 : P0) * ntl * 4096;
+    constexpr int EB = sizeof(TB);                 // bytes per stored B element
     double rb[8], rc[NCR];
 #if defined(__HIP_DEVICE_COMPILE__)
     // CPAD form: buffer loads whose lane offsets are fixed per orientation
@@ -80,14 +83,14 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
     __amdgpu_buffer_rsrc_t rs0, rs1, rsc;
     int boffL[4], boffU[4], coff[NCR];
     if constexpr (CPAD) {
-        const int tb = (int)(ntl * 4096 * 8);
-        rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Bp0), (short)0, tb, 0x00020000);
-        rs1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(Bp1), (short)0, tb, 0x00020000);
+        const int tb = (int)(ntl * 4096 * EB);
+        rs0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<TB*>(Bp0), (short)0, tb, 0x00020000);
+        rs1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<TB*>(Bp1), (short)0, tb, 0x00020000);
         rsc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(C), (short)0, nt * 64 * cld * 8, 0x00020000);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            boffL[r] = (((tid >> 4) + 16 * r) * 64 + (tid & 15)) * 8;     // tile row m, column k
-            boffU[r] = (((tid >> 6) + 4 * r) * 64 + (tid & 63)) * 8;      // tile row k, column m
+            boffL[r] = (((tid >> 4) + 16 * r) * 64 + (tid & 15)) * EB;    // tile row m, column k
+            boffU[r] = (((tid >> 6) + 4 * r) * 64 + (tid & 63)) * EB;     // tile row k, column m
         }
 #pragma unroll
         for (int r = 0; r < NCR; ++r) {
@@ -98,6 +101,13 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
     auto ldb = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
     };
+    // a B element in FP64 (FP32 storage is widened exactly)
+    auto ldbt = [](__amdgpu_buffer_rsrc_t rs, int vo, int so) -> double {
+        if constexpr (EB == 8)
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+        else
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+    };
 #endif
     auto load_b = [&](int J, int k0) {
         const bool lower = J <= I;
@@ -105,13 +115,13 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const double*
         if constexpr (CPAD) {
 #if defined(__HIP_DEVICE_COMPILE__)
             if (lower) {
-                const int so = (tile * 4096 + k0) * 8;
+                const int so = (tile * 4096 + k0) * EB;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) { rb[r] = ldb(rs0, boffL[r], so); rb[4 + r] = ldb(rs1, boffL[r], so); }
+                for (int r = 0; r < 4; ++r) { rb[r] = ldbt(rs0, boffL[r], so); rb[4 + r] = ldbt(rs1, boffL[r], so); }
             } else {
-                const int so = (tile * 4096 + k0 * 64) * 8;
+                const int so = (tile * 4096 + k0 * 64) * EB;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) { rb[r] = ldb(rs0, boffU[r], so); rb[4 + r] = ldb(rs1, boffU[r], so); }
+                for (int r = 0; r < 4; ++r) { rb[r] = ldbt(rs0, boffU[r], so); rb[4 + r] = ldbt(rs1, boffU[r], so); }
             }
 #endif
         } else {
@@ -900,6 +910,9 @@ __global__ __launch_bounds__(256, 2) void x_b_kernel(const ri::MolDesc* d, const
     if constexpr (PREC == RI_FP64)
         x2_body_f64<MF, TQ, true>(I, P0, 0, (const double*)m.B, m.nt, m.ntl, m.Cq, 64, m.N, m.n_occ, m.n_aux,
                                   (double*)m.Xt, m.npad);
+    else if constexpr (PREC == ri::X_F64_B32)
+        x2_body_f64<MF, TQ, true, float>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, m.Cq, 64, m.N, m.n_occ,
+                                         m.n_aux, (double*)m.Xt, m.npad);
     else
         x2_body_f32<MF, true>(I, P0, 0, (const float*)m.B, m.nt, m.ntl, nullptr, (const float*)m.Cq, 64, m.N,
                               m.n_occ, m.n_aux, (float*)m.Xt, m.npad);
@@ -1023,6 +1036,14 @@ hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int tot
     if (prec == RI_FP64) {
         switch (xs) {
 #define XB(f, q) case 4 * f + q: x_b_kernel<f, q, RI_FP64><<<total, 256, 0, st>>>(d, prefix, n_mol); break;
+            XB(0, 1) XB(0, 2) XB(0, 3) XB(1, 0) XB(1, 1) XB(1, 2) XB(1, 3) XB(2, 0)
+            XB(2, 1) XB(2, 2) XB(2, 3) XB(3, 0) XB(3, 1) XB(3, 2) XB(3, 3) XB(4, 0)
+#undef XB
+            default: return hipErrorInvalidValue;
+        }
+    } else if (prec == X_F64_B32) {
+        switch (xs) {
+#define XB(f, q) case 4 * f + q: x_b_kernel<f, q, X_F64_B32><<<total, 256, 0, st>>>(d, prefix, n_mol); break;
             XB(0, 1) XB(0, 2) XB(0, 3) XB(1, 0) XB(1, 1) XB(1, 2) XB(1, 3) XB(2, 0)
             XB(2, 1) XB(2, 2) XB(2, 3) XB(3, 0) XB(3, 1) XB(3, 2) XB(3, 3) XB(4, 0)
 #undef XB

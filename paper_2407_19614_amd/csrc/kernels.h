@@ -113,6 +113,7 @@ void set_hip_error(const char* text);   // text returned by ri_last_hip_error
 struct MolDesc {
     int N, n_aux, n_occ, nt, npad, ks, diis_n;
     int xs;       // X launch shape: 4 * (whole 16-row occupied tiles) + (trailing 4-row quads)
+    int xs64;     // the FP64 X shape (final FP64 exchange after an FP32 SCF)
     int64_t n_pairs, ntl, rows_pad, chunk;
     double tol_E, tol_err;
     const int32_t* pairs;
@@ -152,7 +153,9 @@ __device__ __forceinline__ void decode_item(const int* prefix, int n_mol, int L,
 }
 
 // batched Fock build pieces (fock.hip); `prec` is RI_FP64 or RI_FP32 for all molecules
-// X for the molecules whose xs equals `xs` (one launch per shape present)
+// X for the molecules whose xs equals `xs` (one launch per shape present); prec may
+// also be X_F64_B32: FP64 arithmetic (FP64 shapes, Cq and Xt) on FP32-stored B
+constexpr int X_F64_B32 = 0x41;
 hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int xs, int prec, hipStream_t st);
 // Cq of every active molecule from its C (prefix counts 64-row blocks), in the
 // exchange precision `prec`

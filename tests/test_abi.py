@@ -93,6 +93,20 @@ def test_bad_arguments_rejected_before_device_work():
                                      ctypes.byref(t), ctypes.byref(res1), ws, 256, None) == 1
     assert lib.ri_batch_autotune(1, ctypes.byref(sysarr), ctypes.byref(mols), 0, None, ws, 256, None) == 1
     assert ctypes.sizeof(Bd.BatchTuning) == 4 + 4 * 8 * 4
+    # the final-FP64 flag goes with FP32 exchange only
+    assert lib.ri_energy_batched(1, ctypes.byref(sysarr), ctypes.byref(mols), P.FP64 | P.FINAL_FP64,
+                                 ctypes.byref(opts6), 0, None, ctypes.byref(res1), ws, 256, None) == 7
+    assert lib.ri_energy_batched(1, ctypes.byref(sysarr), ctypes.byref(mols), P.FP32 | P.FINAL_FP64,
+                                 ctypes.byref(opts6), 0, None, ctypes.byref(res1), ws, 256, None) == 1
+    assert lib.ri_energy_batched_workspace(1, ctypes.byref(sysarr), ctypes.byref(mols),
+                                           P.BF16X3 | P.FINAL_FP64) == 0
+    assert ctypes.sizeof(Bd.BatchMol) == 6 * 8
+    # ri_pack_b: sizes and pointers first, then the precision (no flags)
+    assert lib.ri_pack_b(0, 10, ws, ws, 1, ws, P.FP64, ws, 256, None) == 1
+    assert lib.ri_pack_b(10, 10, None, ws, 1, ws, P.FP64, ws, 256, None) == 1
+    assert lib.ri_pack_b(10, 10, ws, ws, 1, None, P.FP64, ws, 256, None) == 1
+    assert lib.ri_pack_b(10, 10, ws, ws, 1, ws, P.FP64 | P.COMPRESSED, ws, 256, None) == 7
+    assert lib.ri_pack_b(10, 10, ws, ws, 1, ws, 9, ws, 256, None) == 7
 
 
 def test_product_path_has_no_oracle_import():

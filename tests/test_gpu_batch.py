@@ -60,6 +60,50 @@ def test_batched_fp32_error():
         assert r["converged"] and abs(r["E_total"] - ref.E) < 1e-6
 
 
+def test_pack_b_matches_metric_factor():
+    """ri_pack_b repacks the fitted tensor into the same bytes that
+    ri_metric_factor writes, in FP64, FP32 and the split-BF16 forms."""
+    need_gpu()
+    import torch
+    import paper_2407_19614_amd as P
+    print("case: ri_pack_b vs ri_metric_factor", flush=True)
+    s = small_batch()[3]
+    for prec in (P.FP64, P.FP32, P.BF16X3, P.BF16X6):
+        pr = P.RIProblem(s, prec=prec)
+        pr.build_3c()
+        pr.metric_factor(prec)
+        B2 = pr.pack_b(prec)
+        torch.cuda.synchronize()
+        assert B2.numel() == pr.B.numel() and torch.equal(B2, pr.B), prec
+
+
+def test_batched_fp32_final_fp64():
+    """FP32 exchange through the SCF, then one exchange build in FP64
+    arithmetic (from the FP32-stored B) at the converged density.  The energy
+    is stationary in the density, so only B's FP32 rounding is left to first
+    order: the energy agrees with the FP64 batched SCF and the oracle to
+    1e-7 Eh, ten times inside the 1e-6 Eh bar of reduced precision."""
+    need_gpu()
+    import paper_2407_19614_amd as P
+    from paper_2407_19614_amd.binding import energy_batched, prepare_batch
+    print("case: batched fp32 + final fp64", flush=True)
+    systems = small_batch()
+    probs = prepare_batch(systems, P.FP32 | P.FINAL_FP64, workers=2)
+    res, _, _ = energy_batched(probs, P.FP32 | P.FINAL_FP64, tol_E=1e-8, tol_err=1e-6)
+    res32, _, _ = energy_batched(probs, P.FP32, tol_E=1e-8, tol_err=1e-6)
+    p64 = prepare_batch(systems, P.FP64, workers=2)
+    res64, _, _ = energy_batched(p64, P.FP64, tol_E=1e-11, tol_err=1e-9)
+    for k, (s, r, r32, r64) in enumerate(zip(systems, res, res32, res64)):
+        print(k, r["E_total"] - r64["E_total"], r32["E_total"] - r64["E_total"], flush=True)
+        assert r["converged"] and r["n_iter"] == r32["n_iter"]
+        assert abs(r["E_total"] - r64["E_total"]) < 1e-7, (k, r["E_total"], r64["E_total"])
+        # only the exchange energy changes: h, J and D are those of the last FP32 iteration
+        assert abs(r["E_1e"] - r32["E_1e"]) < 1e-12 * max(1.0, abs(r32["E_1e"]))
+        if k < 2:
+            ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
+            assert abs(r["E_total"] - ref.E) < 1e-7
+
+
 def test_batched_autotune_and_forced_shapes_agree():
     """Molecules in four size buckets (N = 40, 140, 270, 400): the autotuner's
     choices are valid, and the SCF energies under the default shapes, the

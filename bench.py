@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="also run the batched workload (256 molecules, 10-60 centres) and report SCF/s")
     ap.add_argument("--batched-n", type=int, default=256, help="molecules in the batched workload")
-    ap.add_argument("--batched-prec", default="fp32", choices=["fp32", "fp64", "fp32f64"],
+    ap.add_argument("--batched-prec", default="fp32f64", choices=["fp32", "fp64", "fp32f64"],
                     help="exchange precision of the batched workload")
     ap.add_argument("--aimd", action="store_true",
                     help="also run Born-Oppenheimer NVE dynamics of the N=1000 workload (1 fs steps)")
@@ -313,11 +313,13 @@ def compressed_leg(s, C, res64, args, P, torch, np, ms_fp64):
     return out
 
 
-def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32", autotune=True):
+def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=True):
     """256 independent He-like clusters with n_centres ~ U{10..60} (N = 10 per
     centre, N_aux = 30 per centre, n_occ = n_centres), seeds 4001...: pairs, 3c
-    integrals and FP32 B per molecule, then one lockstep SCF per wave of
-    molecules (HIP-graph replay, FP32 exchange, FP64 everything else).  SCF/s
+    integrals and B per molecule, then one lockstep SCF per wave of molecules
+    (HIP-graph replay, FP64 everything but the exchange).  prec_name picks the
+    exchange: "fp32f64" FP32 iterations and one final exchange build in FP64
+    arithmetic at the converged density, "fp32" FP32 only, "fp64".  SCF/s
     counts the whole job from the first screening to the last convergence.
     The plain FP64 single-molecule path is timed on the first baseline_n
     molecules for comparison; energies are checked against stored oracle

@@ -168,7 +168,8 @@ def main():
         out["scf"]["abs_dE_vs_oracle"] = abs(res["E_total"] - ref["E_total"])
         if not args.no_pipeline:
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
-    out["precision"] = precision_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
+    out["precision"] = precision_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step,
+                                     phases.get("scf_s"))
     out["compressed"] = compressed_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
     out["density_fock"] = density_leg(pr, C, torch, np)
     if args.batched:
@@ -193,13 +194,16 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def precision_leg(s, C, res64, args, P, torch, np, ms_fp64):
+def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None):
     """Reduced-precision exchange contractions at the same workload: Fock
     builds/s and speedup over FP64, and each SCF energy's difference from the
     FP64 one (skipped when res64 is None).  FP32: FP32 MFMA; BF16X3 / BF16X6:
     two- and three-part BF16 splits with 3 and 6 products on BF16 MFMA.
     gamma and J stay FP64.  The X roofline counts the MFMA work actually
-    issued: full square tiles of the padded size times the product count."""
+    issued: full square tiles of the padded size times the product count.
+    fp32_final_fp64: the FP32 SCF followed by one exchange build in FP64
+    arithmetic at the converged density (RI_FINAL_FP64), timed as a whole SCF
+    against the FP64 SCF (scf_s64)."""
     dev = C.device
     N, na = s.N, s.n_aux
     out = {}
@@ -241,9 +245,23 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64):
                                        "b_read_GBs": round(by / tx / 1e9, 1),
                                        "hbm_frac": round(by / tx / 1e9 / PEAK_HBM_GBS, 4)}
         if res64 is not None:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
             r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t_scf = time.perf_counter() - t
             out[name].update({"scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
-                              "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
+                              "scf_s": round(t_scf, 4), "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
+            if prec == P.FP32:
+                t = time.perf_counter()
+                r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False,
+                                  final_fp64=True)
+                torch.cuda.synchronize()
+                t_fin = time.perf_counter() - t
+                out["fp32_final_fp64"] = {
+                    "scf_s": round(t_fin, 4), "scf_E": r["E_total"], "scf_iters": r["n_iter"],
+                    "scf_converged": r["converged"], "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"]),
+                    "scf_speedup_vs_fp64": round(scf_s64 / t_fin, 3) if scf_s64 else None}
         del pr, J, K, g   # blocks stay in torch's cache for the next leg (see batched_leg)
     return out
 

@@ -74,6 +74,20 @@ typedef enum {
 #define RI_COMPRESSED 0x10
 #define RI_COMPRESSED_SLAB 256
 
+/* Flag OR-ed into the precision of ri_energy and of the batched SCF calls,
+ * with RI_FP32 only (resident B): the SCF iterations run with FP32 exchange
+ * as for RI_FP32; once converged, the exchange matrix is rebuilt once in FP64
+ * arithmetic (the FP32-stored B widened exactly on load; C, X and K in FP64)
+ * at the converged density, and the reported energy (E_total, E_K) is the one
+ * with this K.  The energy is stationary in the density, so the density's
+ * FP32 error enters it only to second order, while FP32 arithmetic in the
+ * exchange shifts it to first order; what stays first order is the FP32
+ * rounding of B.  n_iter, converged, last_dE, max_err and the returned Fock
+ * matrix are those of the FP32 iterations; a run that does not converge
+ * reports its FP32 energies.  Workspaces hold FP64 Xt and C copies (sizes
+ * from the same flag).  Other calls reject it (RI_E_UNSUPPORTED). */
+#define RI_FINAL_FP64 0x20
+
 /* Molecular system.  The struct lives in host memory; every array is a
  * device pointer.  Positions in bohr. */
 typedef struct {
@@ -238,7 +252,8 @@ int32_t ri_fock_jk_density(int32_t N, int32_t n_aux, const double* Bc, const int
  * The occupied space of each extrapolated Fock matrix (the n_occ lowest
  * orbitals of F C = S C eps) is obtained as the spectral projector by
  * trace-correcting purification, all on the GPU.
- *   B, prec   as for ri_fock_jk (B may be NULL with prec | RI_COMPRESSED).
+ *   B, prec   as for ri_fock_jk (B may be NULL with prec | RI_COMPRESSED);
+ *             prec may also be RI_FP32 | RI_FINAL_FP64.
  *   guess     device C_occ [N][n_occ] (guess_kind 1) or D [N][N] (guess_kind 2),
  *             else NULL.
  *   C_occ     [N][n_occ] out: orthonormal (C^T S C = 1) occupied orbitals
@@ -345,17 +360,6 @@ typedef struct {
     double* F;              /* [N][N] out, or NULL                              */
 } ri_batch_mol;
 
-/* Flag OR-ed into the precision of the batched calls, with RI_FP32 only.
- * The SCF of every molecule runs with FP32 exchange as for RI_FP32; after
- * the last iteration its exchange matrix is rebuilt once in FP64 arithmetic
- * (the FP32-stored B widened on load; C, X and K in FP64) at the density of
- * that iteration, and the reported energy (E_total, E_K) is the one with
- * this K.  The energy is stationary in the density, so the density's FP32
- * error enters it only to second order, while FP32 arithmetic in the
- * exchange shifts it to first order; what remains first order is the FP32
- * rounding of B.  n_iter, converged, last_dE, max_err and F are those of the
- * FP32 iterations.  The workspace holds FP64 Xt and C copies. */
-#define RI_FINAL_FP64 0x20
 
 /* Workspace bytes for ri_energy_batched (0 on invalid input).  Supported:
  * prec RI_FP64, RI_FP32 or RI_FP32 | RI_FINAL_FP64, n_occ <= 64 for every

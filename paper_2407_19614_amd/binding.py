@@ -335,10 +335,12 @@ class RIProblem:
         return J, K
 
     def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True,
-               guess_density=None, density_fock=False):
+               guess_density=None, density_fock=False, final_fp64=False):
         """SCF.  guess: C_occ start; guess_density: density start, through its
         natural orbitals, or (density_fock=True) through the occupied space of
-        its own Fock matrix (J and K built from the density)."""
+        its own Fock matrix (J and K built from the density).  final_fp64
+        (FP32 problems): one FP64 exchange build at the converged density
+        gives the reported energy (RI_FINAL_FP64)."""
         torch = self.torch
         kind = 0 if guess is None else 1
         if guess_density is not None:
@@ -348,9 +350,10 @@ class RIProblem:
         F = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
         D = torch.empty_like(F)
         res = SCFResult()
-        ws, nb = self._ws_for(OP_ENERGY)
+        fin = FINAL_FP64 if final_fp64 else 0
+        ws, nb = self._ws_for(OP_ENERGY, self.prec | fin)
         g = None if guess is None else guess.contiguous()
-        code = lib().ri_energy(ctypes.byref(self.c_sys), _ptr(self.B), self.pflag, _ptr(self.T), _ptr(self.pairs),
+        code = lib().ri_energy(ctypes.byref(self.c_sys), _ptr(self.B), self.pflag | fin, _ptr(self.T), _ptr(self.pairs),
                                self.n_pairs, ctypes.byref(opts), _ptr(g), _ptr(C), _ptr(F), _ptr(D),
                                ctypes.byref(res), _ptr(ws), nb, self.stream())
         if code == 3 and not raise_on_noconv:

@@ -54,12 +54,14 @@ bool is_bf16(int prec) { return prec == RI_BF16X3 || prec == RI_BF16X6; }
 // A precision argument: an ri_precision, optionally with RI_COMPRESSED (FP64 / FP32 only).
 struct Prec {
     int base;
-    bool comp, ok;
+    bool comp, fin, ok;
 };
-Prec split_prec(int32_t p) {
-    Prec r{p & ~RI_COMPRESSED, (p & RI_COMPRESSED) != 0, true};
+// fin (RI_FINAL_FP64) is accepted where allow_fin is set, with resident FP32 B only
+Prec split_prec(int32_t p, bool allow_fin = false) {
+    Prec r{p & ~(RI_COMPRESSED | RI_FINAL_FP64), (p & RI_COMPRESSED) != 0, (p & RI_FINAL_FP64) != 0, true};
     if (r.base < 0 || r.base > 3) r.ok = false;
     if (r.comp && r.base != RI_FP64 && r.base != RI_FP32) r.ok = false;
+    if (r.fin && (!allow_fin || r.base != RI_FP32 || r.comp)) r.ok = false;
     return r;
 }
 int comp_slab(int n_aux) { return std::min(RI_COMPRESSED_SLAB, (n_aux + 1) / 2 * 2); }
@@ -384,7 +386,7 @@ size_t ri_packed_b_bytes(int32_t N, int32_t n_aux, int32_t prec) {
 }
 
 size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, int64_t n_pairs, int32_t prec_arg) {
-    const Prec pp = split_prec(prec_arg);
+    const Prec pp = split_prec(prec_arg, op == RI_OP_ENERGY);
     const int prec = pp.base;
     if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_pairs < 0 || !pp.ok) return 0;
     Arena a{nullptr, 0, 0, true};
@@ -392,7 +394,7 @@ size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, i
         case RI_OP_BUILD_3C: carve_build(a, N); break;
         case RI_OP_METRIC: carve_metric(a, N, n_aux, n_pairs); break;
         case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp); break;
-        case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, prec, 8, pp.comp); break;
+        case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, pp.fin ? RI_FP64 : prec, 8, pp.comp); break;
         case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec, pp.comp); break;
         case RI_OP_FOCK_DENSITY: carve_density(a, N, n_aux, n_pairs); break;
         case RI_OP_MLP: {
@@ -516,7 +518,7 @@ int32_t ri_fock_jk_density(int32_t N, int32_t n_aux, const double* Bc, const int
 int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const ri_scf_opts* opts, const double* guess, double* C_occ, double* F_out,
                   double* D_out, ri_scf_result* res, void* ws, size_t ws_bytes, hipStream_t st) {
-    const Prec pp = split_prec(prec_arg);
+    const Prec pp = split_prec(prec_arg, true);
     const int prec = pp.base;
     if (!valid_sys(sys) || (!B && !pp.comp) || !opts || !C_occ || !F_out || !res || !ws || n_pairs < 0 ||
         (n_pairs > 0 && (!Bc || !pairs)))
@@ -530,7 +532,8 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    EnergyWS w = carve_energy(a, N, na, no, n_pairs, prec, 8, pp.comp);
+    // with the final FP64 build the exchange workspace holds FP64 Xt and C copies
+    EnergyWS w = carve_energy(a, N, na, no, n_pairs, pp.fin ? RI_FP64 : prec, 8, pp.comp);
     if (!a.ok()) return RI_E_WORKSPACE;
     std::memset(res, 0, sizeof(*res));
 
@@ -631,6 +634,19 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
         }
         rc = occupied_space(Fx, N, no, w, true, C_occ, st);
         if (rc) return rc;
+    }
+    if (pp.fin && converged) {
+        // one exchange build in FP64 arithmetic (the FP32-stored B widened on
+        // load) at the converged density; the energy from the same D, h and J
+        HIPC(ri::x_transform(B, ri::X_F64_B32, N, na, no, C_occ, w.fock.Cp, w.fock.Xt, st));
+        HIPC(ri::k_syrk(w.fock.Xt, RI_FP64, N, na, no, w.fock.part, w.fock.ks, w.K, st));
+        HIPC(ri::energy_terms(w.D, w.H, w.J, w.K, n2, w.scal + 8, w.scal, w.red, st));
+        HIPC(hipMemcpyAsync(host, w.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        res->E_total = host[0];
+        res->E_1e = host[2];
+        res->E_J = host[3];
+        res->E_K = host[4];
     }
     HIPC(ri::copy(F_out, w.F, n2, st));
     if (D_out) HIPC(ri::copy(D_out, w.D, n2, st));

@@ -226,13 +226,13 @@ __device__ __forceinline__ void x2_body_f64(int I, int P0, int i0, const TB* __r
         }
 }
 
-template <int MF, int TQ>
-__global__ __launch_bounds__(256, 2) void x2_kernel_f64(const double* __restrict__ B, int nt, int64_t ntl,
+template <int MF, int TQ, typename TB = double>
+__global__ __launch_bounds__(256, 2) void x2_kernel_f64(const TB* __restrict__ B, int nt, int64_t ntl,
                                                      const double* __restrict__ Cp, int cld, int N, int n_occ,
                                                      int n_aux, double* __restrict__ Xt, int Npad) {
     const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    x2_body_f64<MF, TQ, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, Cp, cld, N, n_occ,
-                              n_aux, Xt, Npad);
+    x2_body_f64<MF, TQ, true, TB>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, Cp, cld, N,
+                                  n_occ, n_aux, Xt, Npad);
 }
 
 
@@ -766,6 +766,23 @@ int cpad_ld(int n_occ) { return (n_occ + 127) / 128 * 128; }
 int64_t cpad_elems(int N, int n_occ) { return (int64_t)n_tiles_1d(N) * 64 * cpad_ld(n_occ); }
 
 
+// The FP64 X launch for shape code 4 * (16-row tiles) + (4-row quads); B
+// stored as TB (double, or float widened on load).
+template <typename TB>
+hipError_t x_f64_launch(const TB* b, dim3 grid, int shape, int nt, int64_t ntl, const double* Cp, int cld, int N,
+                        int n_occ, int n_aux, double* x, int Npad, hipStream_t st) {
+    switch (shape) {
+#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q, TB><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, N, n_occ, n_aux, x, Npad); break;
+#define XROW(f) XCASE(f, 1) XCASE(f, 2) XCASE(f, 3)
+        XROW(0) XROW(1) XROW(2) XROW(3) XROW(4) XROW(5) XROW(6) XROW(7)
+        XCASE(1, 0) XCASE(2, 0) XCASE(3, 0) XCASE(4, 0) XCASE(5, 0) XCASE(6, 0) XCASE(7, 0) XCASE(8, 0)
+#undef XROW
+#undef XCASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C, double* Cp, void* Xt,
                        hipStream_t st) {
     const int nt = n_tiles_1d(N), Npad = xt_ld(N);
@@ -788,8 +805,7 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
         }
         return hipGetLastError();
     }
-    if (prec != RI_FP64) return hipErrorInvalidValue;
-    const double* b = (const double*)B;
+    if (prec != RI_FP64 && prec != X_F64_B32) return hipErrorInvalidValue;
     double* x = (double*)Xt;
     const int64_t ntl = n_tiles(N);
     // occupied rows of one 128-wide chunk: whole 16-row tiles plus, when the
@@ -805,16 +821,8 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
     if (ntl * 4096 * 8 > INT32_MAX || (int64_t)rows * cld * 8 > INT32_MAX) return hipErrorInvalidValue;
     cpad_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cp);
     RI_TRY(hipGetLastError());
-    switch (mf * 4 + tq) {
-#define XCASE(f, q) case f * 4 + q: x2_kernel_f64<f, q><<<grid, 256, 0, st>>>(b, nt, ntl, Cp, cld, N, n_occ, n_aux, x, Npad); break;
-#define XROW(f) XCASE(f, 1) XCASE(f, 2) XCASE(f, 3)
-        XROW(0) XROW(1) XROW(2) XROW(3) XROW(4) XROW(5) XROW(6) XROW(7)
-        XCASE(1, 0) XCASE(2, 0) XCASE(3, 0) XCASE(4, 0) XCASE(5, 0) XCASE(6, 0) XCASE(7, 0) XCASE(8, 0)
-#undef XROW
-#undef XCASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (prec == X_F64_B32) return x_f64_launch((const float*)B, grid, mf * 4 + tq, nt, ntl, Cp, cld, N, n_occ, n_aux, x, Npad, st);
+    return x_f64_launch((const double*)B, grid, mf * 4 + tq, nt, ntl, Cp, cld, N, n_occ, n_aux, x, Npad, st);
 }
 
 int k_split_count(int N, int n_aux, int n_occ) {

@@ -24,6 +24,9 @@ hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, 
 // ---- Fock build pieces
 // Xt[P][i][mu] (row stride Npad = 64 * tiles) = (B^P C_occ)^T
 // Cp: workspace for C_occ zero-padded to [64 * tiles][cpad_ld(n_occ)].
+// prec RI_FP64, RI_FP32, or X_F64_B32: FP64 arithmetic (FP64 Cp and Xt) on
+// FP32-stored B, widened exactly on load.
+constexpr int X_F64_B32 = 0x41;
 int cpad_ld(int n_occ);
 int64_t cpad_elems(int N, int n_occ);
 hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, const double* C,
@@ -154,8 +157,7 @@ __device__ __forceinline__ void decode_item(const int* prefix, int n_mol, int L,
 
 // batched Fock build pieces (fock.hip); `prec` is RI_FP64 or RI_FP32 for all molecules
 // X for the molecules whose xs equals `xs` (one launch per shape present); prec may
-// also be X_F64_B32: FP64 arithmetic (FP64 shapes, Cq and Xt) on FP32-stored B
-constexpr int X_F64_B32 = 0x41;
+// also be X_F64_B32 (FP64 shapes, Cq and Xt)
 hipError_t x_transform_b(const MolDesc* d, const int* prefix, int n_mol, int total, int xs, int prec, hipStream_t st);
 // Cq of every active molecule from its C (prefix counts 64-row blocks), in the
 // exchange precision `prec`

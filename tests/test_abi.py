@@ -101,6 +101,16 @@ def test_bad_arguments_rejected_before_device_work():
     assert lib.ri_energy_batched_workspace(1, ctypes.byref(sysarr), ctypes.byref(mols),
                                            P.BF16X3 | P.FINAL_FP64) == 0
     assert ctypes.sizeof(Bd.BatchMol) == 6 * 8
+    # the final-FP64 flag: ri_energy (and its workspace) with resident FP32 B only
+    W = lib.ri_workspace_bytes
+    assert W(3, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) > W(3, 100, 300, 10, 1000, P.FP32) > 0
+    assert W(3, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) == W(3, 100, 300, 10, 1000, P.FP64)
+    for prec in (P.FP64 | P.FINAL_FP64, P.FP32 | P.COMPRESSED | P.FINAL_FP64, P.BF16X6 | P.FINAL_FP64):
+        assert W(3, 100, 300, 10, 1000, prec) == 0
+    assert W(2, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) == 0      # Fock build
+    assert W(4, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) == 0      # gradient
+    assert lib.ri_fock_jk(10, 10, 2, ws, P.FP32 | P.FINAL_FP64, None, None, 0, ws, ws, ws, None, ws, 64,
+                          None) == 7
     # ri_pack_b: sizes and pointers first, then the precision (no flags)
     assert lib.ri_pack_b(0, 10, ws, ws, 1, ws, P.FP64, ws, 256, None) == 1
     assert lib.ri_pack_b(10, 10, None, ws, 1, ws, P.FP64, ws, 256, None) == 1

@@ -254,7 +254,8 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None):
                               "scf_s": round(t_scf, 4), "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
             if prec == P.FP32:
                 t = time.perf_counter()
-                r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False,
+                # the density's error enters the final energy only to second order (see batched_leg)
+                r, *_ = pr.energy(tol_E=1e-6, tol_err=3e-5, max_iter=60, raise_on_noconv=False,
                                   final_fp64=True)
                 torch.cuda.synchronize()
                 t_fin = time.perf_counter() - t
@@ -349,8 +350,11 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=Tr
     from paper_2407_19614_amd.binding import batch_autotune, energy_batched, prepare_batch
     systems = synth.batched_systems(n_mol)
     prec = {"fp32": P.FP32, "fp64": P.FP64, "fp32f64": P.FP32 | P.FINAL_FP64}[prec_name]
-    # FP32 exchange (with or without the final FP64 exchange build) iterates to its own noise floor
-    tol = dict(tol_E=1e-7, tol_err=1e-5) if prec & 0xF == P.FP32 else dict(tol_E=1e-10, tol_err=1e-8)
+    # FP32 exchange iterates to its own noise floor.  With the final FP64 build the
+    # density's error enters the energy only to second order, so its iterations stop
+    # earlier: at these thresholds the error stays that of B's FP32 rounding.
+    tol = {"fp32": dict(tol_E=1e-7, tol_err=1e-5), "fp32f64": dict(tol_E=1e-6, tol_err=3e-5),
+           "fp64": dict(tol_E=1e-10, tol_err=1e-8)}[prec_name]
     log = lambda m: print(m, file=sys.stderr, flush=True)
     E = np.full(len(systems), np.nan)
     iters = np.zeros(len(systems), dtype=int)

@@ -174,15 +174,17 @@ __global__ __launch_bounds__(256) void energy_conv_b(const MolDesc* d, int n_mol
     }
 }
 
-// Final FP64 exchange after an FP32 SCF: every molecule takes part once more
-// (its ST_CONV is kept), then the energy is formed from the same D, h and J
-// with the rebuilt K and the molecule is left inactive.
+// Final FP64 exchange after an FP32 SCF: every converged molecule takes part
+// once more, then the energy is formed from the same D, h and J with the
+// rebuilt K and the molecule is left inactive.  A molecule that did not
+// converge keeps its FP32 energies.
 __global__ void final_begin_b(const MolDesc* d, int n_mol) {
-    if (threadIdx.x == 0) d[blockIdx.x].state[ST_ACTIVE] = 1;
+    if (threadIdx.x == 0) d[blockIdx.x].state[ST_ACTIVE] = d[blockIdx.x].state[ST_CONV];
 }
 
 __global__ __launch_bounds__(256) void energy_final_b(const MolDesc* d, int n_mol) {
     const MolDesc& m = d[blockIdx.x];
+    if (!m.state[ST_ACTIVE]) return;
     __shared__ double sh[4];
     const int64_t n = (int64_t)m.N * m.N;
     double a = 0.0, b = 0.0, c = 0.0;

@@ -102,6 +102,11 @@ def test_batched_fp32_final_fp64():
         if k < 2:
             ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
             assert abs(r["E_total"] - ref.E) < 1e-7
+    # molecules that do not converge keep their FP32 energies
+    rn, _, _ = energy_batched(probs, P.FP32 | P.FINAL_FP64, max_iter=2, raise_on_noconv=False)
+    rn32, _, _ = energy_batched(probs, P.FP32, max_iter=2, raise_on_noconv=False)
+    for r, r32 in zip(rn, rn32):
+        assert not r["converged"] and r["E_total"] == r32["E_total"] and r["E_K"] == r32["E_K"]
 
 
 def test_batched_autotune_and_forced_shapes_agree():

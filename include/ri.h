@@ -195,14 +195,17 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
                    void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ri_fock_jk_timed - ri_fock_jk with phase events, for measurement.
- * Same computation and arguments as ri_fock_jk (paper: eq. j_ri, eq. k_ri_2,
- * eq. tp, Algorithm 1 Fock-build loop); additionally records, on `stream`,
- *   events[0] before the gamma/J contraction, events[1] before the exchange
- *   half-transform X^P = B^P C_occ, events[2] before the K = sum X X^T SYRK
- *   and its reduction, events[3] after the last kernel.
- * events: four events created by the caller (host array).  Every phase
- * runs on `stream`, in order (no side stream), so the events bracket each
- * phase alone. */
+ * Same computation, arguments and schedule as ri_fock_jk (paper: eq. j_ri,
+ * eq. k_ri_2, eq. tp, Algorithm 1 Fock-build loop): the gamma/J contraction
+ * runs on the library's side stream beside the exchange.  Records
+ *   events[0] on `stream` before both parts;
+ *   events[1] on the side stream after gamma/J (gamma/J = events[0..1]);
+ *   events[2] on `stream` after the exchange half-transform X^P = B^P C_occ
+ *             (X = events[0..2], measured while gamma/J runs beside it);
+ *   events[3] on `stream` after the K = sum X X^T SYRK, its reduction and
+ *             the wait for gamma/J (SYRK = events[2..3]).
+ * events: four events created by the caller (host array).  RI_E_HIP if the
+ * side stream is not available. */
 int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
                          const double* Bc, const int32_t* pairs, int64_t n_pairs,
                          const double* C_occ, double* J, double* K, double* gamma,

@@ -266,19 +266,31 @@ struct Fork {
 
 // The Coulomb part (pair densities, gamma, J) reads only B_c and C_occ and
 // is bound by HBM bandwidth; the exchange contractions are bound by MFMA
-// throughput and touch none of its buffers.  Outside the phase-timed form the
-// Coulomb part runs on the side stream, concurrently with the exchange, and
-// the caller's stream waits for it before the call returns.
+// throughput and touch none of its buffers.  The Coulomb part runs on the
+// side stream, concurrently with the exchange, and the caller's stream waits
+// for it before the call returns.  ev (phase-timed form): ev[0] on `st`
+// before both parts, ev[1] on the side stream after the Coulomb part, ev[2]
+// on `st` after X, ev[3] on `st` after the SYRK and the join.
 int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const double* C, double* J, double* K, double* gamma, const FockWS& w,
                   hipStream_t st, hipEvent_t* ev = nullptr) {
     double* g = gamma ? gamma : w.gamma;
-    Fork fk;
-    const bool overlap = !ev && fk.open(st);
     if (ev) HIPC(hipEventRecord(ev[0], st));
-    HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, overlap ? fk.side : st));
+    Fork fk;
+    const bool overlap = fk.open(st);
+    if (ev && !overlap) {
+        ri::set_hip_error("side stream or its events could not be created");
+        return RI_E_HIP;
+    }
+    // beside a large FP64 or FP32 exchange, gamma and J run on a capped grid so
+    // that the X kernel's workgroups are not held back behind thousands of
+    // theirs; the split-BF16 exchange is shorter than capped gamma/J, which
+    // would then set the build time, so there they keep the full grid
+    const bool capped = overlap && !is_bf16(prec) && (int64_t)n_aux * n_pairs >= ri::GJ_SIDE_MIN;
+    HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, overlap ? fk.side : st,
+                     capped ? ri::GJ_SIDE_CAP : 0));
+    if (ev) HIPC(hipEventRecord(ev[1], fk.side));
     if (overlap) HIPC(hipEventRecord(fk.join, fk.side));
-    if (ev) HIPC(hipEventRecord(ev[1], st));
     if (is_bf16(prec)) {
         HIPC(ri::x_transform_bf16(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
         if (ev) HIPC(hipEventRecord(ev[2], st));

@@ -705,27 +705,37 @@ __global__ void dpair_density_kernel(const int32_t* pairs, int64_t n_pairs, cons
     dp[q] = mu == nu ? D[(int64_t)mu * N + mu] : D[(int64_t)mu * N + nu] + D[(int64_t)nu * N + mu];
 }
 
-__global__ __launch_bounds__(256) void gamma_kernel(const double* Bc, int64_t n_pairs, const double* dp,
+// gamma_P, one block per auxiliary index at a time (grid-stride, so a small
+// grid can run beside the exchange kernels); the sum order per P does not
+// depend on the grid.
+__global__ __launch_bounds__(256) void gamma_kernel(const double* Bc, int n_aux, int64_t n_pairs, const double* dp,
                                                     double* gamma) {
-    const int P = blockIdx.x;
-    const double* row = Bc + (int64_t)P * n_pairs;
-    double s = 0.0;
-    for (int64_t q = threadIdx.x; q < n_pairs; q += 256) s += row[q] * dp[q];
     __shared__ double sh[4];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) gamma[P] = sh[0] + sh[1] + sh[2] + sh[3];
+    for (int P = blockIdx.x; P < n_aux; P += gridDim.x) {
+        const double* row = Bc + (int64_t)P * n_pairs;
+        double s = 0.0;
+        for (int64_t q = threadIdx.x; q < n_pairs; q += 256) s += row[q] * dp[q];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) gamma[P] = sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();
+    }
 }
 
-__global__ void jpair_kernel(const double* Bc, int64_t n_pairs, int n_aux, const double* gamma,
-                             int per, double* jpart) {
-    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= n_pairs) return;
-    int p0 = blockIdx.y * per, p1 = min(n_aux, p0 + per);
-    double s = 0.0;
-    for (int P = p0; P < p1; ++P) s += Bc[(int64_t)P * n_pairs + q] * gamma[P];
-    jpart[(int64_t)blockIdx.y * n_pairs + q] = s;
+// J partials over `per` auxiliary indices per split: item (pair block, split),
+// grid-stride over the pb * n_split items.
+__global__ __launch_bounds__(256) void jpair_kernel(const double* Bc, int64_t n_pairs, int n_aux, const double* gamma,
+                                                    int per, int64_t pb, int n_split, double* jpart) {
+    for (int64_t it = blockIdx.x; it < pb * n_split; it += gridDim.x) {
+        const int64_t q = (it % pb) * 256 + threadIdx.x;
+        const int z = (int)(it / pb);
+        if (q >= n_pairs) continue;
+        const int p0 = z * per, p1 = min(n_aux, p0 + per);
+        double s = 0.0;
+        for (int P = p0; P < p1; ++P) s += Bc[(int64_t)P * n_pairs + q] * gamma[P];
+        jpart[(int64_t)z * n_pairs + q] = s;
+    }
 }
 
 __global__ void jscatter_kernel(const double* jpart, int n_split, const int32_t* pairs,
@@ -873,12 +883,12 @@ int j_split_count(int n_aux) { return n_aux >= 512 ? 16 : 1; }
 
 hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux, int n_occ,
                    const double* C, double* dpair, double* gamma, double* jpart, int n_jsplit, double* J,
-                   hipStream_t st) {
+                   hipStream_t st, int cap) {
     if (n_pairs > 0) {
         dpair_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(pairs, n_pairs, C, n_occ, dpair);
         RI_TRY(hipGetLastError());
     }
-    return gamma_j_pairs(Bc, pairs, n_pairs, N, n_aux, dpair, gamma, jpart, n_jsplit, J, st);
+    return gamma_j_pairs(Bc, pairs, n_pairs, N, n_aux, dpair, gamma, jpart, n_jsplit, J, st, cap);
 }
 
 hipError_t dpair_density(const int32_t* pairs, int64_t n_pairs, const double* D, int N, double* dpair, hipStream_t st) {
@@ -888,14 +898,17 @@ hipError_t dpair_density(const int32_t* pairs, int64_t n_pairs, const double* D,
 }
 
 hipError_t gamma_j_pairs(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
-                         const double* dpair, double* gamma, double* jpart, int n_jsplit, double* J, hipStream_t st) {
+                         const double* dpair, double* gamma, double* jpart, int n_jsplit, double* J, hipStream_t st,
+                         int cap) {
     RI_TRY(fill(J, 0.0, (int64_t)N * N, st));
     if (n_pairs == 0) return fill(gamma, 0.0, n_aux, st);
     const unsigned pb = (unsigned)((n_pairs + 255) / 256);
-    gamma_kernel<<<n_aux, 256, 0, st>>>(Bc, n_pairs, dpair, gamma);
+    const int64_t items = (int64_t)pb * n_jsplit;
+    gamma_kernel<<<cap > 0 ? std::min(n_aux, cap) : n_aux, 256, 0, st>>>(Bc, n_aux, n_pairs, dpair, gamma);
     RI_TRY(hipGetLastError());
     const int per = (n_aux + n_jsplit - 1) / n_jsplit;
-    jpair_kernel<<<dim3(pb, n_jsplit), 256, 0, st>>>(Bc, n_pairs, n_aux, gamma, per, jpart);
+    jpair_kernel<<<(unsigned)(cap > 0 ? std::min<int64_t>(items, cap) : items), 256, 0, st>>>(
+        Bc, n_pairs, n_aux, gamma, per, pb, n_jsplit, jpart);
     RI_TRY(hipGetLastError());
     jscatter_kernel<<<pb, 256, 0, st>>>(jpart, n_jsplit, pairs, n_pairs, N, J);
     return hipGetLastError();

@@ -38,9 +38,12 @@ int k_split_count(int N, int n_aux, int n_occ);
 int64_t xt_rows(int n_aux, int n_occ);
 int xt_ld(int N);
 // gamma and J from the compressed FP64 tensor.
-// gamma and J from pair weights dpair (w D_mu_nu, w = 1 on the diagonal, 2 off it)
+// gamma and J from pair weights dpair (w D_mu_nu, w = 1 on the diagonal, 2 off it).
+// cap > 0 limits the gamma and J-partial launches to cap workgroups each (grid-stride;
+// same results), so they can run beside the exchange kernels on a side stream.
 hipError_t gamma_j_pairs(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
-                         const double* dpair, double* gamma, double* jpart, int n_jsplit, double* J, hipStream_t st);
+                         const double* dpair, double* gamma, double* jpart, int n_jsplit, double* J, hipStream_t st,
+                         int cap = 0);
 // pair weights of a density matrix D [N][N] (symmetrised)
 hipError_t dpair_density(const int32_t* pairs, int64_t n_pairs, const double* D, int N, double* dpair, hipStream_t st);
 // K = 1/2 sum_P B^P D B^P from B_c, slab of S auxiliaries at a time (workspace map [N*N],
@@ -49,7 +52,12 @@ hipError_t k_density(const double* Bc, const int32_t* pairs, int64_t n_pairs, in
                      int32_t* map, double* Bf, double* Y, int S, double* K, hipStream_t st);
 hipError_t gamma_j(const double* Bc, const int32_t* pairs, int64_t n_pairs, int N, int n_aux,
                    int n_occ, const double* C, double* dpair, double* gamma, double* jpart,
-                   int n_jsplit, double* J, hipStream_t st);
+                   int n_jsplit, double* J, hipStream_t st, int cap = 0);
+// Workgroups of each gamma / J launch beside an FP64 or FP32 exchange, applied when
+// B_c has at least GJ_SIDE_MIN elements (N = 1000: 2e8; there 64 workgroups made
+// gamma / J the critical path and 256 slowed X on every CU).
+constexpr int GJ_SIDE_CAP = 128;
+constexpr int64_t GJ_SIDE_MIN = 100000000;
 int j_split_count(int n_aux);
 
 }  // namespace ri

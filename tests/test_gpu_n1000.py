@@ -64,6 +64,30 @@ def test_fock_jk_sampled_rows(setup):
     assert w.min() > -1e-12 * w.max()
 
 
+def test_fock_jk_timed_schedule(setup):
+    """The phase-timed build runs the production schedule (gamma/J on the side
+    stream on a capped grid beside the exchange, which this size triggers):
+    J, K and gamma equal the untimed build's bit for bit, and the events give
+    positive gamma/J, X and SYRK spans with X ending before the build does."""
+    s, ref, pr, *_ = setup
+    import torch
+    print("case: n1000 fock_jk_timed vs fock_jk", flush=True)
+    C = dev(synth.random_coeffs(s.N, s.n_occ, seed=ref["jk_seed"]))
+    J0, K0, g0 = pr.fock_jk(C)
+    J1, K1, g1 = torch.empty_like(J0), torch.empty_like(K0), torch.empty_like(g0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for e in ev:
+        e.record()
+    torch.cuda.synchronize()
+    pr.fock_jk_timed(C, J1, K1, g1, ev)
+    torch.cuda.synchronize()
+    assert torch.equal(J0, J1) and torch.equal(K0, K1) and torch.equal(g0, g1)
+    t_j, t_x, t_k = pr.fock_phases(ev)
+    print(f"gamma/J {t_j:.3f} ms, X {t_x:.3f} ms, SYRK {t_k:.3f} ms", flush=True)
+    assert t_j > 0 and t_x > 0 and t_k > 0
+    assert ev[0].elapsed_time(ev[3]) >= t_x
+
+
 def test_energy_and_gradient(setup):
     s, ref, pr, *_ = setup
     print("case: n1000 energy", flush=True)

@@ -392,7 +392,7 @@ typedef struct {
 /* ri_batch_autotune - choose ri_batch_tuning for a batch by timing each
  * candidate shape (GEMM tile 64 / 128 on the purification square X X; SYRK
  * split 16, 8, 4, 2, 1 including its reduction, stopping at the first candidate
- * 1.5x slower than the best) with HIP events on the batch's own molecules of
+ * 1.1x slower than the best) with HIP events on the batch's own molecules of
  * each bucket, and keeping the fastest.  Takes the same
  * arguments and workspace as ri_energy_batched (sized by
  * ri_energy_batched_workspace) and leaves no result in it; C_occ and F of

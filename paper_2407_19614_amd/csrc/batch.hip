@@ -753,7 +753,8 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
             if (ms < best) { best = ms; out->gemm_tile[b] = tile; out->gemm_ms[b] = ms; }
         }
         // SYRK split: SYRK partials and their reduction for the bucket's molecules;
-        // candidates from the widest down, stopping once one is 1.5x the best
+        // candidates from the widest down (time grows as the split narrows),
+        // stopping once one is 1.1x the best
         best = 1e30f;
         for (int ks : {16, 8, 4, 2, 1}) {
             std::vector<int> ps(n_mol + 1, 0), pr(n_mol + 1, 0);
@@ -775,7 +776,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
             }, st, e0, e1, 2, &ms);
             if (rc != RI_OK) return rc;   // the host vectors stay alive until the timing synchronised
             if (ms < best) { best = ms; out->syrk_split[b] = ks; out->syrk_ms[b] = ms; }
-            if (ms > 1.5f * best) break;
+            if (ms > 1.1f * best) break;
         }
     }
     HIPR(hipStreamSynchronize(st));

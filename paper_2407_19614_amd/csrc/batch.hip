@@ -837,15 +837,41 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
     }
     rc = upload_plan(p, hp, st);
     if (rc != RI_OK) return rc;
-    // per-molecule setup: S, h, E_nn, Cholesky of S and L_S^{-1}
+    // per-molecule setup: S, h, E_nn, Cholesky of S and L_S^{-1}.  Each
+    // molecule's chain is a series of small launches on its own buffers, so
+    // the molecules are spread over SETUP_STREAMS streams forked from and
+    // joined back into `st` (a non-positive pivot is reported by atomicMin)
+    constexpr int SETUP_STREAMS = 4;
+    struct SetupStreams {
+        hipStream_t s[SETUP_STREAMS] = {};
+        hipEvent_t e[SETUP_STREAMS + 1] = {};
+        ~SetupStreams() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+            for (hipStream_t x : s)
+                if (x) (void)hipStreamDestroy(x);
+        }
+    } ss;
     int* bad = p.n_active + 1;
     HIPR(ri::fill_i32(bad, INT_MAX, 1, st));
+    HIPR(hipEventCreateWithFlags(&ss.e[SETUP_STREAMS], hipEventDisableTiming));
+    HIPR(hipEventRecord(ss.e[SETUP_STREAMS], st));
+    for (int k = 0; k < SETUP_STREAMS; ++k) {
+        HIPR(hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking));
+        HIPR(hipEventCreateWithFlags(&ss.e[k], hipEventDisableTiming));
+        HIPR(hipStreamWaitEvent(ss.s[k], ss.e[SETUP_STREAMS], 0));
+    }
     for (int i = 0; i < n_mol; ++i) {
         const MolDesc& m = hp.mols[i];
-        HIPR(ri::one_electron(&sys[i], m.S, m.H, st));
-        HIPR(ri::nuclear_repulsion(&sys[i], m.scal + SC_ENUC, st));
-        HIPR(ri::copy(m.T1, m.S, (int64_t)m.N * m.N, st));
-        HIPR(ri::cholesky_inv(m.T1, m.N, m.N, m.LinvS, m.N, m.dinvM, bad, st));
+        hipStream_t si = ss.s[i % SETUP_STREAMS];
+        HIPR(ri::one_electron(&sys[i], m.S, m.H, si));
+        HIPR(ri::nuclear_repulsion(&sys[i], m.scal + SC_ENUC, si));
+        HIPR(ri::copy(m.T1, m.S, (int64_t)m.N * m.N, si));
+        HIPR(ri::cholesky_inv(m.T1, m.N, m.N, m.LinvS, m.N, m.dinvM, bad, si));
+    }
+    for (int k = 0; k < SETUP_STREAMS; ++k) {
+        HIPR(hipEventRecord(ss.e[k], ss.s[k]));
+        HIPR(hipStreamWaitEvent(st, ss.e[k], 0));
     }
     state_init_b<<<n_mol, 256, 0, st>>>(p.d, n_mol);
     hash_cp_b<<<n_mol, 256, 0, st>>>(p.d, n_mol);

@@ -1,8 +1,11 @@
 """Write oracle reference values for the N=1000 workload (100 He-like
-centres, N=1000, N_aux=3000, n_occ=100, tau=1e-12) to n1000_oracle.json.
+centres, N=1000, N_aux=3000, n_occ=100, tau=1e-12) to n1000_oracle.json,
+and the full J and K (lower triangles, row-major, FP64) for the seeded
+occupied block to n1000_jk.npz.
 
 Calls only the CPU oracle and the seeded input generators.  Run once:
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py            (everything)
+    python tests/golden/make_golden.py --jk-only  (n1000_jk.npz only)
 """
 import json
 import os
@@ -18,6 +21,7 @@ import synth  # noqa: E402
 from oracle import ri as R, scf as S, gradient as G  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "n1000_oracle.json")
+OUT_JK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "n1000_jk.npz")
 ROWS = [0, 1, 137, 499, 500, 731, 998, 999]
 
 
@@ -32,6 +36,11 @@ def main():
     J, K = ri.JK(C)
     tjk = time.time() - t
     print(f"JK {tjk:.1f}s", flush=True)
+    lo = np.tril_indices(s.N)
+    np.savez_compressed(OUT_JK, seed=np.int64(0), J_lower=J[lo], K_lower=K[lo])
+    print("wrote", OUT_JK, flush=True)
+    if "--jk-only" in sys.argv:
+        return
     res = S.run_scf(s, ri, tol_E=1e-12, tol_e=1e-9)
     print(f"SCF E={res.E:.12f} iters={res.n_iter} conv={res.converged} {time.time()-t0:.1f}s", flush=True)
     g = G.analytic_gradient(s, res, ri)

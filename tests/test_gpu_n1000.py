@@ -1,9 +1,11 @@
 """GPU parity at the N=1000 workload (the benchmark's configuration):
 100 He-like centres, N=1000, N_aux=3000, n_occ=100, tau=1e-12.
 
-Reference values come from tests/golden/n1000_oracle.json, written by
-tests/golden/make_golden.py from the CPU oracle; sampled three-centre rows
-are recomputed by the oracle here."""
+Reference values come from tests/golden/n1000_oracle.json and the full J and
+K in tests/golden/n1000_jk.npz, both written by tests/golden/make_golden.py
+from the CPU oracle; three-centre rows on both sides of every 64-row boundary
+of the auxiliary index (and 12 seeded random rows) are recomputed by the
+oracle here."""
 import json
 import os
 
@@ -16,6 +18,7 @@ from tests.gpu_common import need_gpu, problem, to_np, dev
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "n1000_oracle.json")
+GOLD_JK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "n1000_jk.npz")
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +32,9 @@ def setup():
     import paper_2407_19614_amd as P
     pr = P.RIProblem(s)
     pr.build_3c()
-    T_rows_idx = np.random.default_rng(5).choice(s.n_aux, 12, replace=False)
+    edges = {r for k in range(64, s.n_aux, 64) for r in (k - 1, k)} | {0, s.n_aux - 1}
+    rand = set(np.random.default_rng(5).choice(s.n_aux, 12, replace=False).tolist())
+    T_rows_idx = np.array(sorted(edges | rand))
     T_rows = to_np(pr.T[T_rows_idx])
     pairs = to_np(pr.pairs)
     pr.metric_factor(P.FP64)
@@ -47,17 +52,25 @@ def test_pairs_and_sampled_three_centre(setup):
     assert np.all(err <= 1e-14 * np.abs(Tref).max() + 4e-16 * np.abs(Tref)), err.max()
 
 
-def test_fock_jk_sampled_rows(setup):
+def test_fock_jk_every_element(setup):
+    """J and K for the seeded occupied block against the oracle's, every one of
+    the N(N+1)/2 independent entries (both are symmetric) within 1e-11."""
     s, ref, pr, *_ = setup
-    print("case: n1000 fock_jk", flush=True)
+    if not os.path.exists(GOLD_JK):
+        pytest.skip("golden J/K file missing")
+    print("case: n1000 fock_jk every element", flush=True)
+    gold = np.load(GOLD_JK)
+    assert int(gold["seed"]) == ref["jk_seed"]
     C = synth.random_coeffs(s.N, s.n_occ, seed=ref["jk_seed"])
     J, K, _ = pr.fock_jk(dev(C))
     J, K = to_np(J), to_np(K)
-    rows = ref["rows"]
-    dJ = np.abs(J[rows] - np.array(ref["J_rows"])).max()
-    dK = np.abs(K[rows] - np.array(ref["K_rows"])).max()
-    print(f"max|dJ|={dJ:.2e} max|dK|={dK:.2e}", flush=True)
+    lo = np.tril_indices(s.N)
+    dJ = np.abs(J[lo] - gold["J_lower"]).max()
+    dK = np.abs(K[lo] - gold["K_lower"]).max()
+    print(f"max|dJ|={dJ:.2e} max|dK|={dK:.2e} over {lo[0].size} entries each", flush=True)
     assert dJ < 1e-11 and dK < 1e-11
+    rows = ref["rows"]
+    assert np.abs(J[rows] - np.array(ref["J_rows"])).max() < 1e-11
     assert abs(np.trace(J) - ref["J_trace"]) < 1e-8 and abs(np.trace(K) - ref["K_trace"]) < 1e-8
     assert np.abs(K - K.T).max() == 0.0 and np.abs(J - J.T).max() == 0.0
     w = np.linalg.eigvalsh(K)

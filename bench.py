@@ -172,7 +172,8 @@ def main():
         if not args.no_pipeline:
             out["gradient_max_abs_diff_vs_oracle"] = float(np.abs(g.cpu().numpy() - np.array(ref["gradient"])).max())
     out["precision"] = precision_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step,
-                                     phases.get("scf_s"))
+                                     phases.get("scf_s"), K64=K.clone(),
+                                     g64=None if args.no_pipeline else g)
     out["compressed"] = compressed_leg(s, C, None if args.quick else res, args, P, torch, np, ms_step)
     out["density_fock"] = density_leg(pr, C, torch, np)
     if args.batched or not args.no_batched:
@@ -199,22 +200,29 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None):
+def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None, K64=None, g64=None):
     """Reduced-precision exchange contractions at the same workload: Fock
-    builds/s and speedup over FP64, and each SCF energy's difference from the
-    FP64 one (skipped when res64 is None).  FP32: FP32 MFMA; BF16X3 / BF16X6:
-    two- and three-part BF16 splits with 3 and 6 products on BF16 MFMA.
-    gamma and J stay FP64.  The X roofline counts the MFMA work actually
-    issued: full square tiles of the padded size times the product count.
-    fp32_final_fp64: the FP32 SCF followed by one exchange build in FP64
-    arithmetic at the converged density (RI_FINAL_FP64), timed as a whole SCF
-    against the FP64 SCF (scf_s64)."""
+    builds/s and speedup over FP64, the exchange matrix's largest difference
+    from the FP64 one for the same orbitals, and per SCF form (skipped when
+    res64 is None) the converged energy's difference from the FP64 SCF, the
+    SCF time against the FP64 SCF (scf_s64) and the largest difference of the
+    gradient at its orbitals from the FP64 gradient (g64).  FP32: FP32 MFMA;
+    BF16X3 / BF16X6: two- and three-part BF16 splits with 3 and 6 products on
+    BF16 MFMA.  gamma and J stay FP64.  "scf_final_fp64" is the SCF followed by
+    one exchange build in FP64 arithmetic at the converged density
+    (RI_FINAL_FP64); BF16X3 is offered only in that form.  The X roofline
+    counts the MFMA work actually issued: full square tiles of the padded size
+    times the product count."""
     dev = C.device
     N, na = s.N, s.n_aux
     out = {}
-    # SCF thresholds above each form's energy noise floor (FP32 ~1e-8, BF16X3 ~1e-6 Eh)
-    for name, prec, tol in (("fp32", P.FP32, (1e-7, 1e-5)), ("bf16x3", P.BF16X3, (1e-6, 1e-4)),
-                            ("bf16x6", P.BF16X6, (1e-9, 1e-6))):
+    # (final build?, SCF thresholds): plain forms iterate to just above their
+    # energy noise floor; with the final FP64 build the density's error enters
+    # the energy to second order, so 1e-6 / 3e-5 suffices (see batched_leg)
+    forms = (("fp32", P.FP32, ((False, (1e-7, 1e-5)), (True, (1e-6, 3e-5)))),
+             ("bf16x3", P.BF16X3, ((True, (1e-6, 3e-5)),)),
+             ("bf16x6", P.BF16X6, ((False, (1e-9, 1e-6)), (True, (1e-6, 3e-5)))))
+    for name, prec, scfs in forms:
         pr = P.RIProblem(s, device=dev, prec=prec)
         pr.build_3c()
         pr.metric_factor(prec)
@@ -238,6 +246,9 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None):
                      "speedup_vs_fp64": round(ms_fp64 / (dt * 1e3), 3),
                      "phases_ms": {"gamma_J": round(float(ph[0]), 3), "X": round(float(ph[1]), 3),
                                    "K_syrk": round(float(ph[2]), 3)}}
+        if K64 is not None:
+            out[name]["max_abs_dK_vs_fp64"] = float((K - K64).abs().max())
+            out[name]["max_abs_K_fp64"] = float(K64.abs().max())
         if prec in (P.BF16X3, P.BF16X6):
             ns, nprod = (2, 3) if prec == P.BF16X3 else (3, 6)
             npad = 64 * ((N + 63) // 64)
@@ -249,25 +260,25 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None):
                                        "mfma_frac": round(fl / tx / 1e12 / PEAK_BF16_TFLOPS, 4),
                                        "b_read_GBs": round(by / tx / 1e9, 1),
                                        "hbm_frac": round(by / tx / 1e9 / PEAK_HBM_GBS, 4)}
+        if prec == P.BF16X3:
+            out[name]["scf"] = "not offered: two-part B and C_occ alone move the energy past 1e-6 Eh"
         if res64 is not None:
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False)
-            torch.cuda.synchronize()
-            t_scf = time.perf_counter() - t
-            out[name].update({"scf_E": r["E_total"], "scf_iters": r["n_iter"], "scf_converged": r["converged"],
-                              "scf_s": round(t_scf, 4), "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"])})
-            if prec == P.FP32:
-                t = time.perf_counter()
-                # the density's error enters the final energy only to second order (see batched_leg)
-                r, *_ = pr.energy(tol_E=1e-6, tol_err=3e-5, max_iter=60, raise_on_noconv=False,
-                                  final_fp64=True)
+            for fin, tol in scfs:
                 torch.cuda.synchronize()
-                t_fin = time.perf_counter() - t
-                out["fp32_final_fp64"] = {
-                    "scf_s": round(t_fin, 4), "scf_E": r["E_total"], "scf_iters": r["n_iter"],
-                    "scf_converged": r["converged"], "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"]),
-                    "scf_speedup_vs_fp64": round(scf_s64 / t_fin, 3) if scf_s64 else None}
+                t = time.perf_counter()
+                r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, raise_on_noconv=False,
+                                  final_fp64=fin)
+                torch.cuda.synchronize()
+                t_scf = time.perf_counter() - t
+                rec = {"E": r["E_total"], "iters": r["n_iter"], "converged": r["converged"],
+                       "tol_E": tol[0], "tol_err": tol[1], "scf_s": round(t_scf, 4),
+                       "abs_dE_vs_fp64": abs(r["E_total"] - res64["E_total"]),
+                       "speedup_vs_fp64_scf": round(scf_s64 / t_scf, 3) if scf_s64 else None}
+                if g64 is not None and r["converged"]:
+                    gg = pr.gradient()
+                    torch.cuda.synchronize()
+                    rec["max_abs_dgrad_vs_fp64"] = float((gg - g64).abs().max())
+                out[name]["scf_final_fp64" if fin else "scf"] = rec
         del pr, J, K, g   # blocks stay in torch's cache for the next leg (see batched_leg)
     return out
 

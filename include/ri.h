@@ -49,7 +49,9 @@ typedef enum {
     RI_E_WORKSPACE = 4,    /* ws_bytes smaller than ri_workspace_bytes()      */
     RI_E_CAPACITY = 5,     /* pair capacity too small (count is returned)     */
     RI_E_HIP = 6,          /* a HIP runtime call failed                       */
-    RI_E_UNSUPPORTED = 7   /* option not supported (e.g. unknown precision)   */
+    RI_E_UNSUPPORTED = 7,  /* option not supported (e.g. unknown precision)   */
+    RI_E_NO_PURIFY = 8     /* purification of a Fock matrix did not reach an  */
+                           /* idempotent projector within its step limit      */
 } ri_status;
 
 /* Storage precision of the packed B tensor and arithmetic of the X / K
@@ -74,18 +76,25 @@ typedef enum {
 #define RI_COMPRESSED 0x10
 #define RI_COMPRESSED_SLAB 256
 
-/* Flag OR-ed into the precision of ri_energy and of the batched SCF calls,
- * with RI_FP32 only (resident B): the SCF iterations run with FP32 exchange
- * as for RI_FP32; once converged, the exchange matrix is rebuilt once in FP64
- * arithmetic (the FP32-stored B widened exactly on load; C, X and K in FP64)
- * at the converged density, and the reported energy (E_total, E_K) is the one
- * with this K.  The energy is stationary in the density, so the density's
- * FP32 error enters it only to second order, while FP32 arithmetic in the
- * exchange shifts it to first order; what stays first order is the FP32
- * rounding of B.  n_iter, converged, last_dE, max_err and the returned Fock
- * matrix are those of the FP32 iterations; a run that does not converge
- * reports its FP32 energies.  Workspaces hold FP64 Xt and C copies (sizes
- * from the same flag).  Other calls reject it (RI_E_UNSUPPORTED). */
+/* Flag OR-ed into the precision of ri_energy (with RI_FP32, RI_BF16X3 or
+ * RI_BF16X6, resident B) and of the batched SCF calls (RI_FP32 only): the SCF
+ * iterations run with the reduced-precision exchange; once converged, the
+ * exchange matrix is rebuilt once in FP64 arithmetic at the converged density
+ * (C, X and K in FP64; B is the FP32-stored B widened exactly on load, or,
+ * for the split-BF16 forms, the FP64 fitted tensor B_c unpacked
+ * RI_COMPRESSED_SLAB auxiliaries at a time), and the reported energy
+ * (E_total, E_K) is the one with this K.  The energy is stationary in the
+ * density, so the density's error from the reduced-precision iterations enters
+ * it only to second order, while reduced-precision arithmetic in the exchange
+ * shifts it to first order; what stays first order is the rounding of the B
+ * the final build reads (FP32 for RI_FP32, none for the split-BF16 forms).
+ * n_iter, converged, last_dE, max_err and the returned Fock matrix are those
+ * of the reduced-precision iterations; a run that does not converge reports
+ * their energies.  Workspaces hold FP64 Xt and C copies (sizes from the same
+ * flag).  Other calls reject it (RI_E_UNSUPPORTED).
+ * RI_BF16X3 SCF is offered only with this flag: two bfloat16 parts hold B
+ * and C_occ to about 2^-17 relative, which alone moves the 8-centre
+ * workload's energy by more than 1e-6 Eh. */
 #define RI_FINAL_FP64 0x20
 
 /* Molecular system.  The struct lives in host memory; every array is a
@@ -222,6 +231,13 @@ typedef struct {
                            /* 3 density D [N][N] in `guess`: start from the    */
                            /*   occupied space of F(D) = h + J(D) - K(D), the  */
                            /*   Fock matrix of the density itself             */
+    int32_t max_purify;    /* step limit of each trace-correcting purification */
+                           /* (0: the default, 200 for ri_energy; for         */
+                           /* ri_energy_batched, whose launch sequence is     */
+                           /* fixed, 96 at the core-Hamiltonian start and 64  */
+                           /* in each iteration);                             */
+                           /* a purification whose |tr X - tr X^2| has not    */
+                           /* fallen below 1e-11 n_occ by then fails          */
 } ri_scf_opts;
 
 typedef struct {
@@ -256,7 +272,9 @@ int32_t ri_fock_jk_density(int32_t N, int32_t n_aux, const double* Bc, const int
  * orbitals of F C = S C eps) is obtained as the spectral projector by
  * trace-correcting purification, all on the GPU.
  *   B, prec   as for ri_fock_jk (B may be NULL with prec | RI_COMPRESSED);
- *             prec may also be RI_FP32 | RI_FINAL_FP64.
+ *             prec may also be RI_FP32, RI_BF16X3 or RI_BF16X6 with
+ *             RI_FINAL_FP64; RI_BF16X3 without it is rejected
+ *             (RI_E_UNSUPPORTED, see RI_FINAL_FP64).
  *   guess     device C_occ [N][n_occ] (guess_kind 1) or D [N][N] (guess_kind 2),
  *             else NULL.
  *   C_occ     [N][n_occ] out: orthonormal (C^T S C = 1) occupied orbitals
@@ -264,7 +282,10 @@ int32_t ri_fock_jk_density(int32_t N, int32_t n_aux, const double* Bc, const int
  *   F_out     [N][N] out: Fock matrix built from C_occ.
  *   D_out     [N][N] out (may be NULL): D = 2 C_occ C_occ^T.
  *   res       (host, out).
- * Returns RI_E_NO_CONV (with `res` filled) when max_iter is reached.
+ * Returns RI_E_NO_CONV (with `res` filled) when max_iter is reached, and
+ * RI_E_NO_PURIFY (with `res` filled up to the last completed iteration,
+ * converged = 0) when a purification fails (see max_purify), e.g. for a Fock
+ * matrix with no gap between its n_occ-th and next eigenvalue.
  * Synchronises the stream once per iteration. */
 int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const double* Bc,
                   const int32_t* pairs, int64_t n_pairs, const ri_scf_opts* opts,
@@ -280,7 +301,14 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec, const doubl
  *   W = (1/2) D F D (= 2 C eps C^T at convergence),
  *   g = sum D h' - sum W S' + sum Y (mu nu|P)' - 1/2 sum Z (P|Q)' + E_nn'.
  *   B, prec, Bc, pairs, Linv as returned by ri_metric_factor (B may be NULL
- *            with prec | RI_COMPRESSED; prec RI_FP64 or RI_FP32).
+ *            with prec | RI_COMPRESSED).  With RI_FP64 or RI_FP32 the
+ *            half-transform X^P = B^P C for B_ij reads B in that precision.
+ *            With RI_BF16X3 or RI_BF16X6, B is not read (it may be NULL):
+ *            B_ij, Xi and every sum are formed in FP64 from Bc, unpacked
+ *            RI_COMPRESSED_SLAB auxiliaries at a time as for RI_COMPRESSED,
+ *            since B_ij and Xi enter the gradient linearly and the split
+ *            parts carry B only to 2^-17 (or 2^-25); the result is the FP64
+ *            gradient at the orbitals the split-BF16 SCF converged to.
  *   C_occ, F  converged orbitals and Fock matrix from ri_energy.
  *   grad     [n_centres][3] out, Eh/bohr, including nuclear repulsion.
  * Asynchronous. */
@@ -410,7 +438,10 @@ int32_t ri_batch_autotune(int32_t n_mol, const ri_system* sys, const ri_batch_mo
  *              NULL for the defaults; RI_E_ARG if a value is out of range.
  *   prec       RI_FP64, RI_FP32, or RI_FP32 | RI_FINAL_FP64.
  *   res        host [n_mol] (out).
- * Returns RI_E_NO_CONV if any molecule did not converge (all results filled).
+ * A molecule whose purification fails (opts->max_purify) stops iterating and
+ * reports converged = 0.  Returns RI_E_NO_PURIFY if that happened to any
+ * molecule, else RI_E_NO_CONV if any molecule did not converge (all results
+ * filled).
  * Synchronises the stream once per iteration. */
 int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mol* mol, int32_t prec,
                           const ri_scf_opts* opts, int32_t use_graph, const ri_batch_tuning* tuning,

@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(HERE, "libri.so")
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 COMPRESSED = 0x10          # flag: B not resident, decompressed per auxiliary slab each call
 COMPRESSED_SLAB = 256
-FINAL_FP64 = 0x20          # batched flag (with FP32): one FP64 exchange build after the FP32 SCF
+FINAL_FP64 = 0x20          # SCF flag (FP32, BF16X3, BF16X6): one FP64 exchange build after the SCF
 OP_BUILD_3C, OP_METRIC, OP_FOCK, OP_ENERGY, OP_GRADIENT = range(5)
 OP_FOCK_DENSITY = 6
 STATUS = {0: "RI_OK", 1: "RI_E_ARG", 2: "RI_E_NOT_PD", 3: "RI_E_NO_CONV", 4: "RI_E_WORKSPACE",
-          5: "RI_E_CAPACITY", 6: "RI_E_HIP", 7: "RI_E_UNSUPPORTED"}
+          5: "RI_E_CAPACITY", 6: "RI_E_HIP", 7: "RI_E_UNSUPPORTED", 8: "RI_E_NO_PURIFY"}
 
 
 class RIError(RuntimeError):
@@ -39,7 +39,7 @@ class RISystem(ctypes.Structure):
 
 class SCFOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_int32), ("diis_n", c_int32), ("tol_E", c_double), ("tol_err", c_double),
-                ("guess_kind", c_int32)]
+                ("guess_kind", c_int32), ("max_purify", c_int32)]
 
 
 class SCFResult(ctypes.Structure):
@@ -342,17 +342,17 @@ class RIProblem:
         return J, K
 
     def energy(self, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, guess=None, raise_on_noconv=True,
-               guess_density=None, density_fock=False, final_fp64=False):
+               guess_density=None, density_fock=False, final_fp64=False, max_purify=0):
         """SCF.  guess: C_occ start; guess_density: density start, through its
         natural orbitals, or (density_fock=True) through the occupied space of
         its own Fock matrix (J and K built from the density).  final_fp64
-        (FP32 problems): one FP64 exchange build at the converged density
-        gives the reported energy (RI_FINAL_FP64)."""
+        (FP32 and split-BF16 problems): one FP64 exchange build at the
+        converged density gives the reported energy (RI_FINAL_FP64)."""
         torch = self.torch
         kind = 0 if guess is None else 1
         if guess_density is not None:
             kind, guess = (3 if density_fock else 2), guess_density
-        opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, kind)
+        opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, kind, max_purify)
         C = torch.empty((self.N, self.n_occ), dtype=torch.float64, device=self.device)
         F = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
         D = torch.empty_like(F)
@@ -368,6 +368,16 @@ class RIProblem:
         _check(code, "ri_energy")
         self.C_occ, self.F, self.D = C, F, D
         return res.as_dict(), C, F, D
+
+    def record_stream(self, stream):
+        """Marks every device tensor of this problem as used on `stream`, so the
+        caching allocator does not reuse its memory on the stream it was
+        allocated on while work queued on `stream` may still read it."""
+        for name in ("xyz", "Z", "fn_centre", "fn_exp", "aux_centre", "aux_exp", "pairs", "T", "L", "Linv", "B",
+                     "_ws"):
+            t = getattr(self, name, None)
+            if t is not None:
+                t.record_stream(stream)
 
     def gradient(self, C_occ=None, F=None):
         torch = self.torch
@@ -506,6 +516,9 @@ def prepare_batch(systems, prec=FP64, workers=4, device="cuda"):
         t.join()
     if errors:
         raise errors[0]
+    cur = torch.cuda.current_stream(dev)
+    for pr in out:
+        pr.record_stream(cur)   # allocated on a worker stream, used on the caller's
     return out
 
 
@@ -526,7 +539,7 @@ def batch_autotune(problems, prec=FP64):
 
 
 def energy_batched(problems, prec=FP64, max_iter=100, diis_n=6, tol_E=1e-10, tol_err=1e-8, use_graph=True,
-                   want_fock=False, raise_on_noconv=True, tuning=None):
+                   want_fock=False, raise_on_noconv=True, tuning=None, max_purify=0):
     """Lockstep SCF for a list of RIProblem objects (each after build_3c and
     metric_factor in precision `prec`), with launch shapes from `tuning`
     (a BatchTuning, or None for the defaults).  Returns (results, C_occ
@@ -535,12 +548,12 @@ def energy_batched(problems, prec=FP64, max_iter=100, diis_n=6, tol_E=1e-10, tol
     n, dev, sysarr, mols, Cs, Fs = _batch_args(problems, want_fock)
     ws, nb = _batch_ws(n, sysarr, mols, prec, dev)
     res = (SCFResult * n)()
-    opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, 0)
+    opts = SCFOpts(max_iter, diis_n, tol_E, tol_err, 0, max_purify)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     code = lib().ri_energy_batched(n, ctypes.byref(sysarr), ctypes.byref(mols), prec, ctypes.byref(opts),
                                    1 if use_graph else 0, None if tuning is None else ctypes.byref(tuning),
                                    ctypes.byref(res), _ptr(ws), nb, stream)
-    if code not in (0, 3) or (code == 3 and raise_on_noconv):
+    if code not in (0, 3, 8) or (code in (3, 8) and raise_on_noconv):
         _check(code, "ri_energy_batched")
     del ws
     return [r.as_dict() for r in res], Cs, Fs

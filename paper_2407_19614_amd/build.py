@@ -51,6 +51,42 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# The library with its host code under AddressSanitizer and UBSan, linked with
+# tests/host_sanitize_driver.cpp into one executable that checks the host
+# layer on a machine without a GPU (a kernel launch there fails with a HIP
+# error, which the library reports as RI_E_HIP).  Each -fsanitize option
+# applies to the host pass only (-Xarch_host); the device code is the
+# ordinary build's.
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_DIR = os.path.join(OBJDIR, "host_sanitize")
+DRIVER = os.path.join(os.path.dirname(HERE), "tests", "host_sanitize_driver.cpp")
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-fno-omit-frame-pointer", *SAN,
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+
+    def comp(src):
+        obj = os.path.join(SAN_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+        r = subprocess.run([HIPCC, *flags, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc (host, sanitized) failed for {src}:\n{r.stderr}")
+        return obj
+
+    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))] + [DRIVER]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(comp, srcs))
+    exe = os.path.join(SAN_DIR, "host_sanitize_driver")
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", *SAN, *objs, "-o", exe], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (host, sanitized) failed:\n{r.stderr}")
+    if verbose:
+        print("built", exe)
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -40,7 +40,8 @@ struct Arena {
         off += b;
         return dry ? nullptr : (T*)(base + o);
     }
-    bool ok() const { return dry || off <= cap; }
+    // the size ri_workspace_bytes reports is off + 256
+    bool ok() const { return dry || off + 256 <= cap; }
 };
 
 bool valid_sys(const ri_system* s) {
@@ -56,12 +57,13 @@ struct Prec {
     int base;
     bool comp, fin, ok;
 };
-// fin (RI_FINAL_FP64) is accepted where allow_fin is set, with resident FP32 B only
+// fin (RI_FINAL_FP64) is accepted where allow_fin is set, with resident FP32
+// or split-BF16 B only
 Prec split_prec(int32_t p, bool allow_fin = false) {
     Prec r{p & ~(RI_COMPRESSED | RI_FINAL_FP64), (p & RI_COMPRESSED) != 0, (p & RI_FINAL_FP64) != 0, true};
     if (r.base < 0 || r.base > 3) r.ok = false;
     if (r.comp && r.base != RI_FP64 && r.base != RI_FP32) r.ok = false;
-    if (r.fin && (!allow_fin || r.base != RI_FP32 || r.comp)) r.ok = false;
+    if (r.fin && (!allow_fin || r.base == RI_FP64 || r.comp)) r.ok = false;
     return r;
 }
 int comp_slab(int n_aux) { return std::min(RI_COMPRESSED_SLAB, (n_aux + 1) / 2 * 2); }
@@ -175,10 +177,11 @@ struct EnergyWS {
     double *Bmat, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal, *red;
     int* bad;
     FockWS fock;
+    FockWS fin;   // final FP64 exchange build of the split-BF16 forms: FP64 Xt and slabs of B_c
     DensityWS dens;
 };
 EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int prec, int diis_n,
-                      bool comp = false) {
+                      bool comp = false, bool fin_slab = false) {
     EnergyWS w;
     const int64_t n2 = (int64_t)N * N;
     double** mats[] = {&w.S, &w.H, &w.Ls, &w.LinvS, &w.J, &w.K, &w.F, &w.D, &w.T1, &w.T2, &w.E, &w.Fx, &w.X, &w.X2};
@@ -201,9 +204,17 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     w.red = a.take<double>(ri::red_elems(N));   // reduction partials
     w.bad = a.take<int>(2);
     w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, comp);
+    w.fin = fin_slab ? carve_fock(a, N, n_aux, n_occ, n_pairs, RI_FP64, true) : FockWS{};
     w.dens = carve_density(a, N, n_aux, n_pairs);
     return w;
 }
+
+// Exchange workspace layout of an SCF in precision p: with the final FP64
+// build, FP32 iterations use the FP64 layout (the FP32-stored B is widened on
+// load); split-BF16 iterations keep their own layout and the final build gets
+// FP64 slabs of B_c.
+int energy_layout(const Prec& p) { return p.fin && !is_bf16(p.base) ? RI_FP64 : p.base; }
+bool energy_fin_slab(const Prec& p) { return p.fin && is_bf16(p.base); }
 
 struct GradWS { double *D, *W, *T1, *dpair, *gamma, *c, *Bij, *Xi, *Zx, *part, *Cp, *WY; void* Xt; float* Xt32; SlabWS sw; };
 GradWS carve_grad(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, int n_centres, int prec,
@@ -244,11 +255,16 @@ hipStream_t side_stream() {
 }
 
 // Fork/join of the caller's stream with the side stream: events are made per
-// call, so concurrent callers never wait on each other's records.
+// call, so concurrent callers never wait on each other's records.  The
+// caller's stream waits for the side stream on every exit: close() on the
+// normal path, the destructor after an early error return, so no work of
+// the call is left running on the side stream once the call has returned.
 struct Fork {
-    hipStream_t side = nullptr;
+    hipStream_t st = nullptr, side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    bool open(hipStream_t st) {
+    bool closed = false;
+    bool open(hipStream_t s) {
+        st = s;
         side = side_stream();
         if (!side || hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
@@ -258,7 +274,15 @@ struct Fork {
         }
         return true;
     }
+    // st waits for everything enqueued on the side stream so far
+    hipError_t close() {
+        closed = true;
+        if (!side) return hipSuccess;
+        hipError_t e = hipEventRecord(join, side);
+        return e == hipSuccess ? hipStreamWaitEvent(st, join, 0) : e;
+    }
     ~Fork() {
+        if (side && !closed) (void)close();
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
     }
@@ -290,7 +314,6 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
     HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, overlap ? fk.side : st,
                      capped ? ri::GJ_SIDE_CAP : 0));
     if (ev) HIPC(hipEventRecord(ev[1], fk.side));
-    if (overlap) HIPC(hipEventRecord(fk.join, fk.side));
     if (is_bf16(prec)) {
         HIPC(ri::x_transform_bf16(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
         if (ev) HIPC(hipEventRecord(ev[2], st));
@@ -300,7 +323,7 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
         if (ev) HIPC(hipEventRecord(ev[2], st));
         HIPC(ri::k_syrk(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
     }
-    if (overlap) HIPC(hipStreamWaitEvent(st, fk.join, 0));
+    HIPC(fk.close());
     if (ev) HIPC(hipEventRecord(ev[3], st));
     return RI_OK;
 }
@@ -310,7 +333,7 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
 // by L_S^{-1}, then an orthonormal basis of its range by two passes of
 // projection and Cholesky QR, mapped back by L_S^{-T}.
 int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool have_prev, double* C_out,
-                       hipStream_t st) {
+                       int max_it, hipStream_t st) {
     const int64_t n2 = (int64_t)N * N;
     HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.LinvS, N, 0, Fx, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
     HIPC(ri::gemm_f64(false, true, N, N, N, 1.0, w.T1, N, 0, w.LinvS, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
@@ -318,7 +341,6 @@ int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool hav
     HIPC(ri::tc2_init(w.T2, w.scal + 16, N, w.X, st));
     double idem = 1.0;
     int it = 0, extra = -1;
-    const int max_it = 200;
     // When the 64 x 64 tiles of X^2 are fewer than two per compute unit, the
     // square is formed as two K-halves in one batched launch into T1 and T2
     // (free here) and summed, so twice as many workgroups share the work.
@@ -347,7 +369,9 @@ int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool hav
             if (std::fabs(idem) < 1e-11 * std::max(1, n_occ)) extra = 3;
         }
     }
-    if (extra != 0) return RI_E_NO_CONV;
+    // a projector that reached the idempotency threshold is used even when the
+    // step limit cut its last extra steps short
+    if (extra < 0) return RI_E_NO_PURIFY;
     if (!have_prev) HIPC(ri::hash_matrix(w.Cp, (int64_t)N * n_occ, 0x5eed1234u, st));
     for (int pass = 0; pass < 2; ++pass) {
         HIPC(ri::gemm_f64(false, false, N, n_occ, N, 1.0, w.X, N, 0, w.Cp, n_occ, 0, 0.0, w.Y, n_occ, 0, 1, 0, 0, st));
@@ -384,6 +408,7 @@ const char* ri_status_str(int32_t s) {
         case RI_E_CAPACITY: return "pair capacity too small";
         case RI_E_HIP: return "HIP runtime error";
         case RI_E_UNSUPPORTED: return "unsupported option";
+        case RI_E_NO_PURIFY: return "purification did not reach an idempotent projector";
         default: return "unknown status";
     }
 }
@@ -406,8 +431,12 @@ size_t ri_workspace_bytes(int32_t op, int32_t N, int32_t n_aux, int32_t n_occ, i
         case RI_OP_BUILD_3C: carve_build(a, N); break;
         case RI_OP_METRIC: carve_metric(a, N, n_aux, n_pairs); break;
         case RI_OP_FOCK: carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp); break;
-        case RI_OP_ENERGY: carve_energy(a, N, n_aux, n_occ, n_pairs, pp.fin ? RI_FP64 : prec, 8, pp.comp); break;
-        case RI_OP_GRADIENT: carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, prec, pp.comp); break;
+        case RI_OP_ENERGY:
+            carve_energy(a, N, n_aux, n_occ, n_pairs, energy_layout(pp), 8, pp.comp, energy_fin_slab(pp));
+            break;
+        case RI_OP_GRADIENT:
+            carve_grad(a, N, n_aux, n_occ, n_pairs, 2048, is_bf16(prec) ? RI_FP64 : prec, pp.comp || is_bf16(prec));
+            break;
         case RI_OP_FOCK_DENSITY: carve_density(a, N, n_aux, n_pairs); break;
         case RI_OP_MLP: {
             size_t off = 0;
@@ -539,13 +568,20 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
     if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0))
         return RI_E_ARG;
     if (opts->guess_kind != 0 && !guess) return RI_E_ARG;
+    if (opts->max_purify < 0) return RI_E_ARG;
+    const int npur = opts->max_purify > 0 ? opts->max_purify : 200;
     if (opts->guess_kind < 0 || opts->guess_kind > 3) return RI_E_UNSUPPORTED;
     if (!pp.ok || (is_bf16(prec) && sys->n_occ > 128)) return RI_E_UNSUPPORTED;
+    // Two bfloat16 parts hold B and C_occ to about 2^-17: at the 8-centre
+    // workload that rounding alone moves the energy by 1.6e-6 Eh (B) and
+    // 8e-6 Eh (C_occ), and the SYRK's dropped lo x lo product is a Gram matrix,
+    // so its error does not cancel.  BF16X3 iterations are therefore offered
+    // only with the final FP64 exchange build, which removes them to first order.
+    if (prec == RI_BF16X3 && !pp.fin) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, dn = opts->diis_n;
     const int64_t n2 = (int64_t)N * N;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    // with the final FP64 build the exchange workspace holds FP64 Xt and C copies
-    EnergyWS w = carve_energy(a, N, na, no, n_pairs, pp.fin ? RI_FP64 : prec, 8, pp.comp);
+    EnergyWS w = carve_energy(a, N, na, no, n_pairs, energy_layout(pp), 8, pp.comp, energy_fin_slab(pp));
     if (!a.ok()) return RI_E_WORKSPACE;
     std::memset(res, 0, sizeof(*res));
 
@@ -561,19 +597,19 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
 
     int32_t rc;
     if (opts->guess_kind == 0) {
-        rc = occupied_space(w.H, N, no, w, false, C_occ, st);
+        rc = occupied_space(w.H, N, no, w, false, C_occ, npur, st);
         if (rc) return rc;
     } else if (opts->guess_kind == 3) {
         // Fock matrix of the density itself (J and K from D), then its occupied space
         HIPC(jk_density(Bc, pairs, n_pairs, N, na, guess, w.J, w.K, nullptr, w.dens, st));
         HIPC(ri::fock_assemble(w.H, w.J, w.K, w.F, n2, st));
-        rc = occupied_space(w.F, N, no, w, false, C_occ, st);
+        rc = occupied_space(w.F, N, no, w, false, C_occ, npur, st);
         if (rc) return rc;
     } else if (opts->guess_kind == 2) {
         // occupied space of the density: lowest solutions of (-S D S) v = l S v
         HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.S, N, 0, guess, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
         HIPC(ri::gemm_f64(false, false, N, N, N, -1.0, w.T1, N, 0, w.S, N, 0, 0.0, w.Fx, N, 0, 1, 0, 0, st));
-        rc = occupied_space(w.Fx, N, no, w, false, C_occ, st);
+        rc = occupied_space(w.Fx, N, no, w, false, C_occ, npur, st);
         if (rc) return rc;
     } else {
         HIPC(ri::copy(C_occ, guess, (int64_t)N * no, st));
@@ -644,14 +680,21 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
             HIPC(ri::diis_combine(fs, w.coef, m, w.Fx, n2, st));
             Fx = w.Fx;
         }
-        rc = occupied_space(Fx, N, no, w, true, C_occ, st);
+        rc = occupied_space(Fx, N, no, w, true, C_occ, npur, st);
         if (rc) return rc;
     }
     if (pp.fin && converged) {
-        // one exchange build in FP64 arithmetic (the FP32-stored B widened on
-        // load) at the converged density; the energy from the same D, h and J
-        HIPC(ri::x_transform(B, ri::X_F64_B32, N, na, no, C_occ, w.fock.Cp, w.fock.Xt, st));
-        HIPC(ri::k_syrk(w.fock.Xt, RI_FP64, N, na, no, w.fock.part, w.fock.ks, w.K, st));
+        // one exchange build in FP64 arithmetic at the converged density: from
+        // the FP32-stored B widened on load, or (split-BF16 forms, whose parts
+        // hold B only to 2^-17 or 2^-25) from the FP64 B_c unpacked slab by
+        // slab; the energy from the same D, h and J
+        if (is_bf16(prec)) {
+            HIPC(x_any(nullptr, RI_FP64, N, na, no, C_occ, w.fin.Cp, w.fin.Xt, Bc, pairs, n_pairs, w.fin.sw, st));
+            HIPC(ri::k_syrk(w.fin.Xt, RI_FP64, N, na, no, w.fin.part, w.fin.ks, w.K, st));
+        } else {
+            HIPC(ri::x_transform(B, ri::X_F64_B32, N, na, no, C_occ, w.fock.Cp, w.fock.Xt, st));
+            HIPC(ri::k_syrk(w.fock.Xt, RI_FP64, N, na, no, w.fock.part, w.fock.ks, w.K, st));
+        }
         HIPC(ri::energy_terms(w.D, w.H, w.J, w.K, n2, w.scal + 8, w.scal, w.red, st));
         HIPC(hipMemcpyAsync(host, w.scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPC(hipStreamSynchronize(st));
@@ -671,18 +714,22 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
                     const double* Bc, const double* Linv, const double* C, const double* F, double* grad, void* ws,
                     size_t ws_bytes, hipStream_t st) {
     const Prec pp = split_prec(prec_arg);
-    const int prec = pp.base;
-    if (!valid_sys(sys) || (!B && !pp.comp) || !Linv || !C || !F || !grad || !ws || n_pairs < 0 ||
+    // The split-BF16 forms form B_ij^P = C^T B^P C in FP64 arithmetic from B_c,
+    // slab by slab as the compressed form does: Xi and Z enter the gradient
+    // linearly, and their parts would carry B's 2^-17 (or 2^-25) rounding.
+    const bool slabs = pp.comp || is_bf16(pp.base);
+    const int prec = is_bf16(pp.base) ? RI_FP64 : pp.base;
+    if (!valid_sys(sys) || (!B && !slabs) || !Linv || !C || !F || !grad || !ws || n_pairs < 0 ||
         (n_pairs > 0 && (!Bc || !pairs)))
         return RI_E_ARG;
-    if (!pp.ok || (prec != RI_FP64 && prec != RI_FP32)) return RI_E_UNSUPPORTED;
-    if (pp.comp) B = nullptr;
+    if (!pp.ok) return RI_E_UNSUPPORTED;
+    if (slabs) B = nullptr;
     if (sys->n_centres > 2048) return RI_E_UNSUPPORTED;
     const int N = sys->n_fn, na = sys->n_aux, no = sys->n_occ, nc = sys->n_centres;
     const int Npad = ri::xt_ld(N);
     const int64_t o2 = (int64_t)no * no;
     Arena a{(char*)ws, ws_bytes, 0, false};
-    GradWS w = carve_grad(a, N, na, no, n_pairs, 2048, prec, pp.comp);
+    GradWS w = carve_grad(a, N, na, no, n_pairs, 2048, prec, slabs);
     if (!a.ok()) return RI_E_WORKSPACE;
     // D = 2 C C^T, W = 1/2 D F D
     HIPC(ri::gemm_f64(false, true, N, N, no, 2.0, C, no, 0, C, no, 0, 0.0, w.D, N, 0, 1, 0, 0, st));
@@ -732,7 +779,7 @@ int32_t ri_mlp_forward(const ri_mlp* net, const float* feat, int64_t n, float* y
     if (prec != RI_MLP_FP32 && prec != RI_MLP_BF16) return RI_E_UNSUPPORTED;
     size_t off = 0;
     ri::carve_mlp(nullptr, 0, off, n);
-    if (off > ws_bytes) return RI_E_WORKSPACE;
+    if (off + 256 > ws_bytes) return RI_E_WORKSPACE;
     off = 0;
     ri::MlpWS w = ri::carve_mlp((char*)ws, ws_bytes, off, n);
     HIPC(ri::mlp_forward(net, feat, n, y, prec, w, st));
@@ -746,7 +793,7 @@ int32_t ri_mlp_train_step(const ri_mlp* net, float* m, float* v, int32_t step, f
         return RI_E_ARG;
     size_t off = 0;
     ri::carve_mlp(nullptr, 0, off, n);
-    if (off > ws_bytes) return RI_E_WORKSPACE;
+    if (off + 256 > ws_bytes) return RI_E_WORKSPACE;
     off = 0;
     ri::MlpWS w = ri::carve_mlp((char*)ws, ws_bytes, off, n);
     HIPC(ri::mlp_train_step(net, m, v, step, lr, feat, target, n, loss, w, st));

@@ -22,6 +22,9 @@ constexpr int ST_ACTIVE = 0, ST_IT = 1, ST_PUSH = 2, ST_CONV = 3, ST_NSLOT = 4, 
 // purification: ST_TC2 1 while squares are still formed, ST_TC2U 1 if this
 // step's update runs, ST_TC2X the steps left once idempotent (-1 before)
 constexpr int ST_TC2 = 14, ST_TC2X = 15, ST_TC2U = 16, ST_N = 32;
+// ST_NOPUR 1 once a purification ended its launch sequence without reaching the
+// idempotency threshold: the molecule stops iterating and is reported unconverged
+constexpr int ST_NOPUR = 17;
 constexpr int SC_E = 0, SC_ERR = 5, SC_EOLD = 6, SC_ENUC = 8, SC_BOUNDS = 16, SC_TR = 20;
 
 #define DECODE()                                         \
@@ -98,14 +101,18 @@ __global__ void tc2_init_b(const MolDesc* d, const int* prefix, int n_mol) {
     m.X[e] = ((r == c ? hi : 0.0) - m.T2[e]) / (hi - lo);
 }
 
+// Grid-stride over the molecule's N^2 elements with the blocks its prefix
+// table gives it (about N^2 / 2048), so that a step whose molecules have all
+// finished costs few empty blocks.
 __global__ void tc2_update_b(const MolDesc* d, const int* prefix, int n_mol) {
     DECODE();
     if (!m.state[ST_TC2U]) return;
-    int64_t e = (int64_t)loc * 256 + threadIdx.x;
-    if (e >= (int64_t)m.N * m.N) return;
+    const int nblk = prefix[mol + 1] - prefix[mol];
     const double t1 = m.scal[SC_TR], t2 = m.scal[SC_TR + 1];
     const bool sq = fabs(t2 - m.n_occ) < fabs(2.0 * t1 - t2 - m.n_occ);
-    m.X[e] = sq ? m.X2[e] : 2.0 * m.X[e] - m.X2[e];
+    const int64_t n = (int64_t)m.N * m.N;
+    for (int64_t e = (int64_t)loc * 256 + threadIdx.x; e < n; e += (int64_t)nblk * 256)
+        m.X[e] = sq ? m.X2[e] : 2.0 * m.X[e] - m.X2[e];
 }
 
 // -------------------------------------------------- one block per molecule
@@ -340,6 +347,18 @@ __global__ __launch_bounds__(256) void traces_b(const MolDesc* d, int n_mol) {
     }
 }
 
+// After the purification's fixed launch sequence: a molecule still active
+// whose |tr X - tr X^2| never fell below the threshold has no usable
+// projector; it is flagged and leaves the batch (later launches skip it).  One
+// that reached the threshold but had extra steps left keeps its projector.
+__global__ void tc2_check_b(const MolDesc* d, int n_mol) {
+    const MolDesc& m = d[blockIdx.x];
+    if (threadIdx.x != 0 || !m.state[ST_ACTIVE] || m.state[ST_TC2X] >= 0) return;
+    m.state[ST_NOPUR] = 1;
+    m.state[ST_ACTIVE] = 0;
+    m.state[ST_TC2] = 0;
+}
+
 // Cholesky of the n_occ x n_occ (<= 64) Gram matrix Mo and its inverse into
 // LinvM (64 x 64, row stride 64).
 __global__ __launch_bounds__(256) void small_chol_b(const MolDesc* d, int n_mol) {
@@ -370,10 +389,17 @@ struct Table {
 };
 
 struct Plan {
-    int n_mol = 0, prec = 0, tc2_iters = 48;
+    // purification steps of each launch sequence: tc2_iters inside the
+    // captured iteration, tc2_start for the core-Hamiltonian start.  Steps
+    // grow with log(spectral width / gap): converged Fock matrices of the
+    // 10-60-centre molecules need 27-30, their core Hamiltonians 34-67, and a
+    // DIIS-extrapolated Fock matrix of an early iteration can have a smaller
+    // gap still.  Molecules whose purification has finished skip the
+    // remaining steps of the sequence at once.
+    int n_mol = 0, prec = 0, tc2_iters = 64, tc2_start = 96;
     bool fin = false;                                     // FP64 exchange once after the FP32 SCF
     MolDesc* d = nullptr;
-    Table n2, rows, pairs, aux, syrk, tail, cq, x[33];   // x[xs], xs = 4 * tiles + quads
+    Table n2, n2s, rows, pairs, aux, syrk, tail, cq, x[33];   // x[xs], xs = 4 * tiles + quads
     Table x64[33];                                        // FP64 shapes of the final exchange (fin)
     // members on 64 x 64 tiles in t, on 128 x 128 tiles in t128
     struct G { ri::GemmDesc* d = nullptr; Table t, t128; bool ta = false, tb = false; };
@@ -387,7 +413,7 @@ struct Plan {
         if (_e != hipSuccess) return _e;       \
     } while (0)
 
-hipError_t occupied_space_b(const Plan& p, hipStream_t st) {
+hipError_t occupied_space_b(const Plan& p, int tc2_steps, hipStream_t st) {
     const MolDesc* d = p.d;
     const int nm = p.n_mol;
     auto gg = [&](const Plan::G& g) {
@@ -398,11 +424,12 @@ hipError_t occupied_space_b(const Plan& p, hipStream_t st) {
     HC(gg(p.g_t2));
     gersh_b<<<nm, 256, 0, st>>>(d, nm);
     tc2_init_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
-    for (int k = 0; k < p.tc2_iters; ++k) {
+    for (int k = 0; k < tc2_steps; ++k) {
         HC(gg(p.g_x2));
         traces_b<<<nm, 256, 0, st>>>(d, nm);
-        tc2_update_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
+        tc2_update_b<<<p.n2s.total, 256, 0, st>>>(d, p.n2s.prefix, nm);
     }
+    tc2_check_b<<<nm, 64, 0, st>>>(d, nm);
     for (int pass = 0; pass < 2; ++pass) {
         HC(gg(p.g_y));
         HC(gg(p.g_mo));
@@ -441,7 +468,7 @@ hipError_t iteration_b(const Plan& p, int max_iter, hipStream_t st) {
     diis_dots_b<<<dim3(nm, 8), 256, 0, st>>>(d, nm);
     diis_solve_b<<<nm, 64, 0, st>>>(d, nm);
     diis_combine_b<<<p.n2.total, 256, 0, st>>>(d, p.n2.prefix, nm);
-    HC(occupied_space_b(p, st));
+    HC(occupied_space_b(p, p.tc2_iters, st));
     count_active_b<<<1, 64, 0, st>>>(d, nm, p.n_active);
     return hipGetLastError();
 }
@@ -591,6 +618,8 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
     std::vector<int> c(n_mol);
     for (int i = 0; i < n_mol; ++i) c[i] = (int)(((int64_t)hp.mols[i].N * hp.mols[i].N + 255) / 256);
     mk(c, p.n2);
+    for (int i = 0; i < n_mol; ++i) c[i] = (int)(((int64_t)hp.mols[i].N * hp.mols[i].N + 2047) / 2048);
+    mk(c, p.n2s);
     for (int i = 0; i < n_mol; ++i) c[i] = hp.mols[i].N;
     mk(c, p.rows);
     for (int i = 0; i < n_mol; ++i) c[i] = (int)((hp.mols[i].n_pairs + 255) / 256);
@@ -626,7 +655,8 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         std::vector<int> c64(n_mol), c128(n_mol);
         for (int i = 0; i < n_mol; ++i) {
             fill(hp.mols[i], v[i]);
-            v[i].active = hp.mols[i].state + act;   // runs while this flag is set
+            // runs while this flag is set (no pointer in the sizing pass, whose carver has no base)
+            v[i].active = hp.mols[i].state ? hp.mols[i].state + act : nullptr;
             const bool big = tunable && hp.tile[i] == 128;
             c64[i] = big ? 0 : ((v[i].M + 63) / 64) * ((v[i].N + 63) / 64);
             c128[i] = big ? ((v[i].M + 127) / 128) * ((v[i].N + 127) / 128) : 0;
@@ -713,7 +743,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
     HostPlan hp;
     int32_t rc = batch_layout(n_mol, sys, mol, prec, 8, nullptr, cv, p, hp);
     if (rc != RI_OK) return rc;
-    if (cv.off > ws_bytes) return RI_E_WORKSPACE;
+    if (cv.off + 256 > ws_bytes) return RI_E_WORKSPACE;
     rc = upload_plan(p, hp, st);
     if (rc != RI_OK) return rc;
     // every molecule active; operands zeroed (the timings do not depend on values)
@@ -822,19 +852,20 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
     int32_t rc = check_batch(n_mol, sys, mol, prec);
     if (rc != RI_OK) return rc;
     if (opts->diis_n < 1 || opts->diis_n > 8 || opts->max_iter < 1 || !(opts->tol_E > 0) || !(opts->tol_err > 0) ||
-        opts->guess_kind != 0)
+        opts->guess_kind != 0 || opts->max_purify < 0)
         return RI_E_ARG;
     Carver cv{(char*)ws, ws_bytes};
     Plan p;
     HostPlan hp;
     rc = batch_layout(n_mol, sys, mol, prec, 8, tuning, cv, p, hp);
     if (rc != RI_OK) return rc;
-    if (cv.off > ws_bytes) return RI_E_WORKSPACE;
+    if (cv.off + 256 > ws_bytes) return RI_E_WORKSPACE;
     for (auto& m : hp.mols) {
         m.tol_E = opts->tol_E;
         m.tol_err = opts->tol_err;
         m.diis_n = opts->diis_n;
     }
+    if (opts->max_purify > 0) p.tc2_iters = p.tc2_start = opts->max_purify;
     rc = upload_plan(p, hp, st);
     if (rc != RI_OK) return rc;
     // per-molecule setup: S, h, E_nn, Cholesky of S and L_S^{-1}.  Each
@@ -842,16 +873,29 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
     // the molecules are spread over SETUP_STREAMS streams forked from and
     // joined back into `st` (a non-positive pivot is reported by atomicMin)
     constexpr int SETUP_STREAMS = 4;
+    // On every exit the caller's stream waits for all of them before they are
+    // destroyed, so no setup work is left running after an error return.
     struct SetupStreams {
+        hipStream_t st;
         hipStream_t s[SETUP_STREAMS] = {};
         hipEvent_t e[SETUP_STREAMS + 1] = {};
         ~SetupStreams() {
+            for (int k = 0; k < SETUP_STREAMS; ++k) {
+                if (!s[k]) continue;
+                hipEvent_t j = nullptr;
+                if (hipEventCreateWithFlags(&j, hipEventDisableTiming) == hipSuccess) {
+                    if (hipEventRecord(j, s[k]) == hipSuccess) (void)hipStreamWaitEvent(st, j, 0);
+                    (void)hipEventDestroy(j);
+                } else {
+                    (void)hipStreamSynchronize(s[k]);
+                }
+            }
             for (hipEvent_t x : e)
                 if (x) (void)hipEventDestroy(x);
             for (hipStream_t x : s)
                 if (x) (void)hipStreamDestroy(x);
         }
-    } ss;
+    } ss{st};
     int* bad = p.n_active + 1;
     HIPR(ri::fill_i32(bad, INT_MAX, 1, st));
     HIPR(hipEventCreateWithFlags(&ss.e[SETUP_STREAMS], hipEventDisableTiming));
@@ -882,7 +926,7 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
     if (hbad != INT_MAX) return RI_E_NOT_PD;
     // core-Hamiltonian start
     copy_h_b<<<p.n2.total, 256, 0, st>>>(p.d, p.n2.prefix, n_mol);
-    HIPR(occupied_space_b(p, st));
+    HIPR(occupied_space_b(p, p.tc2_start, st));
     // iterations.  A graph is captured on a private non-blocking stream (the
     // caller's stream may be the legacy default stream, which cannot be
     // captured); the host waits for every iteration, so ordering with the
@@ -924,11 +968,11 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
         HIPR(final_fp64_b(p, st));
     }
     // results
-    bool all = true;
+    bool all = true, nopur = false;
     for (int i = 0; i < n_mol; ++i) {
         const MolDesc& m = hp.mols[i];
         double sc[8];
-        int stt[16];
+        int stt[ST_N];
         HIPR(hipMemcpyAsync(sc, m.scal, sizeof(sc), hipMemcpyDeviceToHost, st));
         HIPR(hipMemcpyAsync(stt, m.state, sizeof(stt), hipMemcpyDeviceToHost, st));
         HIPR(hipStreamSynchronize(st));
@@ -938,10 +982,11 @@ int32_t ri_energy_batched(int32_t n_mol, const ri_system* sys, const ri_batch_mo
         r.n_iter = stt[ST_IT];
         r.converged = stt[ST_CONV];
         all = all && stt[ST_CONV];
+        nopur = nopur || stt[ST_NOPUR];
         if (mol[i].F) HIPR(ri::copy(mol[i].F, m.F, (int64_t)m.N * m.N, st));
     }
     HIPR(hipStreamSynchronize(st));
-    return all ? RI_OK : RI_E_NO_CONV;
+    return nopur ? RI_E_NO_PURIFY : (all ? RI_OK : RI_E_NO_CONV);
 }
 
 }  // extern "C"

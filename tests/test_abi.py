@@ -101,11 +101,16 @@ def test_bad_arguments_rejected_before_device_work():
     assert lib.ri_energy_batched_workspace(1, ctypes.byref(sysarr), ctypes.byref(mols),
                                            P.BF16X3 | P.FINAL_FP64) == 0
     assert ctypes.sizeof(Bd.BatchMol) == 6 * 8
-    # the final-FP64 flag: ri_energy (and its workspace) with resident FP32 B only
+    # the final-FP64 flag: ri_energy (and its workspace) with resident FP32 or split-BF16 B only
     W = lib.ri_workspace_bytes
     assert W(3, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) > W(3, 100, 300, 10, 1000, P.FP32) > 0
     assert W(3, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) == W(3, 100, 300, 10, 1000, P.FP64)
-    for prec in (P.FP64 | P.FINAL_FP64, P.FP32 | P.COMPRESSED | P.FINAL_FP64, P.BF16X6 | P.FINAL_FP64):
+    for prec in (P.BF16X3, P.BF16X6):
+        # the split-BF16 final build adds FP64 X^T and one slab of unpacked FP64 tiles
+        assert W(3, 100, 300, 10, 1000, prec | P.FINAL_FP64) > W(3, 100, 300, 10, 1000, prec) > 0
+        # their gradient reads B_c slab by slab, as the compressed FP64 form does
+        assert W(4, 100, 300, 10, 1000, prec) == W(4, 100, 300, 10, 1000, P.FP64 | P.COMPRESSED)
+    for prec in (P.FP64 | P.FINAL_FP64, P.FP32 | P.COMPRESSED | P.FINAL_FP64, P.BF16X6 | P.COMPRESSED):
         assert W(3, 100, 300, 10, 1000, prec) == 0
     assert W(2, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) == 0      # Fock build
     assert W(4, 100, 300, 10, 1000, P.FP32 | P.FINAL_FP64) == 0      # gradient

@@ -32,7 +32,9 @@ def test_batched_fp64_matches_single_and_oracle(graph):
         pr.build_3c()
         pr.metric_factor(P.FP64)
         probs.append(pr)
-    res, Cs, _ = energy_batched(probs, P.FP64, tol_E=1e-11, tol_err=1e-9, use_graph=graph)
+    res, Cs, _ = energy_batched(probs, P.FP64, tol_E=1e-11, tol_err=1e-9, use_graph=graph, raise_on_noconv=False)
+    print(" ".join(f"[N={s.N} conv={r['converged']} it={r['n_iter']} E={r['E_total']:.10f}]"
+                   for s, r in zip(systems, res)), flush=True)
     for k, (s, pr, r) in enumerate(zip(systems, probs, res)):
         single, *_ = pr.energy(tol_E=1e-11, tol_err=1e-9)
         assert r["converged"]
@@ -54,7 +56,9 @@ def test_batched_fp32_error():
         pr.build_3c()
         pr.metric_factor(P.FP32)
         probs.append(pr)
-    res, _, _ = energy_batched(probs, P.FP32, tol_E=1e-7, tol_err=1e-5)
+    res, _, _ = energy_batched(probs, P.FP32, tol_E=1e-7, tol_err=1e-5, raise_on_noconv=False)
+    print(" ".join(f"[N={s.N} conv={r['converged']} it={r['n_iter']} E={r['E_total']:.10f}]"
+                   for s, r in zip(systems, res)), flush=True)
     for s, r in zip(systems, res):
         ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
         assert r["converged"] and abs(r["E_total"] - ref.E) < 1e-6

@@ -203,6 +203,26 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
                    const double* C_occ, double* J, double* K, double* gamma,
                    void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ri_fock_jk_noalloc - ri_fock_jk for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments without the workspace, same kernels and
+ * results (bit for bit).  Scratch is a static device array of
+ * RI_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends; the call returns RI_E_WORKSPACE when the build
+ * needs more (ri_workspace_bytes(RI_OP_FOCK, ...) above that size: N = 200
+ * with N_aux = 600 and n_occ = 20 fits in FP64, N = 240 with 720 and 24 does
+ * not).  It makes no allocation of any kind: the whole build runs on
+ * `stream` (no side stream, no events).  The first call on a device looks up
+ * the array's device address once.  Every call on a device shares that
+ * device's array and leaves its contents behind; nothing in it needs to start
+ * at zero (each call writes every scratch element it reads).  Calls that
+ * overlap in time on one device (other streams or threads) race on the array
+ * and must be serialised by the caller.  Asynchronous. */
+#define RI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int32_t ri_fock_jk_noalloc(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
+                           const double* Bc, const int32_t* pairs, int64_t n_pairs,
+                           const double* C_occ, double* J, double* K, double* gamma, hipStream_t stream);
+
 /* ri_fock_jk_timed - ri_fock_jk with phase events, for measurement.
  * Same computation, arguments and schedule as ri_fock_jk (paper: eq. j_ri,
  * eq. k_ri_2, eq. tp, Algorithm 1 Fock-build loop): the gamma/J contraction

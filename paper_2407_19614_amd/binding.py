@@ -100,6 +100,8 @@ _SIGS = {
                                    c_int32, POINTER(c_int64), c_void_p, c_size_t, c_void_p]),
     "ri_fock_jk": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64, c_void_p,
                              c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "ri_fock_jk_noalloc": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_fock_jk_timed": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
                                    ctypes.POINTER(c_void_p)]),
@@ -288,6 +290,14 @@ class RIProblem:
                                 _ptr(ws), nb, self.stream())
         _check(code, "ri_fock_jk")
         return J, K, gamma
+
+    def fock_jk_noalloc(self, C_occ, J, K, gamma=None):
+        """ri_fock_jk_noalloc into caller-owned J, K (and gamma): the library's
+        static scratch instead of a workspace.  Returns the status code."""
+        C_occ = C_occ.contiguous()
+        return lib().ri_fock_jk_noalloc(self.N, self.n_aux, self.n_occ, _ptr(self.B), self.pflag, _ptr(self.T),
+                                        _ptr(self.pairs), self.n_pairs, _ptr(C_occ), _ptr(J), _ptr(K), _ptr(gamma),
+                                        self.stream())
 
     def fock_jk_timed(self, C_occ, J, K, gamma, events):
         """ri_fock_jk with four torch.cuda.Event objects recorded by the

@@ -295,13 +295,15 @@ struct Fork {
 // for it before the call returns.  ev (phase-timed form): ev[0] on `st`
 // before both parts, ev[1] on the side stream after the Coulomb part, ev[2]
 // on `st` after X, ev[3] on `st` after the SYRK and the join.
+// With side == false everything runs on `st` (no side stream, no events): the
+// same kernels and sums, so the same results bit for bit.
 int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const double* Bc, const int32_t* pairs,
                   int64_t n_pairs, const double* C, double* J, double* K, double* gamma, const FockWS& w,
-                  hipStream_t st, hipEvent_t* ev = nullptr) {
+                  hipStream_t st, hipEvent_t* ev = nullptr, bool side = true) {
     double* g = gamma ? gamma : w.gamma;
     if (ev) HIPC(hipEventRecord(ev[0], st));
     Fork fk;
-    const bool overlap = fk.open(st);
+    const bool overlap = side && fk.open(st);
     if (ev && !overlap) {
         ri::set_hip_error("side stream or its events could not be created");
         return RI_E_HIP;
@@ -383,6 +385,29 @@ int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool hav
     }
     HIPC(ri::gemm_f64(true, false, N, n_occ, N, 1.0, w.LinvS, N, 0, w.Cp, n_occ, 0, 0.0, C_out, n_occ, 0, 1, 2, 0,
                       st));
+    return RI_OK;
+}
+
+// Scratch of ri_fock_jk_noalloc: a static device array, one copy on each
+// device the library runs on, held until the process ends.  Host code never
+// names it except to look up its device address.
+static __device__ __align__(256) char scratch[RI_NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int32_t noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* ptrs[64] = {};
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return RI_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        ptrs[dev] = p;
+    }
+    *out = ptrs[dev];
     return RI_OK;
 }
 
@@ -525,6 +550,27 @@ int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32
     FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp);
     if (!a.ok()) return RI_E_WORKSPACE;
     return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st);
+}
+
+int32_t ri_fock_jk_noalloc(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec_arg,
+                           const double* Bc, const int32_t* pairs, int64_t n_pairs, const double* C, double* J,
+                           double* K, double* gamma, hipStream_t st) {
+    const Prec pp = split_prec(prec_arg);
+    const int prec = pp.base;
+    if (N <= 0 || n_aux <= 0 || n_occ <= 0 || n_occ > N || n_pairs < 0 || (!B && !pp.comp) || !C || !J || !K ||
+        (n_pairs > 0 && (!Bc || !pairs)))
+        return RI_E_ARG;
+    if (!pp.ok || (is_bf16(prec) && n_occ > 128)) return RI_E_UNSUPPORTED;
+    if (pp.comp) B = nullptr;
+    Arena dry{nullptr, 0, 0, true};
+    carve_fock(dry, N, n_aux, n_occ, n_pairs, prec, pp.comp);
+    if (dry.off + 256 > RI_NOALLOC_SCRATCH_BYTES) return RI_E_WORKSPACE;
+    void* ws = nullptr;
+    const int32_t rc = noalloc_scratch(&ws);
+    if (rc != RI_OK) return rc;
+    Arena a{(char*)ws, RI_NOALLOC_SCRATCH_BYTES, 0, false};
+    FockWS w = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, pp.comp);
+    return fock_impl(N, n_aux, n_occ, B, prec, Bc, pairs, n_pairs, C, J, K, gamma, w, st, nullptr, false);
 }
 
 int32_t ri_fock_jk_timed(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec_arg,

@@ -23,7 +23,7 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["gemm.hip", "integrals.hip", "fock.hip", "scf.hip", "grad.hip", "mlp.hip", "batch.hip", "bf16.hip", "md.hip", "density.hip", "api.hip"]
+SOURCES = ["gemm.hip", "integrals.hip", "fock.hip", "scf.hip", "grad.hip", "mlp.hip", "batch.hip", "bf16.hip", "md.hip", "density.hip", "tc2.hip", "api.hip"]
 
 
 def _compile(src):

@@ -174,8 +174,8 @@ hipError_t jk_density(const double* Bc, const int32_t* pairs, int64_t n_pairs, i
 struct EnergyWS {
     double *S, *H, *Ls, *LinvS, *J, *K, *F, *D, *T1, *T2, *E, *Fx, *X, *X2;
     double *dF[8], *dE[8];
-    double *Bmat, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal, *red;
-    int* bad;
+    double *Bmat, *Bfull, *coef, *row, *Y, *Cp, *R, *Mo, *LinvM, *dinvS, *dinvM, *scal, *red, *tpart;
+    int *bad, *tst;
     FockWS fock;
     FockWS fin;   // final FP64 exchange build of the split-BF16 forms: FP64 Xt and slabs of B_c
     DensityWS dens;
@@ -191,6 +191,7 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
         w.dE[i] = i < diis_n ? a.take<double>(n2) : nullptr;
     }
     w.Bmat = a.take<double>(64);
+    w.Bfull = a.take<double>(64);
     w.coef = a.take<double>(8);
     w.row = a.take<double>(8);
     w.Y = a.take<double>((int64_t)N * n_occ);
@@ -202,7 +203,9 @@ EnergyWS carve_energy(Arena& a, int N, int n_aux, int n_occ, int64_t n_pairs, in
     w.dinvM = a.take<double>((int64_t)((n_occ + 63) / 64) * 4096);
     w.scal = a.take<double>(32);
     w.red = a.take<double>(ri::red_elems(N));   // reduction partials
+    w.tpart = a.take<double>(4 * (int64_t)ri::tc2f_tiles(N));   // purification partial sums, two parities
     w.bad = a.take<int>(2);
+    w.tst = a.take<int>(16);                                    // purification state, two parities
     w.fock = carve_fock(a, N, n_aux, n_occ, n_pairs, prec, comp);
     w.fin = fin_slab ? carve_fock(a, N, n_aux, n_occ, n_pairs, RI_FP64, true) : FockWS{};
     w.dens = carve_density(a, N, n_aux, n_pairs);
@@ -333,47 +336,36 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
 // Occupied orbitals of the Fock matrix Fx (the n_occ lowest solutions of
 // F C = S C eps): projector by TC2 purification in the basis orthonormalised
 // by L_S^{-1}, then an orthonormal basis of its range by two passes of
-// projection and Cholesky QR, mapped back by L_S^{-T}.
+// projection and Cholesky QR, mapped back by L_S^{-T}.  The purification
+// steps are launched in chunks (first `pred` steps, the previous
+// purification's count plus two, then 8 at a time) and the state is read once
+// per chunk; steps after the last one exit at once.
 int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool have_prev, double* C_out,
-                       int max_it, hipStream_t st) {
+                       int max_it, int& pred, hipStream_t st) {
     const int64_t n2 = (int64_t)N * N;
     HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.LinvS, N, 0, Fx, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
     HIPC(ri::gemm_f64(false, true, N, N, N, 1.0, w.T1, N, 0, w.LinvS, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
     HIPC(ri::gershgorin(w.T2, N, w.scal + 16, w.red, st));
-    HIPC(ri::tc2_init(w.T2, w.scal + 16, N, w.X, st));
-    double idem = 1.0;
-    int it = 0, extra = -1;
-    // When the 64 x 64 tiles of X^2 are fewer than two per compute unit, the
-    // square is formed as two K-halves in one batched launch into T1 and T2
-    // (free here) and summed, so twice as many workgroups share the work.
-    const int t64 = (N + 63) / 64;
-    const bool halves = N % 2 == 0 && N >= 256 && t64 * t64 < 2 * ri::device_cus();
-    double* X2 = halves ? w.T1 : w.X2;
-    while (it < max_it) {
-        if (halves) {
-            const int h = N / 2;
-            HIPC(ri::gemm_f64(false, false, N, N, h, 1.0, w.X, N, h, w.X, N, (int64_t)h * N, 0.0, w.T1, N,
-                              (int64_t)(w.T2 - w.T1), 2, 0, 0, st));
-            HIPC(ri::axpby(w.T1, w.T2, 1.0, 1.0, n2, st));
-        } else {
-            HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.X, N, 0, w.X, N, 0, 0.0, w.X2, N, 0, 1, 0, 0, st));
+    const int tiles = ri::tc2f_tiles(N);
+    HIPC(ri::tc2f_init(w.T2, w.scal + 16, N, w.X, w.tpart, w.tst, st));
+    int k = 0, chunk = std::max(8, std::min(pred, max_it)), hs[8] = {};
+    while (true) {
+        const int upto = std::min(max_it, k + chunk);
+        for (; k < upto; ++k) {
+            const int p = k & 1;
+            HIPC(ri::tc2f_step(p ? w.X2 : w.X, p ? w.X : w.X2, N, n_occ, w.tpart + 2 * tiles * p,
+                               w.tpart + 2 * tiles * (p ^ 1), w.tst + 8 * p, w.tst + 8 * (p ^ 1), p ? 0 : 1, st));
         }
-        HIPC(ri::traces(w.X, X2, N, w.scal + 20, st));
-        HIPC(ri::tc2_update(w.X, X2, w.scal + 20, n_occ, n2, st));
-        ++it;
-        if (extra > 0) {
-            if (--extra == 0) break;
-            continue;
-        }
-        if (it % 4 == 0) {
-            HIPC(hipMemcpyAsync(&idem, w.scal + 22, sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPC(hipStreamSynchronize(st));
-            if (std::fabs(idem) < 1e-11 * std::max(1, n_occ)) extra = 3;
-        }
+        HIPC(hipMemcpyAsync(hs, w.tst + 8 * (k & 1), sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        if (hs[1] || k >= max_it) break;
+        chunk = 8;
     }
     // a projector that reached the idempotency threshold is used even when the
     // step limit cut its last extra steps short
-    if (extra < 0) return RI_E_NO_PURIFY;
+    if (hs[0] < 0) return RI_E_NO_PURIFY;
+    pred = hs[2] + 2;
+    HIPC(ri::tc2f_final(w.X, w.X2, N, w.tst + 8 * (k & 1), st));
     if (!have_prev) HIPC(ri::hash_matrix(w.Cp, (int64_t)N * n_occ, 0x5eed1234u, st));
     for (int pass = 0; pass < 2; ++pass) {
         HIPC(ri::gemm_f64(false, false, N, n_occ, N, 1.0, w.X, N, 0, w.Cp, n_occ, 0, 0.0, w.Y, n_occ, 0, 1, 0, 0, st));
@@ -505,7 +497,7 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
     *bad_pivot = -1;
     HIPC(ri::metric(sys, L, st));
     HIPC(ri::fill_i32(w.bad, INT_MAX, 1, st));
-    HIPC(ri::cholesky_inv(L, na, na, Linv, na, w.dinv, w.bad, st));
+    HIPC(ri::cholesky_inv(L, na, na, nullptr, na, w.dinv, w.bad, st));
     int bad = INT_MAX;
     HIPC(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
@@ -513,13 +505,39 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
         *bad_pivot = bad;
         return RI_E_NOT_PD;
     }
-    // Bc = L^{-1} T by blocked forward substitution, in place over T.
-    if (n_pairs > 0) HIPC(ri::trsm_lower_inplace(L, na, na, w.dinv, T, (int)n_pairs, n_pairs, st));
-    if (B) {
-        HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
-        if (is_bf16(prec)) HIPC(ri::pack_b_bf16(T, n_pairs, w.map, N, na, B, prec, st));
-        else HIPC(ri::pack_b(T, n_pairs, w.map, N, na, B, prec, st));
-    }
+    // L^{-1}, and the packing of each block of B rows once the triangular solve
+    // has finished them, run on the side stream beside the solve: the solve is
+    // bound by MFMA throughput, the packing by memory bandwidth.
+    Fork fk;
+    const bool side = fk.open(st);
+    hipStream_t ss = side ? fk.side : st;
+    HIPC(ri::tri_inverse(L, na, na, w.dinv, Linv, na, ss));
+    if (B) HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
+    struct Events {
+        std::vector<hipEvent_t> e;
+        ~Events() {
+            for (hipEvent_t x : e) (void)hipEventDestroy(x);
+        }
+    } evs;
+    const int64_t b_row = B ? (int64_t)ri_packed_b_bytes(N, 1, prec) : 0;   // bytes of one auxiliary's packed tiles
+    auto pack_rows = [&](int r0, int r1) -> hipError_t {
+        if (!B) return hipSuccess;
+        if (side) {
+            hipEvent_t e = nullptr;
+            RI_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            evs.e.push_back(e);
+            RI_TRY(hipEventRecord(e, st));
+            RI_TRY(hipStreamWaitEvent(ss, e, 0));
+        }
+        const double* rows = T + (int64_t)r0 * n_pairs;
+        void* out = (char*)B + r0 * b_row;
+        return is_bf16(prec) ? ri::pack_b_bf16(rows, n_pairs, w.map, N, r1 - r0, out, prec, ss)
+                             : ri::pack_b(rows, n_pairs, w.map, N, r1 - r0, out, prec, ss);
+    };
+    // Bc = L^{-1} T by recursive blocked forward substitution, in place over T.
+    if (n_pairs > 0) HIPC(ri::trsm_rec(L, na, na, w.dinv, T, (int)n_pairs, n_pairs, st, 0, pack_rows));
+    else HIPC(pack_rows(0, na));
+    HIPC(fk.close());
     return RI_OK;
 }
 
@@ -616,6 +634,7 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
     if (opts->guess_kind != 0 && !guess) return RI_E_ARG;
     if (opts->max_purify < 0) return RI_E_ARG;
     const int npur = opts->max_purify > 0 ? opts->max_purify : 200;
+    int pred = 40;   // purification steps launched before the first state read
     if (opts->guess_kind < 0 || opts->guess_kind > 3) return RI_E_UNSUPPORTED;
     if (!pp.ok || (is_bf16(prec) && sys->n_occ > 128)) return RI_E_UNSUPPORTED;
     // Two bfloat16 parts hold B and C_occ to about 2^-17: at the 8-centre
@@ -643,19 +662,19 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
 
     int32_t rc;
     if (opts->guess_kind == 0) {
-        rc = occupied_space(w.H, N, no, w, false, C_occ, npur, st);
+        rc = occupied_space(w.H, N, no, w, false, C_occ, npur, pred, st);
         if (rc) return rc;
     } else if (opts->guess_kind == 3) {
         // Fock matrix of the density itself (J and K from D), then its occupied space
         HIPC(jk_density(Bc, pairs, n_pairs, N, na, guess, w.J, w.K, nullptr, w.dens, st));
         HIPC(ri::fock_assemble(w.H, w.J, w.K, w.F, n2, st));
-        rc = occupied_space(w.F, N, no, w, false, C_occ, npur, st);
+        rc = occupied_space(w.F, N, no, w, false, C_occ, npur, pred, st);
         if (rc) return rc;
     } else if (opts->guess_kind == 2) {
         // occupied space of the density: lowest solutions of (-S D S) v = l S v
         HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.S, N, 0, guess, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
         HIPC(ri::gemm_f64(false, false, N, N, N, -1.0, w.T1, N, 0, w.S, N, 0, 0.0, w.Fx, N, 0, 1, 0, 0, st));
-        rc = occupied_space(w.Fx, N, no, w, false, C_occ, npur, st);
+        rc = occupied_space(w.Fx, N, no, w, false, C_occ, npur, pred, st);
         if (rc) return rc;
     } else {
         HIPC(ri::copy(C_occ, guess, (int64_t)N * no, st));
@@ -664,7 +683,7 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
     }
 
     std::vector<int> slots;
-    double Bh[8][8] = {};   // DIIS inner products <e_i, e_j>, indexed by ring slot
+    HIPC(ri::fill(w.Bfull, 0.0, 64, st));   // DIIS inner products <e_i, e_j>, indexed by ring slot
     int pushes = 0;
     double E_old = 0.0, host[8];
     bool converged = false;
@@ -709,24 +728,17 @@ int32_t ri_energy(const ri_system* sys, const void* B, int32_t prec_arg, const d
             const double* es[8];
             for (int k = 0; k < m; ++k) es[k] = w.dE[slots[k]];
             HIPC(ri::diis_dots(es, m, w.dE[s], w.row, n2, w.red, st));
-            double row[8];
-            HIPC(hipMemcpyAsync(row, w.row, m * sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPC(hipStreamSynchronize(st));
-            for (int k = 0; k < m; ++k) { Bh[s][slots[k]] = row[k]; Bh[slots[k]][s] = row[k]; }
+            HIPC(ri::diis_prep(w.Bfull, w.row, slots.data(), m, s, w.Bmat, st));
         }
         const double* Fx = w.F;
         if (m >= 2) {
             const double* fs[8];
             for (int k = 0; k < m; ++k) fs[k] = w.dF[slots[k]];
-            double Bm[64];
-            for (int i = 0; i < m; ++i)
-                for (int j = 0; j < m; ++j) Bm[i * 8 + j] = Bh[slots[i]][slots[j]];
-            HIPC(hipMemcpyAsync(w.Bmat, Bm, sizeof(Bm), hipMemcpyHostToDevice, st));
             HIPC(ri::diis_solve(w.Bmat, m, 8, w.coef, st));
             HIPC(ri::diis_combine(fs, w.coef, m, w.Fx, n2, st));
             Fx = w.Fx;
         }
-        rc = occupied_space(Fx, N, no, w, true, C_occ, npur, st);
+        rc = occupied_space(Fx, N, no, w, true, C_occ, npur, pred, st);
         if (rc) return rc;
     }
     if (pp.fin && converged) {

@@ -360,19 +360,18 @@ __global__ void tc2_check_b(const MolDesc* d, int n_mol) {
 }
 
 // Cholesky of the n_occ x n_occ (<= 64) Gram matrix Mo and its inverse into
-// LinvM (64 x 64, row stride 64).
-__global__ __launch_bounds__(256) void small_chol_b(const MolDesc* d, int n_mol) {
+// LinvM (64 x 64, row stride 64), on one wave per molecule.
+__global__ __launch_bounds__(64) void small_chol_b(const MolDesc* d, int n_mol) {
     const MolDesc& m = d[blockIdx.x];
     if (!m.state[ST_ACTIVE]) return;
-    __shared__ double L[64][65];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nb = m.n_occ;
-    for (int r = wv; r < 64; r += 4)
-        L[r][lane] = (r < nb && lane < nb) ? m.Mo[(int64_t)r * nb + lane] : (r == lane ? 1.0 : 0.0);
+    __shared__ double S[64][65];
+    const int lane = threadIdx.x, nb = m.n_occ;
+    for (int r = 0; r < 64; ++r)
+        S[r][lane] = (r < nb && lane < nb) ? m.Mo[(int64_t)r * nb + lane] : (r == lane ? 1.0 : 0.0);
     __syncthreads();
     int* bad = m.state + ST_BAD;
     double* out = m.LinvM;
-    potrf_inv_block64<256>(L, nb, [&](int) { atomicAdd(bad, 1); },
-                           [&](int i, int c, double v) { out[i * 64 + c] = v; });
+    chol_inv64_wave(S, nb, [&](int) { atomicAdd(bad, 1); }, [&](int i, int c, double v) { out[i * 64 + c] = v; });
 }
 
 __global__ void count_active_b(const MolDesc* d, int n_mol, int* out) {
@@ -433,7 +432,7 @@ hipError_t occupied_space_b(const Plan& p, int tc2_steps, hipStream_t st) {
     for (int pass = 0; pass < 2; ++pass) {
         HC(gg(p.g_y));
         HC(gg(p.g_mo));
-        small_chol_b<<<nm, 256, 0, st>>>(d, nm);
+        small_chol_b<<<nm, 64, 0, st>>>(d, nm);
         HC(gg(p.g_cp));
     }
     HC(gg(p.g_c));

@@ -63,43 +63,85 @@ __device__ __forceinline__ double boys_f1(double t) {
     return (boys_f0(t) - e) / (2.0 * t);
 }
 
-// Lower Cholesky of an nb x nb (nb <= 64) block held in LDS as L[64][65]
-// (rows/columns beyond nb set to the identity by the caller), in place on
-// and below the diagonal, and its inverse, written through store(i, c, value)
-// for all 64 x 64 entries (zero above the diagonal, identity beyond nb).  A
-// workgroup of NT threads (NT / 64 waves) runs it: at step j the pivot and
-// column j are finished, row j of the inverse is scaled, and then every wave
-// takes rows i > j of both the trailing Cholesky update and the forward
-// elimination X_i -= L_ij X_j, one column per lane, so each step is two
-// barriers of uniform work.  A pivot that is not positive is reported through
-// bad(j) and replaced by 1.
-template <int NT, class Bad, class Store>
-__device__ __forceinline__ void potrf_inv_block64(double (*L)[65], int nb, Bad bad, Store store) {
-    static_assert(NT % 64 == 0, "whole waves");
-    constexpr int NW = NT / 64;
-    __shared__ double X[64][65];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    for (int i = wv; i < 64; i += NW) X[i][lane] = i == lane ? 1.0 : 0.0;
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        const double d = L[j][j];
+// Value of v in lane src, for every lane of the wave.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// Lower Cholesky of a 64 x 64 block and the inverse of its factor on one
+// wave (the workgroup is exactly 64 lanes), with no waits on other waves.
+// S[64][65] in LDS holds the block on entry (row-major; rows and columns at
+// or beyond nb set to the identity by the caller; only the lower triangle is
+// read) and the factor L (zero above the diagonal) on exit.
+// - Factor, right-looking: lane r keeps row r in registers.  At step j the
+//   pivot comes from lane j, every lane forms its L[r][j] and writes it to an
+//   LDS column, and the trailing update a[c] -= L[r][j] L[c][j] (r >= c)
+//   reads that column back as broadcast loads, 16 entries ahead of their use.
+// - Inverse, forward substitution: lane c forms column c of X = L^{-1},
+//   X[r][c] = (delta_rc - sum_{k<r} L[r][k] X[k][c]) / L[r][r], reading the
+//   rows of L as broadcast loads, and passes it to store(r, c, value) (row r
+//   across lanes is contiguous).
+// A pivot that is not positive is reported through bad(j) and replaced by 1.
+// Each pivot's reciprocal is formed once (hardware estimate and two Newton
+// steps, within an ulp of 1/piv) and multiplies instead of dividing, which
+// keeps the fully unrolled steps free of the division sequence.
+template <class Bad, class Store>
+__device__ __forceinline__ void chol_inv64_wave(double (*S)[65], int nb, Bad bad, Store store) {
+    const int lane = threadIdx.x & 63;
+    __shared__ double rdiag[64];
+    __shared__ double col[64];
+    double a[64];
+    int first_bad = 64;   // branch-free inside the unrolled steps; reported once
+#pragma unroll
+    for (int c = 0; c < 64; ++c) a[c] = S[lane][c];
+#pragma clang loop unroll(full)
+    for (int j = 0; j < 64; ++j) {
+        const double d = lane_bcast(a[j], j);
+        first_bad = (j < nb && !(d > 0.0) && first_bad == 64) ? j : first_bad;
         const double piv = sqrt(d > 0.0 ? d : 1.0);
-        if (wv == 0) {
-            if (lane == 0 && !(d > 0.0)) bad(j);
-            if (lane > j && lane < nb) L[lane][j] /= piv;      // column j of the factor
-            if (lane <= j) X[j][lane] /= piv;                   // row j of the inverse
-        }
+        double rp = __builtin_amdgcn_rcp(piv);
+        rp = fma(rp, fma(-piv, rp, 1.0), rp);
+        rp = fma(rp, fma(-piv, rp, 1.0), rp);
+        rdiag[j] = rp;   // every lane writes the same value
+        a[j] = lane > j ? a[j] * rp : (lane == j ? piv : 0.0);
+        col[lane] = a[j];
         __syncthreads();
-        if (t == 0) L[j][j] = piv;
-        const double lcj = lane > j ? L[lane][j] : 0.0, xjc = X[j][lane];
-        for (int i = j + 1 + wv; i < nb; i += NW) {
-            const double lij = L[i][j];
-            if (lane > j && lane <= i) L[i][lane] -= lij * lcj;
-            if (lane <= j) X[i][lane] -= lij * xjc;
+        // column j read back 16 entries at a time ahead of their updates
+#pragma unroll
+        for (int c0 = j + 1; c0 < 64; c0 += 16) {
+            double l[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) l[t] = c0 + t < 64 ? col[c0 + t] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (c0 + t < 64 && lane >= c0 + t) a[c0 + t] -= a[j] * l[t];
         }
         __syncthreads();
     }
-    for (int i = wv; i < 64; i += NW) store(i, lane, X[i][lane]);
+    if (lane == 0 && first_bad < 64) bad(first_bad);
+#pragma unroll
+    for (int c = 0; c < 64; ++c) S[lane][c] = c <= lane ? a[c] : 0.0;
+    __syncthreads();
+    // row r of L read 16 entries at a time ahead of its products, into four
+    // partial sums (independent chains)
+    double x[64];
+#pragma clang loop unroll(full)
+    for (int r = 0; r < 64; ++r) {
+        double v[4] = {r == lane ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k0 = 0; k0 < r; k0 += 16) {
+            double l[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) l[t] = k0 + t < r ? S[r][k0 + t] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (k0 + t < r) v[t & 3] -= l[t] * x[k0 + t];
+        }
+        x[r] = ((v[0] + v[1]) + (v[2] + v[3])) * rdiag[r];
+        store(r, lane, x[r]);
+    }
 }
 
 // ------------------------------------------------------------ launch helpers
@@ -120,6 +162,11 @@ hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha,
 // *d_bad (device int, caller initialises it to INT_MAX).
 hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi,
                         double* dwork, int* d_bad, hipStream_t s);
+
+// Linv = L^{-1} from the factor and its diagonal-block inverses (as left by
+// cholesky_inv with Linv == nullptr).
+hipError_t tri_inverse(const double* L, int n, int64_t lda, const double* Dinv, double* Linv, int64_t ldi,
+                       hipStream_t s);
 
 // In place B <- L^{-1} B for lower L (n x n) whose 64 x 64 diagonal-block
 // inverses are in Dinv (as left by cholesky_inv); B has ncols columns.

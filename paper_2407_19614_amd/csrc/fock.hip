@@ -23,24 +23,24 @@ __global__ void pair_map_kernel(const int32_t* pairs, int64_t n_pairs, int N, in
     map[(int64_t)pairs[2 * q] * N + pairs[2 * q + 1]] = (int32_t)q;
 }
 
-// B[P][tile][r*64+c] = Bc[P][pair(64I+r, 64J+c)] or 0.
+// B[P][tile][r*64+c] = Bc[P][pair(64I+r, 64J+c)] or 0, for PB consecutive P
+// per workgroup so that each pair-map lookup serves all of them.
+constexpr int PACK_PB = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void pack_kernel(const double* Bc, int64_t n_pairs, const int32_t* map,
-                                                   int N, int64_t ntl, T* B) {
-    const int t = blockIdx.x, P = blockIdx.y;
+                                                   int N, int64_t ntl, int n_aux, T* B) {
+    const int t = blockIdx.x, P0 = blockIdx.y * PACK_PB;
     int I, J;
     tile_ij(t, I, J);
-    const double* row = Bc + (int64_t)P * n_pairs;
-    T* out = B + ((int64_t)P * ntl + t) * 4096;
     for (int e = threadIdx.x; e < 4096; e += 256) {
-        int mu = 64 * I + (e >> 6), nu = 64 * J + (e & 63);
-        double v = 0.0;
-        if (mu < N && nu < N) {
-            int m = max(mu, nu), n = min(mu, nu);
-            int32_t q = map[(int64_t)m * N + n];
-            if (q >= 0) v = row[q];
+        const int mu = 64 * I + (e >> 6), nu = 64 * J + (e & 63);
+        int32_t q = -1;
+        if (mu < N && nu < N) q = map[(int64_t)max(mu, nu) * N + min(mu, nu)];
+#pragma unroll
+        for (int p = 0; p < PACK_PB; ++p) {
+            const int P = P0 + p;
+            if (P < n_aux) B[((int64_t)P * ntl + t) * 4096 + e] = (T)(q >= 0 ? Bc[(int64_t)P * n_pairs + q] : 0.0);
         }
-        out[e] = (T)v;
     }
 }
 
@@ -762,11 +762,11 @@ hipError_t pair_map(const int32_t* pairs, int64_t n_pairs, int N, int32_t* map, 
 
 hipError_t pack_b(const double* Bc, int64_t n_pairs, const int32_t* map, int N, int n_aux, void* B,
                   int prec, hipStream_t st) {
-    dim3 grid((unsigned)n_tiles(N), n_aux);
+    dim3 grid((unsigned)n_tiles(N), (n_aux + PACK_PB - 1) / PACK_PB);
     if (prec == RI_FP64)
-        pack_kernel<double><<<grid, 256, 0, st>>>(Bc, n_pairs, map, N, n_tiles(N), (double*)B);
+        pack_kernel<double><<<grid, 256, 0, st>>>(Bc, n_pairs, map, N, n_tiles(N), n_aux, (double*)B);
     else if (prec == RI_FP32)
-        pack_kernel<float><<<grid, 256, 0, st>>>(Bc, n_pairs, map, N, n_tiles(N), (float*)B);
+        pack_kernel<float><<<grid, 256, 0, st>>>(Bc, n_pairs, map, N, n_tiles(N), n_aux, (float*)B);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -3,6 +3,7 @@
 #include "common.h"
 #include "kernels.h"
 #include <climits>
+#include <functional>
 
 namespace {
 
@@ -129,11 +130,11 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const ri::GemmDesc* d
 
 // 128 x 128 variant: 4 waves in 2 x 2, each owning 64 x 64 of C as 4 x 4 MFMA
 // tiles (64 FP64 accumulators per lane).  Same staging scheme as above.
-template <bool TA, bool TB>
+template <bool TA, bool TB, int BK = ::BK>
 __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, const double* __restrict__ A,
                                              int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
                                              double* __restrict__ C, int64_t ldc, int tri, int m0, int n0) {
-    constexpr int TM = 128, LD = TM + 1;
+    constexpr int TM = 128, LD = TM + 1, R = BK / 2;   // R: elements of each operand per thread per slice
     __shared__ double As[BK][LD];
     __shared__ double Bs[BK][LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -141,32 +142,35 @@ __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, 
     int kbeg = 0, kend = K;
     if (tri == 1) kend = min(K, m0 + TM);
     if (tri == 2) kbeg = (m0 / BK) * BK;
-    double ra[8], rb[8];
+    double ra[R], rb[R];
+    // thread tid covers (k-major) k = tid % BK, m = tid / BK + (256 / BK) r, or
+    // (m-major) m = tid % 128, k = tid / 128 + 2 r
+    constexpr int MS = 256 / BK;
     auto load = [&](int k0) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < R; ++r) {
             int m, k;
-            if (!TA) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            if (!TA) { k = tid % BK; m = tid / BK + MS * r; }
             else     { m = tid & 127; k = (tid >> 7) + 2 * r; }
             int gm = m0 + m, gk = k0 + k;
             ra[r] = (gm < M && gk < kend) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0;
             int n, kb;
             if (!TB) { n = tid & 127; kb = (tid >> 7) + 2 * r; }
-            else     { kb = tid & 15; n = (tid >> 4) + 16 * r; }
+            else     { kb = tid % BK; n = tid / BK + MS * r; }
             int gn = n0 + n, gkb = k0 + kb;
             rb[r] = (gn < N && gkb < kend) ? (TB ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn]) : 0.0;
         }
     };
     auto store = [&]() {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < R; ++r) {
             int m, k;
-            if (!TA) { k = tid & 15; m = (tid >> 4) + 16 * r; }
+            if (!TA) { k = tid % BK; m = tid / BK + MS * r; }
             else     { m = tid & 127; k = (tid >> 7) + 2 * r; }
             As[k][m] = ra[r];
             int n, kb;
             if (!TB) { n = tid & 127; kb = (tid >> 7) + 2 * r; }
-            else     { kb = tid & 15; n = (tid >> 4) + 16 * r; }
+            else     { kb = tid % BK; n = tid / BK + MS * r; }
             Bs[kb][n] = rb[r];
         }
     };
@@ -210,7 +214,7 @@ __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, 
             }
 }
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, int SBK = BK>
 __global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
     const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
@@ -221,8 +225,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
     const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
     const int m0 = by * TM, n0 = bx * TN;
     if (lowerC && n0 > m0 + TM - 1) return;
-    gemm_tile128<TA, TB>(M, N, K, alpha, A + (int64_t)bz * sA, lda, B + (int64_t)bz * sB, ldb, beta,
-                         C + (int64_t)bz * sC, ldc, tri, m0, n0);
+    gemm_tile128<TA, TB, SBK>(M, N, K, alpha, A + (int64_t)bz * sA, lda, B + (int64_t)bz * sB, ldb, beta,
+                              C + (int64_t)bz * sC, ldc, tri, m0, n0);
 }
 
 // Grouped GEMM on 128 x 128 tiles: problem g owns tiles prefix[g] ..
@@ -240,18 +244,18 @@ __global__ __launch_bounds__(256, 2) void gemm_grouped128_kernel(const ri::GemmD
 
 // Factor one 64x64 diagonal block in place (lower Cholesky) and write the
 // inverse of its factor to Dinv (64x64, lower, identity padding beyond n).
-// One workgroup of 4 waves; rows move with lanes along columns (coalesced).
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int n, int64_t lda, int kb,
-                                                          double* Dinv, int* bad) {
-    __shared__ double L[64][65];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, o = kb * 64, nb = min(64, n - o);
-    for (int r = wv; r < 64; r += 4)
-        L[r][lane] = (r < nb && lane < nb) ? A[(int64_t)(o + r) * lda + o + lane] : (r == lane ? 1.0 : 0.0);
+// One wave; rows are loaded and stored across lanes (coalesced).
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int n, int64_t lda, int kb, double* Dinv,
+                                                         int* bad) {
+    __shared__ double S[64][65];
+    const int lane = threadIdx.x, o = kb * 64, nb = min(64, n - o);
+    for (int r = 0; r < 64; ++r)
+        S[r][lane] = (r < nb && lane < nb) ? A[(int64_t)(o + r) * lda + o + lane] : (r == lane ? 1.0 : 0.0);
     __syncthreads();
-    potrf_inv_block64<256>(L, nb, [&](int j) { atomicMin(bad, o + j); },
-                           [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
-    for (int r = wv; r < nb; r += 4)
-        if (lane < nb) A[(int64_t)(o + r) * lda + o + lane] = (lane <= r) ? L[r][lane] : 0.0;
+    chol_inv64_wave(S, nb, [&](int j) { atomicMin(bad, o + j); }, [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
+    __syncthreads();
+    for (int r = 0; r < nb; ++r)
+        if (lane < nb) A[(int64_t)(o + r) * lda + o + lane] = S[r][lane];
 }
 
 __global__ void zero_upper_kernel(double* A, int n, int64_t lda) {
@@ -383,7 +387,7 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
     const int nb = (n + 63) / 64;
     for (int k = 0; k < nb; ++k) {
         const int o = k * 64, w = min(64, n - o), rest = n - o - w;
-        potrf_diag_kernel<<<1, 256, 0, s>>>(A, n, lda, k, dwork + (int64_t)k * 4096, d_bad);
+        potrf_diag_kernel<<<1, 64, 0, s>>>(A, n, lda, k, dwork + (int64_t)k * 4096, d_bad);
         RI_TRY(hipGetLastError());
         if (rest > 0) {
             double* panel = A + (int64_t)(o + w) * lda + o;
@@ -399,6 +403,12 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
     zero_upper_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(A, n, lda);
     RI_TRY(hipGetLastError());
     if (!Linv) return hipSuccess;
+    return tri_inverse(A, n, lda, dwork, Linv, ldi, s);
+}
+
+hipError_t tri_inverse(const double* A, int n, int64_t lda, const double* dwork, double* Linv, int64_t ldi,
+                       hipStream_t s) {
+    const int nb = (n + 63) / 64;
     // Solve L X = I by blocks: X_k = Dinv_k (I_k - L_{k,<k} X_{<k}).
     identity_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(Linv, n, ldi);
     RI_TRY(hipGetLastError());
@@ -412,6 +422,34 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
                             ldi, 0, 1.0, Linv + (int64_t)(o + w) * ldi, ldi, 0, 1, 0, 0, s));
     }
     return hipSuccess;
+}
+
+// Recursive form: B1 = L11^{-1} B1, B2 -= L21 B1, B2 = L22^{-1} B2, splitting
+// at a multiple of 64 near the middle, so that half the flops run in one GEMM
+// with K = n/2, a quarter in two with K = n/4, and so on; blocks of at most
+// TRSM_LEAF rows use the 64-row scheme below.  done(r0, r1) is called (in
+// stream order) once rows r0 .. r1 of B are final.
+constexpr int TRSM_LEAF = 256;
+hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols, int64_t ldb,
+                    hipStream_t s, int r0, const std::function<hipError_t(int, int)>& done) {
+    if (n <= TRSM_LEAF) {
+        for (int k0 = 0; k0 < n; k0 += 64) {
+            const int w = min(64, n - k0), k1 = k0 + w;
+            double* Bk = B + (int64_t)k0 * ldb;
+            RI_TRY(gemm_f64(false, false, w, ncols, w, 1.0, Dinv + (int64_t)(k0 / 64) * 4096, 64, 0, Bk, ldb, 0,
+                            0.0, Bk, ldb, 0, 1, 0, 0, s));
+            if (k1 < n)
+                RI_TRY(gemm_f64(false, false, n - k1, ncols, w, -1.0, L + (int64_t)k1 * lda + k0, lda, 0, Bk, ldb, 0,
+                                1.0, B + (int64_t)k1 * ldb, ldb, 0, 1, 0, 0, s));
+        }
+        return done ? done(r0, r0 + n) : hipSuccess;
+    }
+    const int n1 = max(64, n / 2 / 64 * 64), n2 = n - n1;
+    RI_TRY(trsm_rec(L, n1, lda, Dinv, B, ncols, ldb, s, r0, done));
+    RI_TRY(gemm_f64(false, false, n2, ncols, n1, -1.0, L + (int64_t)n1 * lda, lda, 0, B, ldb, 0, 1.0,
+                    B + (int64_t)n1 * ldb, ldb, 0, 1, 0, 0, s));
+    return trsm_rec(L + (int64_t)n1 * lda + n1, n2, lda, Dinv + (int64_t)(n1 / 64) * 4096, B + (int64_t)n1 * ldb,
+                    ncols, ldb, s, r0 + n1, done);
 }
 
 hipError_t trsm_lower_inplace(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols,

@@ -2,7 +2,14 @@
 #pragma once
 #include "common.h"
 
+#include <functional>
+
 namespace ri {
+
+// Recursive in-place B <- L^{-1} B (see gemm.hip); done(r0, r1) runs in stream
+// order once rows r0 .. r1 of B are final (r0 offsets the row numbers).
+hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols, int64_t ldb,
+                    hipStream_t s, int r0, const std::function<hipError_t(int, int)>& done);
 
 // ---- integrals
 hipError_t screen_pairs(const ri_system* s, double tau, int32_t* counts, int64_t* offsets, hipStream_t st);
@@ -71,12 +78,27 @@ int red_elems(int N);
 hipError_t diis_dots(const double* const* es, int m, const double* enew, double* row, int64_t n, double* red,
                      hipStream_t st);
 hipError_t diis_solve(const double* Bmat, int m, int ld, double* coef, hipStream_t st);
+// DIIS inner products into the slot-indexed 8 x 8 matrix Bfull, and the m x m
+// matrix of slots[0..m) gathered into Bm (ld 8); no host round trip.
+hipError_t diis_prep(double* Bfull, const double* row, const int* slots, int m, int snew, double* Bm,
+                     hipStream_t st);
 hipError_t diis_combine(const double* const* Fs, const double* coef, int m, double* out, int64_t n, hipStream_t st);
 hipError_t gershgorin(const double* F, int N, double* bounds, double* red, hipStream_t st);
 hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st);
 hipError_t traces(const double* X, const double* X2, int N, double* tr, hipStream_t st);
 hipError_t tc2_update(double* X, const double* X2, const double* tr, int n_occ, int64_t n, hipStream_t st);
 hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st);
+// ---- purification, one launch per step (tc2.hip).  part: 2 * tc2f_tiles(N)
+// doubles per parity; state: 8 ints per parity ([0] countdown, [1] done,
+// [2] steps run, [3] 1 if the latest X is in the step's output buffer).
+// Step k reads parity k % 2 and writes parity (k + 1) % 2; out_id says which
+// buffer the step writes (1: Y).
+int tc2f_tiles(int N);
+hipError_t tc2f_init(const double* F, const double* bounds, int N, double* X, double* part, int* state,
+                     hipStream_t st);
+hipError_t tc2f_step(const double* X, double* Y, int N, int n_occ, const double* part_in, double* part_out,
+                     const int* st_in, int* st_out, int out_id, hipStream_t st);
+hipError_t tc2f_final(double* X, const double* Y, int N, const int* state, hipStream_t st);
 hipError_t energy_terms(const double* D, const double* h, const double* J, const double* K, int64_t n,
                         const double* enuc, double* out, double* red, hipStream_t st);
 }  // namespace ri

@@ -100,6 +100,23 @@ __global__ void diis_solve_kernel(const double* Bm, int m, int ld, double* coef)
     for (int i = 0; i < m; ++i) coef[i] = x[i];
 }
 
+// DIIS matrix on the device.  row[k] = <e_{slot k}, e_new> for the slots in
+// order (the new one last) goes into row and column `snew` of the
+// slot-indexed 8 x 8 matrix Bfull; then the m x m matrix of the slots in order
+// is gathered into Bm (ld 8) for the solve.  The slot order is host
+// bookkeeping that depends on the iteration count only.
+struct Slots { int s[8]; };
+__global__ void diis_prep_kernel(double* Bfull, const double* row, Slots sl, int m, int snew, double* Bm) {
+    if (threadIdx.x == 0)
+        for (int k = 0; k < m; ++k) {
+            Bfull[snew * 8 + sl.s[k]] = row[k];
+            Bfull[sl.s[k] * 8 + snew] = row[k];
+        }
+    __syncthreads();
+    const int i = threadIdx.x >> 3, j = threadIdx.x & 7;
+    if (threadIdx.x < 64 && i < m && j < m) Bm[i * 8 + j] = Bfull[sl.s[i] * 8 + sl.s[j]];
+}
+
 __global__ void combine_kernel(Ptrs Fs, const double* coef, int m, double* out, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -246,6 +263,14 @@ hipError_t diis_dots(const double* const* es, int m, const double* enew, double*
     multi_dot_part_kernel<<<RED_BLOCKS, 256, 0, st>>>(p, enew, m, n, red);
     RI_TRY(hipGetLastError());
     multi_dot_final_kernel<<<1, 256, 0, st>>>(red, m, row);
+    return hipGetLastError();
+}
+hipError_t diis_prep(double* Bfull, const double* row, const int* slots, int m, int snew, double* Bm,
+                     hipStream_t st) {
+    if (m < 1 || m > 8) return hipErrorInvalidValue;
+    Slots sl{};
+    for (int k = 0; k < m; ++k) sl.s[k] = slots[k];
+    diis_prep_kernel<<<1, 64, 0, st>>>(Bfull, row, sl, m, snew, Bm);
     return hipGetLastError();
 }
 hipError_t diis_solve(const double* Bmat, int m, int ld, double* coef, hipStream_t st) {

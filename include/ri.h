@@ -254,8 +254,8 @@ typedef struct {
     int32_t max_purify;    /* step limit of each trace-correcting purification */
                            /* (0: the default, 200 for ri_energy; for         */
                            /* ri_energy_batched, whose launch sequence is     */
-                           /* fixed, 96 at the core-Hamiltonian start and 64  */
-                           /* in each iteration);                             */
+                           /* fixed, 128 at the core-Hamiltonian start and in */
+                           /* each iteration);                                */
                            /* a purification whose |tr X - tr X^2| has not    */
                            /* fallen below 1e-11 n_occ by then fails          */
 } ri_scf_opts;
@@ -396,6 +396,30 @@ int32_t ri_density_from_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, 
 /* ri_density_to_pairs - d[q] = (float) D[mu][nu] for each listed pair q. */
 int32_t ri_density_to_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d,
                             hipStream_t stream);
+
+/* Start along a geometry sequence from the previous geometry's converged
+ * density D' plus a predicted change (the network trained on the change
+ * between consecutive geometries of the sequence).
+ * ri_pair_delta_features - features of each listed pair for that change,
+ * between the previous positions xyz_prev (device [n_centres][3]; the basis
+ * is sys's) and sys->xyz, with f4, c_X and f7 as for ri_pair_features:
+ *   g0 = D'[mu][nu], g1 = change of |A - B|, g2 = change of f4,
+ *   g3 = ln max(a,b), g4 = ln min(a,b), g5 = [A == B],
+ *   g6 = change of c_A + c_B, g7 = change of f7.
+ *   D_prev [N][N] device FP64; feat [n_pairs][RI_MLP_NFEAT] FP32 (out). */
+int32_t ri_pair_delta_features(const ri_system* sys, const double* xyz_prev, const int32_t* pairs, int64_t n_pairs,
+                               const double* D_prev, float* feat, hipStream_t stream);
+
+/* ri_density_change_pairs - d[q] = scale (D_new - D_prev)[mu][nu] for each
+ * listed pair q (training targets of the change). */
+int32_t ri_density_change_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const double* D_new,
+                                const double* D_prev, float scale, float* d, hipStream_t stream);
+
+/* ri_density_add_pairs - D_out = D_prev, except D_out[mu][nu] = D_out[nu][mu]
+ * = D_prev[mu][nu] + scale d[q] on each listed pair q (the start density).
+ * D_out must not alias D_prev. */
+int32_t ri_density_add_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const float* d, double scale,
+                             const double* D_prev, double* D_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Batched SCF (project extension): many independent molecules advance through

@@ -12,12 +12,21 @@ Pair features of (mu, nu), A, B their centres, a = fn_exp[mu], b = fn_exp[nu]:
   f4 = exp(-(ab/(a+b)) |A-B|^2)
   f5 = max(c_A, c_B), f6 = min(c_A, c_B), c_X = sum_{C != X} exp(-|R_X - R_C|^2 / 8)
   f7 = sum_C exp(-|P - R_C|^2 / 4),  P = (aA + bB)/(a + b)
+Change features of (mu, nu) between a previous geometry R' (converged
+density D') and a new one R, same basis and pair list (start along a
+geometry sequence: D' plus the predicted change):
+  g0 = D'[mu][nu],  g1 = f0(R) - f0(R'),  g2 = f4(R) - f4(R'),
+  g3 = f1, g4 = f2, g5 = f3,
+  g6 = (c_A + c_B)(R) - (c_A + c_B)(R'),  g7 = f7(R) - f7(R')
 Network: x = (f - mu) / sigma;  h1 = silu(x W1 + b1);  h2 = silu(h1 W2 + b2);
   y = h2 w3 + b3,  silu(z) = z / (1 + exp(-z)).  Loss: mean (y - t)^2.
 Adam: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
   p -= lr * (m / (1 - b1^k)) / (sqrt(v / (1 - b2^k)) + eps).
 Pins: finite differences of the loss (tests/test_oracle_mlp.py), a one-step
-Adam closed form, and feature symmetry / special values.
+Adam closed form, feature symmetry / special values, and for the change
+features the unchanged geometry (all changes zero), a rigid translation of
+both geometries (features unchanged) and the distance change of a known
+displacement.
 """
 from __future__ import annotations
 
@@ -49,6 +58,22 @@ def pair_features(sys, mu, nu):
     f[:, 6] = np.minimum(cA, cB)
     f[:, 7] = np.exp(-((P[:, None, :] - R[None, :, :]) ** 2).sum(-1) / 4.0).sum(1)
     return f
+
+
+def delta_features(sys, xyz_prev, mu, nu, D_prev):
+    """Change features of each pair between geometry xyz_prev and sys.xyz."""
+    new = pair_features(sys, mu, nu)
+    old = pair_features(sys.with_xyz(xyz_prev), mu, nu)
+    g = np.empty((mu.size, NFEAT))
+    g[:, 0] = D_prev[mu, nu]
+    g[:, 1] = new[:, 0] - old[:, 0]
+    g[:, 2] = new[:, 4] - old[:, 4]
+    g[:, 3] = new[:, 1]
+    g[:, 4] = new[:, 2]
+    g[:, 5] = new[:, 3]
+    g[:, 6] = (new[:, 5] + new[:, 6]) - (old[:, 5] + old[:, 6])
+    g[:, 7] = new[:, 7] - old[:, 7]
+    return g
 
 
 def silu(z):

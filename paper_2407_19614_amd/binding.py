@@ -114,6 +114,12 @@ _SIGS = {
                                     c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_density_to_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "ri_density_from_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "ri_pair_delta_features": (c_int32, [POINTER(RISystem), c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                         c_void_p]),
+    "ri_density_change_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_void_p, ctypes.c_float, c_void_p,
+                                          c_void_p]),
+    "ri_density_add_pairs": (c_int32, [c_int32, c_void_p, c_int64, c_void_p, c_double, c_void_p, c_void_p,
+                                       c_void_p]),
     "ri_energy_batched_workspace": (c_size_t, [c_int32, c_void_p, c_void_p, c_int32]),
     "ri_batch_autotune": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "ri_energy_batched": (c_int32, [c_int32, c_void_p, c_void_p, c_int32, POINTER(SCFOpts), c_int32, c_void_p,
@@ -330,6 +336,31 @@ class RIProblem:
         _check(lib().ri_density_to_pairs(self.N, _ptr(self.pairs), self.n_pairs, _ptr(D.contiguous()), _ptr(d),
                                          self.stream()), "ri_density_to_pairs")
         return d[: self.n_pairs]
+
+    def pair_delta_features(self, xyz_prev, D_prev):
+        """Features of this problem's pairs for the density change from the
+        previous geometry (positions xyz_prev, converged density D_prev)."""
+        torch = self.torch
+        f = torch.empty((max(self.n_pairs, 1), NFEAT), dtype=torch.float32, device=self.device)
+        _check(lib().ri_pair_delta_features(ctypes.byref(self.c_sys), _ptr(xyz_prev.contiguous()), _ptr(self.pairs),
+                                            self.n_pairs, _ptr(D_prev.contiguous()), _ptr(f), self.stream()),
+               "ri_pair_delta_features")
+        return f[: self.n_pairs]
+
+    def density_change_pairs(self, D_new, D_prev, scale):
+        torch = self.torch
+        d = torch.empty(max(self.n_pairs, 1), dtype=torch.float32, device=self.device)
+        _check(lib().ri_density_change_pairs(self.N, _ptr(self.pairs), self.n_pairs, _ptr(D_new.contiguous()),
+                                             _ptr(D_prev.contiguous()), float(scale), _ptr(d), self.stream()),
+               "ri_density_change_pairs")
+        return d[: self.n_pairs]
+
+    def density_add_pairs(self, d, scale, D_prev):
+        torch = self.torch
+        D = torch.empty((self.N, self.N), dtype=torch.float64, device=self.device)
+        _check(lib().ri_density_add_pairs(self.N, _ptr(self.pairs), self.n_pairs, _ptr(d.contiguous()), float(scale),
+                                          _ptr(D_prev.contiguous()), _ptr(D), self.stream()), "ri_density_add_pairs")
+        return D
 
     def density_from_pairs(self, d):
         torch = self.torch

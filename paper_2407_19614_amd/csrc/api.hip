@@ -508,8 +508,10 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
     // L^{-1}, and the packing of each block of B rows once the triangular solve
     // has finished them, run on the side stream beside the solve: the solve is
     // bound by MFMA throughput, the packing by memory bandwidth.
+    // (Small problems keep one stream: many callers' setups, as the batched
+    // workload's, would otherwise share the one side stream.)
     Fork fk;
-    const bool side = fk.open(st);
+    const bool side = (int64_t)na * n_pairs >= ri::GJ_SIDE_MIN && fk.open(st);
     hipStream_t ss = side ? fk.side : st;
     HIPC(ri::tri_inverse(L, na, na, w.dinv, Linv, na, ss));
     if (B) HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
@@ -870,6 +872,28 @@ int32_t ri_density_to_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, co
                             hipStream_t st) {
     if (N <= 0 || n_pairs < 0 || !D || (n_pairs > 0 && (!pairs || !d))) return RI_E_ARG;
     HIPC(ri::gather_density(N, pairs, n_pairs, D, d, st));
+    return RI_OK;
+}
+
+int32_t ri_pair_delta_features(const ri_system* sys, const double* xyz_prev, const int32_t* pairs, int64_t n_pairs,
+                               const double* D_prev, float* feat, hipStream_t st) {
+    if (!valid_sys(sys) || !xyz_prev || !D_prev || n_pairs < 0 || (n_pairs > 0 && (!pairs || !feat))) return RI_E_ARG;
+    HIPC(ri::pair_delta_features(sys, xyz_prev, pairs, n_pairs, D_prev, feat, st));
+    return RI_OK;
+}
+
+int32_t ri_density_change_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const double* D_new,
+                                const double* D_prev, float scale, float* d, hipStream_t st) {
+    if (N <= 0 || n_pairs < 0 || !D_new || !D_prev || (n_pairs > 0 && (!pairs || !d))) return RI_E_ARG;
+    HIPC(ri::density_change(N, pairs, n_pairs, D_new, D_prev, scale, d, st));
+    return RI_OK;
+}
+
+int32_t ri_density_add_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, const float* d, double scale,
+                             const double* D_prev, double* D_out, hipStream_t st) {
+    if (N <= 0 || n_pairs < 0 || !D_prev || !D_out || D_prev == D_out || (n_pairs > 0 && (!pairs || !d)))
+        return RI_E_ARG;
+    HIPC(ri::density_add(N, pairs, n_pairs, d, scale, D_prev, D_out, st));
     return RI_OK;
 }
 

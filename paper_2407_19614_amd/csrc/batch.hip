@@ -393,9 +393,10 @@ struct Plan {
     // grow with log(spectral width / gap): converged Fock matrices of the
     // 10-60-centre molecules need 27-30, their core Hamiltonians 34-67, and a
     // DIIS-extrapolated Fock matrix of an early iteration can have a smaller
-    // gap still.  Molecules whose purification has finished skip the
-    // remaining steps of the sequence at once.
-    int n_mol = 0, prec = 0, tc2_iters = 64, tc2_start = 96;
+    // gap still (3 of the 256 molecules of the batched workload need more
+    // than 64 steps there).  Molecules whose purification has finished skip
+    // the remaining steps of the sequence at once.
+    int n_mol = 0, prec = 0, tc2_iters = 128, tc2_start = 128;
     bool fin = false;                                     // FP64 exchange once after the FP32 SCF
     MolDesc* d = nullptr;
     Table n2, n2s, rows, pairs, aux, syrk, tail, cq, x[33];   // x[xs], xs = 4 * tiles + quads

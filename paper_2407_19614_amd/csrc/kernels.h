@@ -135,6 +135,12 @@ hipError_t mlp_train_step(const ri_mlp* net, float* m, float* v, int step, float
                           const float* target, int64_t n, float* loss, const MlpWS& w, hipStream_t st);
 hipError_t gather_density(int N, const int32_t* pairs, int64_t n_pairs, const double* D, float* d, hipStream_t st);
 hipError_t scatter_density(int N, const int32_t* pairs, int64_t n_pairs, const float* d, double* D, hipStream_t st);
+hipError_t pair_delta_features(const ri_system* s, const double* xyz_prev, const int32_t* pairs, int64_t n_pairs,
+                               const double* D_prev, float* feat, hipStream_t st);
+hipError_t density_change(int N, const int32_t* pairs, int64_t n_pairs, const double* Dn, const double* Dp,
+                          float scale, float* d, hipStream_t st);
+hipError_t density_add(int N, const int32_t* pairs, int64_t n_pairs, const float* d, double scale, const double* Dp,
+                       double* Dout, hipStream_t st);
 }  // namespace ri
 
 namespace ri {

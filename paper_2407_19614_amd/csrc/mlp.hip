@@ -285,6 +285,78 @@ __global__ void gather_density_kernel(const int32_t* pairs, int64_t n_pairs, con
     d[q] = (float)D[(int64_t)pairs[2 * q] * N + pairs[2 * q + 1]];
 }
 
+// Distance^2 of the pair's centres, the coordination sum c_A + c_B and the
+// Gaussian-product-centre density (f7 above) of one geometry.
+__device__ __forceinline__ void pair_geometry(const double* xyz, int nc, int ca, int cb, double a, double b,
+                                              double& r2, double& csum, double& md) {
+    const double* A = xyz + 3 * ca;
+    const double* B = xyz + 3 * cb;
+    const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+    r2 = dx * dx + dy * dy + dz * dz;
+    const double Px = (a * A[0] + b * B[0]) / (a + b), Py = (a * A[1] + b * B[1]) / (a + b),
+                 Pz = (a * A[2] + b * B[2]) / (a + b);
+    double cA = 0.0, cB = 0.0, m = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        const double* C = xyz + 3 * c;
+        const double ax = A[0] - C[0], ay = A[1] - C[1], az = A[2] - C[2];
+        const double bx = B[0] - C[0], by = B[1] - C[1], bz = B[2] - C[2];
+        const double px = Px - C[0], py = Py - C[1], pz = Pz - C[2];
+        if (c != ca) cA += exp(-(ax * ax + ay * ay + az * az) / 8.0);
+        if (c != cb) cB += exp(-(bx * bx + by * by + bz * bz) / 8.0);
+        m += exp(-(px * px + py * py + pz * pz) / 4.0);
+    }
+    csum = cA + cB;
+    md = m;
+}
+
+// Features of a pair for the density change between the previous geometry
+// (xyz0, converged density Dp) and the new one (xyz): g0 = Dp[mu][nu],
+// g1 = change of |A - B|, g2 = change of exp(-(ab/(a+b))|A-B|^2), g3/g4 =
+// ln max/min(a, b), g5 = same centre, g6 = change of c_A + c_B, g7 = change of
+// the product-centre density.
+__global__ void delta_features_kernel(const double* xyz, const double* xyz0, int nc, const int32_t* fc,
+                                      const double* fe, const int32_t* pairs, int64_t n_pairs, const double* Dp,
+                                      int N, float* feat) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    const int mu = pairs[2 * q], nu = pairs[2 * q + 1];
+    const int ca = fc[mu], cb = fc[nu];
+    const double a = fe[mu], b = fe[nu], e = a * b / (a + b);
+    double r2, cs, md, r20, cs0, md0;
+    pair_geometry(xyz, nc, ca, cb, a, b, r2, cs, md);
+    pair_geometry(xyz0, nc, ca, cb, a, b, r20, cs0, md0);
+    float* f = feat + q * NF;
+    f[0] = (float)Dp[(int64_t)mu * N + nu];
+    f[1] = (float)(sqrt(r2) - sqrt(r20));
+    f[2] = (float)(exp(-e * r2) - exp(-e * r20));
+    f[3] = (float)log(fmax(a, b));
+    f[4] = (float)log(fmin(a, b));
+    f[5] = ca == cb ? 1.0f : 0.0f;
+    f[6] = (float)(cs - cs0);
+    f[7] = (float)(md - md0);
+}
+
+// d[q] = scale (Dn - Dp)[mu][nu] on the listed pairs
+__global__ void density_change_kernel(const int32_t* pairs, int64_t n_pairs, const double* Dn, const double* Dp,
+                                      int N, float scale, float* d) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    const int64_t i = (int64_t)pairs[2 * q] * N + pairs[2 * q + 1];
+    d[q] = (float)((double)scale * (Dn[i] - Dp[i]));
+}
+
+// Dout[mu][nu] = Dout[nu][mu] = Dp[mu][nu] + scale d[q] on the listed pairs
+// (Dout holds a copy of Dp elsewhere)
+__global__ void density_add_kernel(const int32_t* pairs, int64_t n_pairs, const float* d, double scale,
+                                   const double* Dp, int N, double* Dout) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n_pairs) return;
+    const int mu = pairs[2 * q], nu = pairs[2 * q + 1];
+    const double v = Dp[(int64_t)mu * N + nu] + scale * (double)d[q];
+    Dout[(int64_t)mu * N + nu] = v;
+    Dout[(int64_t)nu * N + mu] = v;
+}
+
 inline unsigned g1(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 template <bool TA, bool TB>
@@ -391,6 +463,29 @@ hipError_t scatter_density(int N, const int32_t* pairs, int64_t n_pairs, const f
     RI_TRY(fill(D, 0.0, (int64_t)N * N, st));
     if (n_pairs == 0) return hipSuccess;
     scatter_density_kernel<<<g1(n_pairs), 256, 0, st>>>(pairs, n_pairs, d, N, D);
+    return hipGetLastError();
+}
+
+hipError_t pair_delta_features(const ri_system* s, const double* xyz_prev, const int32_t* pairs, int64_t n_pairs,
+                               const double* D_prev, float* feat, hipStream_t st) {
+    if (n_pairs == 0) return hipSuccess;
+    delta_features_kernel<<<g1(n_pairs), 256, 0, st>>>(s->xyz, xyz_prev, s->n_centres, s->fn_centre, s->fn_exp,
+                                                        pairs, n_pairs, D_prev, s->n_fn, feat);
+    return hipGetLastError();
+}
+
+hipError_t density_change(int N, const int32_t* pairs, int64_t n_pairs, const double* Dn, const double* Dp,
+                          float scale, float* d, hipStream_t st) {
+    if (n_pairs == 0) return hipSuccess;
+    density_change_kernel<<<g1(n_pairs), 256, 0, st>>>(pairs, n_pairs, Dn, Dp, N, scale, d);
+    return hipGetLastError();
+}
+
+hipError_t density_add(int N, const int32_t* pairs, int64_t n_pairs, const float* d, double scale, const double* Dp,
+                       double* Dout, hipStream_t st) {
+    RI_TRY(copy(Dout, Dp, (int64_t)N * N, st));
+    if (n_pairs == 0) return hipSuccess;
+    density_add_kernel<<<g1(n_pairs), 256, 0, st>>>(pairs, n_pairs, d, scale, Dp, N, Dout);
     return hipGetLastError();
 }
 

@@ -35,6 +35,32 @@ def test_pair_features(setup):
     assert err.max() < 2e-6, err.max()
 
 
+def test_delta_features_and_density_change(setup):
+    """Change features between two geometries of the walk against the oracle,
+    and the change targets / start density against their definitions."""
+    s, pr, *_ = setup
+    print("case: n400 change features", flush=True)
+    xyz0 = synth.random_walk(s.xyz, 1, 0.05, 2.0, seed=11)[1]
+    rng = np.random.default_rng(4)
+    Dp = rng.standard_normal((s.N, s.N))
+    Dp = Dp + Dp.T
+    mu, nu = to_np(pr.pairs)[: pr.n_pairs].T.astype(np.int64)
+    g = to_np(pr.pair_delta_features(torch.tensor(xyz0, device="cuda"), torch.tensor(Dp, device="cuda")))
+    g_ref = M.delta_features(s, xyz0, mu, nu, Dp)
+    scale = np.maximum(np.abs(g_ref), 1e-3 * np.abs(g_ref).max(0))
+    err = (np.abs(g - g_ref) / scale).max()
+    print(f"max scaled |dg| = {err:.2e}", flush=True)
+    assert err < 2e-6
+    Dn = Dp + 1e-3 * rng.standard_normal((s.N, s.N))
+    d = to_np(pr.density_change_pairs(torch.tensor(Dn, device="cuda"), torch.tensor(Dp, device="cuda"), 100.0))
+    assert np.allclose(d, (100.0 * (Dn - Dp)[mu, nu]).astype(np.float32), rtol=1e-6, atol=1e-7)
+    Dout = to_np(pr.density_add_pairs(torch.tensor(d, device="cuda"), 0.01, torch.tensor(Dp, device="cuda")))
+    ref = Dp.copy()
+    ref[mu, nu] = Dp[mu, nu] + 0.01 * d.astype(np.float64)
+    ref[nu, mu] = ref[mu, nu]
+    assert np.allclose(Dout, ref, rtol=1e-15, atol=1e-15)
+
+
 def test_forward_fp32_bf16(setup):
     s, pr, f_ref, fm, fs, p = setup
     import paper_2407_19614_amd as P

@@ -63,3 +63,30 @@ def test_feature_special_values():
     m1, n1 = R.screen_pairs(s1)
     f1 = M.pair_features(s1, m1, n1)
     assert np.allclose(f1[:, 5], 0) and np.allclose(f1[:, 7], 1)
+
+
+def test_delta_features_pins():
+    """Change features: zero changes for an unchanged geometry; invariant under
+    a rigid translation of both geometries; g1 equals the distance change of a
+    known displacement of one centre; g0 reads D' at (mu, nu)."""
+    s = synth.config_system("tiny")
+    mu, nu = R.screen_pairs(s)
+    rng = np.random.default_rng(3)
+    Dp = rng.standard_normal((s.N, s.N))
+    g = M.delta_features(s, s.xyz, mu, nu, Dp)
+    assert np.all(g[:, [1, 2, 6, 7]] == 0.0)
+    assert np.array_equal(g[:, 0], Dp[mu, nu])
+    f = M.pair_features(s, mu, nu)
+    assert np.array_equal(g[:, 3:6], f[:, 1:4])
+    moved = s.xyz.copy()
+    moved[2] += np.array([0.3, -0.1, 0.2])
+    g1 = M.delta_features(s.with_xyz(moved), s.xyz, mu, nu, Dp)
+    t = np.array([1.5, -2.0, 0.7])
+    g2 = M.delta_features(s.with_xyz(moved + t), s.xyz + t, mu, nu, Dp)
+    assert np.allclose(g1, g2, rtol=1e-12, atol=1e-12)
+    A, B = s.fn_centre[mu], s.fn_centre[nu]
+    d_new = np.linalg.norm(moved[A] - moved[B], axis=1)
+    d_old = np.linalg.norm(s.xyz[A] - s.xyz[B], axis=1)
+    assert np.allclose(g1[:, 1], d_new - d_old, atol=1e-14)
+    untouched = (A != 2) & (B != 2)
+    assert np.all(g1[untouched, 1] == 0.0) and np.all(g1[untouched, 2] == 0.0)

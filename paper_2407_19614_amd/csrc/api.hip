@@ -343,8 +343,9 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
 int32_t occupied_space(const double* Fx, int N, int n_occ, EnergyWS& w, bool have_prev, double* C_out,
                        int max_it, int& pred, hipStream_t st) {
     const int64_t n2 = (int64_t)N * N;
-    HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.LinvS, N, 0, Fx, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
-    HIPC(ri::gemm_f64(false, true, N, N, N, 1.0, w.T1, N, 0, w.LinvS, N, 0, 0.0, w.T2, N, 0, 1, 0, 0, st));
+    // L_S^{-1} F L_S^{-T}, skipping the zero triangle of L_S^{-1} in both products
+    HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, w.LinvS, N, 0, Fx, N, 0, 0.0, w.T1, N, 0, 1, 1, 0, st));
+    HIPC(ri::gemm_f64(false, true, N, N, N, 1.0, w.T1, N, 0, w.LinvS, N, 0, 0.0, w.T2, N, 0, 1, 3, 0, st));
     HIPC(ri::gershgorin(w.T2, N, w.scal + 16, w.red, st));
     const int tiles = ri::tc2f_tiles(N);
     HIPC(ri::tc2f_init(w.T2, w.scal + 16, N, w.X, w.tpart, w.tst, st));

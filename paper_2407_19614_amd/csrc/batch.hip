@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void gersh_b(const MolDesc* d, int n_mol) {
 }
 
 // tr X and tr X^2 of a purification step, and when to stop: once
-// |tr X - tr X^2| < 1e-11 n_occ, this step's update and three more run (the
+// |tr X - tr X^2| < 1e-11 n_occ, this step's update and one more run (the
 // rule of the single-molecule path); later steps of the fixed launch
 // sequence find ST_TC2 clear and exit at once.
 __global__ __launch_bounds__(256) void traces_b(const MolDesc* d, int n_mol) {
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void traces_b(const MolDesc* d, int n_mol) {
         m.state[ST_TC2U] = 1;
         int x = m.state[ST_TC2X];
         if (x < 0) {
-            if (fabs(a - b) < 1e-11 * (double)max(1, m.n_occ)) x = 3;
+            if (fabs(a - b) < 1e-11 * (double)max(1, m.n_occ)) x = 1;
         } else if (x > 0) {
             --x;
         }

@@ -148,7 +148,8 @@ __device__ __forceinline__ void chol_inv64_wave(double (*S)[65], int nb, Bad bad
 namespace ri {
 
 // GEMM C = alpha op(A) op(B) + beta C over a batch (row-major, FP64 MFMA).
-// tri: 0 general; 1 op(A) lower triangular; 2 op(A) upper triangular.
+// tri: 0 general; 1 op(A) lower triangular; 2 op(A) upper triangular;
+// 3 op(B) upper triangular.
 // lowerC: skip 64x64 tiles of C strictly above the diagonal.
 hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, int64_t lda, int64_t sA,

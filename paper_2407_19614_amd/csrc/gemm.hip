@@ -26,6 +26,7 @@ __device__ __forceinline__ void gemm_tile64(int M, int N, int K, double alpha, c
     int kbeg = 0, kend = K;
     if (tri == 1) kend = min(K, m0 + BM);
     if (tri == 2) kbeg = (m0 / BK) * BK;
+    if (tri == 3) kend = min(K, n0 + BN);
 
     double ra[4], rb[4];
     auto load = [&](int k0) {
@@ -142,6 +143,7 @@ __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, 
     int kbeg = 0, kend = K;
     if (tri == 1) kend = min(K, m0 + TM);
     if (tri == 2) kbeg = (m0 / BK) * BK;
+    if (tri == 3) kend = min(K, n0 + TM);
     double ra[R], rb[R];
     // thread tid covers (k-major) k = tid % BK, m = tid / BK + (256 / BK) r, or
     // (m-major) m = tid % 128, k = tid / 128 + 2 r

@@ -10,9 +10,12 @@
 // output Y, and every workgroup of the next step sums those partials in one
 // fixed order, so all of them take the same branch and the same stopping
 // decision.  The stopping rule is the one the batched SCF uses: once
-// |tr X - tr X^2| < 1e-11 n_occ, this step and three more run, and later
-// steps exit at once, so the host can launch steps in chunks and read the
-// state once per chunk instead of once every few steps.
+// |tr X - tr X^2| < 1e-11 n_occ, this step and one more run, and later steps
+// exit at once, so the host can launch steps in chunks and read the state
+// once per chunk instead of once every few steps.  (Near convergence a step
+// squares the eigenvalues' distance to 0 or 1 on one side and at most
+// doubles it on the other, so the two steps take a summed distance of
+// 1e-11 n_occ down to rounding.)
 //
 // Layout of a step: 64 x 64 output tiles, one workgroup of 8 waves each.
 // Waves 0-3 and 4-7 take the two halves of the reduction index (split-K
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict
     const double t2 = wg_sum_fixed<512>(b, sh);
     int cd = st_in[S_CD];
     if (cd < 0) {
-        if (fabs(t1 - t2) < 1e-11 * (double)max(1, n_occ)) cd = 3;
+        if (fabs(t1 - t2) < 1e-11 * (double)max(1, n_occ)) cd = 1;
     } else if (cd > 0) {
         --cd;
     }
@@ -118,26 +121,27 @@ __global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict
     const int Kh = min(N, ((N + 1) / 2 + SK - 1) / SK * SK);
     const int kb = half ? Kh : 0, ke = half ? N : Kh;
     const int nsl = (max(Kh, N - Kh) + SK - 1) / SK;   // the same count in both halves
-    // loader lanes: 256 per half, row lrow of the panel, 4 consecutive k
-    const int gt = tid & 255, lrow = gt >> 2, lkq = 4 * (gt & 3);
-    const bool aok = m0 + lrow < N, bok = n0 + lrow < N;
-    const double* Ar = X + (int64_t)min(m0 + lrow, N - 1) * N;
-    const double* Br = X + (int64_t)min(n0 + lrow, N - 1) * N;
-    double ra[4], rb[4];
+    // loader lanes: 256 per half; element gt + 256 i of the 64 x SK slice is
+    // row (gt + 256 i) / SK, k = gt % SK, so SK consecutive lanes read one
+    // row's SK consecutive doubles (whole cache lines per instruction)
+    constexpr int KQ = SK / 4, RS = 256 / SK;
+    const int gt = tid & 255, lk0 = gt % SK, lr0 = gt / SK;
+    double ra[KQ], rb[KQ];
     auto load = [&](int s) {
-        const int k = kb + s * SK + lkq;
+        const int k = kb + s * SK + lk0;
+        const bool kin = k < ke;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const bool kin = k + i < ke;
-            ra[i] = (aok && kin) ? Ar[k + i] : 0.0;
-            rb[i] = (bok && kin) ? Br[k + i] : 0.0;
+        for (int i = 0; i < KQ; ++i) {
+            const int r = lr0 + RS * i;
+            ra[i] = (kin && m0 + r < N) ? X[(int64_t)(m0 + r) * N + k] : 0.0;
+            rb[i] = (kin && n0 + r < N) ? X[(int64_t)(n0 + r) * N + k] : 0.0;
         }
     };
     auto store = [&](int stg) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            As[half][stg][lkq + i][lrow] = ra[i];
-            Bs[half][stg][lkq + i][lrow] = rb[i];
+        for (int i = 0; i < KQ; ++i) {
+            As[half][stg][lk0][lr0 + RS * i] = ra[i];
+            Bs[half][stg][lk0][lr0 + RS * i] = rb[i];
         }
     };
     d4_t acc[2][2];

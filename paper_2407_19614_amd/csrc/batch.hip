@@ -98,7 +98,10 @@ __global__ void tc2_init_b(const MolDesc* d, const int* prefix, int n_mol) {
     if (e >= (int64_t)m.N * m.N) return;
     int r = e / m.N, c = e % m.N;
     const double lo = m.scal[SC_BOUNDS], hi = m.scal[SC_BOUNDS + 1];
-    m.X[e] = ((r == c ? hi : 0.0) - m.T2[e]) / (hi - lo);
+    // symmetrised, so that X and every square of it (formed on the upper tiles
+    // and mirrored) stay exactly symmetric
+    const double fs = 0.5 * (m.T2[e] + m.T2[(int64_t)c * m.N + r]);
+    m.X[e] = ((r == c ? hi : 0.0) - fs) / (hi - lo);
 }
 
 // Grid-stride over the molecule's N^2 elements with the blocks its prefix
@@ -525,6 +528,13 @@ struct HostPlan {
 
 int tune_bucket(int N, int n_buckets) { return std::min((N + 127) / 128, n_buckets) - 1; }
 
+// Tiles of an M x N product on tile x tile tiles (upper ones only for a
+// symmetric product).
+int gemm_tiles(int M, int N, int tile, bool sym) {
+    const int tm = (M + tile - 1) / tile, tn = (N + tile - 1) / tile;
+    return sym ? tn * (tn + 1) / 2 : tm * tn;
+}
+
 bool tuning_ok(const ri_batch_tuning* t) {
     if (!t) return true;
     if (t->n_buckets < 1 || t->n_buckets > RI_TUNE_BUCKETS) return false;
@@ -648,18 +658,19 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
         }
     // grouped GEMMs: member i of each
     // tunable: the member runs on the molecule's tuned tile (else on 64 x 64)
-    auto mkg = [&](Plan::G& g, bool ta, bool tb, bool tunable, auto fill, int act = ST_ACTIVE) {
+    auto mkg = [&](Plan::G& g, bool ta, bool tb, bool tunable, auto fill, int act = ST_ACTIVE, bool sym = false) {
         g.ta = ta;
         g.tb = tb;
         std::vector<ri::GemmDesc> v(n_mol);
         std::vector<int> c64(n_mol), c128(n_mol);
         for (int i = 0; i < n_mol; ++i) {
             fill(hp.mols[i], v[i]);
+            v[i].sym = sym;
             // runs while this flag is set (no pointer in the sizing pass, whose carver has no base)
             v[i].active = hp.mols[i].state ? hp.mols[i].state + act : nullptr;
             const bool big = tunable && hp.tile[i] == 128;
-            c64[i] = big ? 0 : ((v[i].M + 63) / 64) * ((v[i].N + 63) / 64);
-            c128[i] = big ? ((v[i].M + 127) / 128) * ((v[i].N + 127) / 128) : 0;
+            c64[i] = big ? 0 : gemm_tiles(v[i].M, v[i].N, 64, sym);
+            c128[i] = big ? gemm_tiles(v[i].M, v[i].N, 128, sym) : 0;
         }
         g.d = cv.take<ri::GemmDesc>(n_mol);
         hp.gs.push_back(&g);
@@ -670,17 +681,21 @@ static int32_t batch_layout(int32_t n_mol, const ri_system* sys, const ri_batch_
     auto set = [](ri::GemmDesc& g, int M, int N, int K, double al, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double* C, int64_t ldc, int tri) {
         g.M = M; g.N = N; g.K = K; g.tri = tri; g.alpha = al; g.beta = 0.0;
-        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.sym = 0;
     };
     mkg(p.g_lfx, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.LinvS, m.N, m.Fx, m.N, m.T1, m.N, 1); });
-    mkg(p.g_t2, false, true, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.LinvS, m.N, m.T2, m.N, 0); });
+    // L_S^{-1} Fx L_S^{-T} and 2 C C^T are symmetric: upper tiles only, mirrored
+    mkg(p.g_t2, false, true, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.LinvS, m.N, m.T2, m.N, 0); },
+        ST_ACTIVE, true);
+    // the purification square X X of a symmetric X: upper tiles only, mirrored
     mkg(p.g_x2, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.X, m.N, m.X, m.N, m.X2, m.N, 0); },
-        ST_TC2);
+        ST_TC2, true);
     mkg(p.g_y, false, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.X, m.N, m.Cp, m.n_occ, m.Y, m.n_occ, 0); });
     mkg(p.g_mo, true, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.n_occ, m.n_occ, m.N, 1.0, m.Y, m.n_occ, m.Y, m.n_occ, m.Mo, m.n_occ, 0); });
     mkg(p.g_cp, false, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.n_occ, 1.0, m.Y, m.n_occ, m.LinvM, 64, m.Cp, m.n_occ, 0); });
     mkg(p.g_c, true, false, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.n_occ, m.N, 1.0, m.LinvS, m.N, m.Cp, m.n_occ, m.C, m.n_occ, 2); });
-    mkg(p.g_d, false, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.n_occ, 2.0, m.C, m.n_occ, m.C, m.n_occ, m.D, m.N, 0); });
+    mkg(p.g_d, false, true, false, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.n_occ, 2.0, m.C, m.n_occ, m.C, m.n_occ, m.D, m.N, 0); },
+        ST_ACTIVE, true);
     mkg(p.g_fd, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.F, m.N, m.D, m.N, m.T1, m.N, 0); });
     mkg(p.g_fds, false, false, true, [&](MolDesc& m, ri::GemmDesc& g) { set(g, m.N, m.N, m.N, 1.0, m.T1, m.N, m.S, m.N, m.T2, m.N, 0); });
     p.d = cv.take<MolDesc>(n_mol);
@@ -772,7 +787,7 @@ int32_t autotune_impl(int32_t n_mol, const ri_system* sys, const ri_batch_mol* m
             std::vector<int> pre(n_mol + 1, 0);
             for (int i = 0; i < n_mol; ++i) {
                 const int M = hp.mols[i].N;
-                const int t = tile == 64 ? ((M + 63) / 64) * ((M + 63) / 64) : ((M + 127) / 128) * ((M + 127) / 128);
+                const int t = gemm_tiles(M, M, tile, true);
                 pre[i + 1] = pre[i] + (tune_bucket(M, RI_TUNE_BUCKETS) == b ? t : 0);
             }
             HIPR(hipMemcpyAsync(gx.t.prefix, pre.data(), sizeof(int) * (n_mol + 1), hipMemcpyHostToDevice, st));

@@ -17,7 +17,8 @@ constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 1;
 template <bool TA, bool TB>
 __device__ __forceinline__ void gemm_tile64(int M, int N, int K, double alpha, const double* __restrict__ A,
                                             int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
-                                            double* __restrict__ C, int64_t ldc, int tri, int m0, int n0) {
+                                            double* __restrict__ C, int64_t ldc, int tri, int m0, int n0,
+                                            bool sym = false) {
     __shared__ double As[BK][LDP];
     __shared__ double Bs[BK][LDP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -94,12 +95,24 @@ __device__ __forceinline__ void gemm_tile64(int M, int N, int K, double alpha, c
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
-                if (gm < M && gn < N) {
+                if (gm < M && gn < N && !(sym && gm > gn)) {
                     double* c = C + (int64_t)gm * ldc + gn;
                     double v = alpha * acc[i][j][r];
                     *c = (beta == 0.0) ? v : v + beta * *c;
+                    if (sym && gm != gn) C[(int64_t)gn * ldc + gm] = *c;
                 }
             }
+}
+
+// upper tile t (row-major over I <= J) of a t x t tiling
+__device__ __forceinline__ void upper_tile(int t, int nt, int& I, int& J) {
+    int i = 0, rem = t;
+    while (rem >= nt - i) {
+        rem -= nt - i;
+        ++i;
+    }
+    I = i;
+    J = i + rem;
 }
 
 template <bool TA, bool TB>
@@ -125,8 +138,10 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const ri::GemmDesc* d
     const ri::GemmDesc& p = d[g];
     if (p.active && !*p.active) return;
     const int tn = (p.N + BN - 1) / BN;
-    gemm_tile64<TA, TB>(p.M, p.N, p.K, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, p.tri,
-                        (loc / tn) * BM, (loc % tn) * BN);
+    int I = loc / tn, J = loc % tn;
+    if (p.sym) upper_tile(loc, tn, I, J);
+    gemm_tile64<TA, TB>(p.M, p.N, p.K, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, p.tri, I * BM, J * BN,
+                        p.sym != 0);
 }
 
 // 128 x 128 variant: 4 waves in 2 x 2, each owning 64 x 64 of C as 4 x 4 MFMA
@@ -134,7 +149,8 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(const ri::GemmDesc* d
 template <bool TA, bool TB, int BK = ::BK>
 __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, const double* __restrict__ A,
                                              int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
-                                             double* __restrict__ C, int64_t ldc, int tri, int m0, int n0) {
+                                             double* __restrict__ C, int64_t ldc, int tri, int m0, int n0,
+                                             bool sym = false) {
     constexpr int TM = 128, LD = TM + 1, R = BK / 2;   // R: elements of each operand per thread per slice
     __shared__ double As[BK][LD];
     __shared__ double Bs[BK][LD];
@@ -208,10 +224,11 @@ __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
-                if (gm < M && gn < N) {
+                if (gm < M && gn < N && !(sym && gm > gn)) {
                     double* c = C + (int64_t)gm * ldc + gn;
                     double v = alpha * acc[i][j][r];
                     *c = (beta == 0.0) ? v : v + beta * *c;
+                    if (sym && gm != gn) C[(int64_t)gn * ldc + gm] = *c;
                 }
             }
 }
@@ -240,8 +257,10 @@ __global__ __launch_bounds__(256, 2) void gemm_grouped128_kernel(const ri::GemmD
     const ri::GemmDesc& p = d[g];
     if (p.active && !*p.active) return;
     const int tn = (p.N + 127) / 128;
-    gemm_tile128<TA, TB>(p.M, p.N, p.K, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, p.tri,
-                         (loc / tn) * 128, (loc % tn) * 128);
+    int I = loc / tn, J = loc % tn;
+    if (p.sym) upper_tile(loc, tn, I, J);
+    gemm_tile128<TA, TB>(p.M, p.N, p.K, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, p.tri, I * 128, J * 128,
+                         p.sym != 0);
 }
 
 // Factor one 64x64 diagonal block in place (lower Cholesky) and write the

@@ -176,8 +176,13 @@ struct GemmDesc {
     double* C;
     int64_t lda, ldb, ldc;
     const int* active;
+    // sym: the product is symmetric (M == N): only the tiles on and above the
+    // diagonal run, in row-major order, and every entry is also written to its
+    // mirror position, so C comes out exactly symmetric
+    int sym;
 };
-// tile: 64 (64 x 64 tiles) or 128 (128 x 128 tiles); prefix counts tiles of that size.
+// tile: 64 (64 x 64 tiles) or 128 (128 x 128 tiles); prefix counts tiles of
+// that size (t (t + 1) / 2 for a symmetric product).
 hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s,
                         int tile = 64);
 

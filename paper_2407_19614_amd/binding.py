@@ -563,6 +563,35 @@ def prepare_batch(systems, prec=FP64, workers=4, device="cuda"):
     return out
 
 
+class PreparedBatch:
+    """prepare_batch running on a host thread of its own (its launches go to
+    the worker streams, so they overlap whatever the caller's stream runs,
+    e.g. the SCF of the previous batch).  result() waits for it and returns
+    the problems, recorded for use on the calling thread's current stream."""
+
+    def __init__(self, systems, prec=FP64, workers=4, device="cuda"):
+        import threading
+        self._out, self._err = None, None
+
+        def run():
+            try:
+                self._out = prepare_batch(systems, prec, workers, device)
+            except BaseException as e:     # re-raised by result()
+                self._err = e
+        self._thread = threading.Thread(target=run)
+        self._thread.start()
+
+    def result(self):
+        import torch
+        self._thread.join()
+        if self._err is not None:
+            raise self._err
+        cur = torch.cuda.current_stream()
+        for pr in self._out:
+            pr.record_stream(cur)
+        return self._out
+
+
 def batch_autotune(problems, prec=FP64):
     """Times the candidate launch shapes of the batched SCF on these problems
     (each after build_3c and metric_factor in `prec`) and returns the chosen

@@ -180,3 +180,30 @@ def test_prepare_batch_matches_sequential_setup():
     for s, r in zip(systems, res):
         ref = S.run_scf(s, R.RIData(s), tol_E=1e-12, tol_e=1e-10)
         assert r["converged"] and abs(r["E_total"] - ref.E) < 1e-9
+
+
+def test_prepared_batch_beside_a_running_scf():
+    """A batch prepared on a host thread while another batch's SCF runs on the
+    caller's stream gives bit-identical setups and the same SCF energies as a
+    batch prepared alone."""
+    need_gpu()
+    import torch
+    import paper_2407_19614_amd as P
+    from paper_2407_19614_amd.binding import PreparedBatch, energy_batched, prepare_batch
+    print("case: PreparedBatch beside a running batched SCF", flush=True)
+    systems = small_batch()
+    first, second = systems[:3], systems[3:]
+    p1 = prepare_batch(first, P.FP64, workers=2)
+    nxt = PreparedBatch(second, P.FP64, workers=2)
+    r1, _, _ = energy_batched(p1, P.FP64, tol_E=1e-11, tol_err=1e-9)
+    p2 = nxt.result()
+    r2, _, _ = energy_batched(p2, P.FP64, tol_E=1e-11, tol_err=1e-9)
+    alone = prepare_batch(second, P.FP64, workers=2)
+    torch.cuda.synchronize()
+    for a, b in zip(p2, alone):
+        for name in ("pairs", "T", "L", "Linv", "B"):
+            assert torch.equal(getattr(a, name), getattr(b, name)), name
+    ra, _, _ = energy_batched(alone, P.FP64, tol_E=1e-11, tol_err=1e-9)
+    for x, y in zip(r2, ra):
+        assert x["converged"] and y["converged"] and x["E_total"] == y["E_total"]
+    assert all(r["converged"] for r in r1)

@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--aimd", action="store_true",
                     help="also run Born-Oppenheimer NVE dynamics of the N=1000 workload (1 fs steps)")
     ap.add_argument("--aimd-steps", type=int, default=10, help="time steps of that run")
+    ap.add_argument("--no-batched-overlap", action="store_true",
+                    help="batched workload: set each wave up before its SCF instead of beside the previous one")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched workload with the default launch shapes instead of autotuned ones")
     ap.add_argument("--quick", action="store_true",
@@ -96,7 +98,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.only == "batched":
         print(json.dumps({"batched": batched_leg(args.batched_n, baseline_n=0, prec_name=args.batched_prec,
-                                                 autotune=not args.no_autotune, oracle_sample=False)}))
+                                                 autotune=not args.no_autotune, oracle_sample=False,
+                                                 allow_overlap=not args.no_batched_overlap)}))
         return
     s = synth.config_system("n1000")
     pr = P.RIProblem(s, device=dev, prec=P.FP64)
@@ -206,7 +209,7 @@ def main():
         del pr, J, K, gam
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(args.batched_n, prec_name=args.batched_prec, autotune=not args.no_autotune,
-                                     oracle_sample=not args.no_cpu)
+                                     oracle_sample=not args.no_cpu, allow_overlap=not args.no_batched_overlap)
     if not args.no_learned and not args.quick:
         out["learned_start"] = learned_leg(args.learned_steps, oracle_sample=not args.no_cpu)
     if args.aimd:
@@ -375,7 +378,8 @@ def compressed_leg(s, C, res64, args, P, torch, np, ms_fp64):
     return out
 
 
-def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=True, oracle_sample=True):
+def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=True, oracle_sample=True,
+                allow_overlap=True):
     """256 independent He-like clusters with n_centres ~ U{10..60} (N = 10 per
     centre, N_aux = 30 per centre, n_occ = n_centres), seeds 4001...: pairs, 3c
     integrals and B per molecule, then one lockstep SCF per wave of molecules
@@ -390,7 +394,8 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=Tr
     import torch
     import synth
     import paper_2407_19614_amd as P
-    from paper_2407_19614_amd.binding import PreparedBatch, batch_autotune, energy_batched, prepare_batch
+    from paper_2407_19614_amd.binding import (PreparedBatch, batch_autotune, batch_workspace_bytes, energy_batched,
+                                              prepare_batch)
     systems = synth.batched_systems(n_mol)
     prec = {"fp32": P.FP32, "fp64": P.FP64, "fp32f64": P.FP32 | P.FINAL_FP64}[prec_name]
     # FP32 exchange iterates to its own noise floor.  With the final FP64 build the
@@ -421,8 +426,17 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=Tr
             ts = time.perf_counter()
             tune = batch_autotune(probs, prec)
             t_tune = time.perf_counter() - ts
+        if w == 0:
+            # the next wave's setup runs beside this wave's SCF only if both waves' data and
+            # the SCF workspace fit in device memory at once (the FP32-stored forms do; two
+            # waves of FP64 B do not), with the first wave's footprint standing in for the next
+            data0 = torch.cuda.memory_allocated()
+            need = 2 * data0 + batch_workspace_bytes(probs, prec) + (8 << 30)
+            overlap = allow_overlap and need < torch.cuda.get_device_properties(0).total_memory
+            log(f"batched: first wave {data0 / 2**30:.1f} GiB, two waves + workspace {need / 2**30:.1f} GiB: "
+                f"{'setup beside SCF' if overlap else 'setup before each wave'}")
         nxt = (PreparedBatch(systems[starts[w + 1]:starts[w + 1] + wave], prec, workers=4)
-               if w + 1 < len(starts) else None)
+               if overlap and w + 1 < len(starts) else None)
         ts = time.perf_counter()
         res, _, _ = energy_batched(probs, prec, use_graph=True, raise_on_noconv=False, tuning=tune, **tol)
         torch.cuda.synchronize()
@@ -457,7 +471,7 @@ def batched_leg(n_mol, wave=128, baseline_n=32, prec_name="fp32f64", autotune=Tr
            "scf_per_s": round(len(systems) / wall, 3), "wall_s": round(wall, 2),
            "scf_per_s_steady": round(len(systems) / (wall - t_tune), 3),
            "setup_waited_s": round(t_setup, 2), "autotune_s": round(t_tune, 3), "batched_scf_s": round(t_scf, 2),
-           "wave": wave, "tuning": tune.as_dict() if tune is not None else None,
+           "wave": wave, "setup_beside_scf": bool(overlap), "tuning": tune.as_dict() if tune is not None else None,
            "all_converged": bool(conv.all()), "mean_iters": round(float(iters.mean()), 2)}
     if baseline_n > 0:
         out.update({

@@ -513,6 +513,12 @@ def _batch_ws(n, sysarr, mols, prec, dev):
     return torch.empty(nb, dtype=torch.uint8, device=dev), nb
 
 
+def batch_workspace_bytes(problems, prec=FP64):
+    """Workspace bytes energy_batched allocates for these problems."""
+    n, _, sysarr, mols, _, _ = _batch_args(problems)
+    return int(lib().ri_energy_batched_workspace(n, ctypes.byref(sysarr), ctypes.byref(mols), prec))
+
+
 _PREP_STREAMS = {}
 
 

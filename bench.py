@@ -81,9 +81,10 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="profiling mode: seeded random occupied orbitals instead of the converged SCF "
                          "(same shapes and kernels), no pipeline, no CPU baseline")
-    ap.add_argument("--only", choices=["pipeline", "batched"],
+    ap.add_argument("--only", choices=["pipeline", "batched", "learned"],
                     help="profiling mode: only the N=1000 energy+gradient pipeline (a cold and a warm pass), "
-                         "or only the batched workload (no single-path or oracle baselines); prints its JSON")
+                         "only the batched workload (no single-path or oracle baselines), or only the "
+                         "learned-start workload (no oracle baseline); prints its JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -96,6 +97,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only == "learned":
+        print(json.dumps({"learned_start": learned_leg(args.learned_steps, oracle_sample=False)}))
+        return
     if args.only == "batched":
         print(json.dumps({"batched": batched_leg(args.batched_n, baseline_n=0, prec_name=args.batched_prec,
                                                  autotune=not args.no_autotune, oracle_sample=False,

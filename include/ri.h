@@ -400,6 +400,11 @@ int32_t ri_density_to_pairs(int32_t N, const int32_t* pairs, int64_t n_pairs, co
 /* Start along a geometry sequence from the previous geometry's converged
  * density D' plus a predicted change (the network trained on the change
  * between consecutive geometries of the sequence).
+ * Paper: the molecular-dynamics start from the previous step's solution
+ * (Ab Initio Molecular Dynamics subsection of the algorithm section); the predicted
+ * change on top of it is this library's extension.  Each of the three calls
+ * returns RI_E_ARG for invalid sizes or NULL buffers and RI_E_HIP when its
+ * launch fails; all pointers are device memory owned by the caller.
  * ri_pair_delta_features - features of each listed pair for that change,
  * between the previous positions xyz_prev (device [n_centres][3]; the basis
  * is sys's) and sys->xyz, with f4, c_X and f7 as for ri_pair_features:

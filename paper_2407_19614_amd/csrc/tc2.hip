@@ -127,21 +127,27 @@ __global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict
     constexpr int KQ = SK / 4, RS = 256 / SK;
     const int gt = tid & 255, lk0 = gt % SK, lr0 = gt / SK;
     double ra[KQ], rb[KQ];
+    // unconditional loads from clamped addresses, zeroed by a select only
+    // when they are stored (no branch around each load, and no wait for the
+    // load before the MFMAs of the current slice)
+    bool kin = false;
     auto load = [&](int s) {
         const int k = kb + s * SK + lk0;
-        const bool kin = k < ke;
+        kin = k < ke;
+        const int kc = min(k, N - 1);
 #pragma unroll
         for (int i = 0; i < KQ; ++i) {
             const int r = lr0 + RS * i;
-            ra[i] = (kin && m0 + r < N) ? X[(int64_t)(m0 + r) * N + k] : 0.0;
-            rb[i] = (kin && n0 + r < N) ? X[(int64_t)(n0 + r) * N + k] : 0.0;
+            ra[i] = X[(int64_t)min(m0 + r, N - 1) * N + kc];
+            rb[i] = X[(int64_t)min(n0 + r, N - 1) * N + kc];
         }
     };
     auto store = [&](int stg) {
 #pragma unroll
         for (int i = 0; i < KQ; ++i) {
-            As[half][stg][lk0][lr0 + RS * i] = ra[i];
-            Bs[half][stg][lk0][lr0 + RS * i] = rb[i];
+            const int r = lr0 + RS * i;
+            As[half][stg][lk0][r] = (kin && m0 + r < N) ? ra[i] : 0.0;
+            Bs[half][stg][lk0][r] = (kin && n0 + r < N) ? rb[i] : 0.0;
         }
     };
     d4_t acc[2][2];
@@ -156,14 +162,25 @@ __global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict
     for (int s = 0; s < nsl; ++s) {
         const int cur = s & 1;
         if (s + 1 < nsl) load(s + 1);
+        // operands of the next k-step are read from LDS before this step's
+        // MFMAs, so their latency hides under the MFMAs
+        double a0 = As[half][cur][lk][wm + li], a1 = As[half][cur][lk][wm + 16 + li];
+        double b0 = Bs[half][cur][lk][wn + li], b1 = Bs[half][cur][lk][wn + 16 + li];
 #pragma unroll
         for (int kk = 0; kk < SK; kk += 4) {
-            const double a0 = As[half][cur][kk + lk][wm + li], a1 = As[half][cur][kk + lk][wm + 16 + li];
-            const double b0 = Bs[half][cur][kk + lk][wn + li], b1 = Bs[half][cur][kk + lk][wn + 16 + li];
+            double na0 = 0.0, na1 = 0.0, nb0 = 0.0, nb1 = 0.0;
+            if (kk + 4 < SK) {
+                na0 = As[half][cur][kk + 4 + lk][wm + li];
+                na1 = As[half][cur][kk + 4 + lk][wm + 16 + li];
+                nb0 = Bs[half][cur][kk + 4 + lk][wn + li];
+                nb1 = Bs[half][cur][kk + 4 + lk][wn + 16 + li];
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep those reads ahead of the MFMAs
             acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
             acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
             acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
             acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+            a0 = na0; a1 = na1; b0 = nb0; b1 = nb1;
         }
         if (s + 1 < nsl) store(cur ^ 1);
         __syncthreads();

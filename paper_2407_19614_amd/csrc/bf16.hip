@@ -299,6 +299,153 @@ __global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict
 #endif
 }
 
+// X for items (row block I2 of 128 rows, auxiliary pair P0 = 2 Pp, P0 + 1),
+// item = I2 + nt2 * Pp, persistent as above.  One ring stage holds the B
+// parts of both indices' 128 rows and one C slice, so each C slice serves
+// two auxiliary indices (it is about half of a one-index stage).  Waves 0-3
+// take index P0 and waves 4-7 index P0 + 1; wave w owns rows 32 (w % 4) ..
+// +31 and every occupied column tile.  RING2 slots (one or two stages in
+// flight while one is multiplied, as LDS allows).  With an odd n_aux the
+// last pair's second index reloads P0 and is not stored.
+template <int NS> struct Bf16PairRing { static constexpr int value = NS == 3 ? 2 : 3; };
+
+template <int NS, int MT>
+__global__ __launch_bounds__(512, 1) void x_bf16p_kernel(const __bf16* __restrict__ B, int nt, int n_aux,
+                                                         const __bf16* __restrict__ Ct, int Npad, int n_occ,
+                                                         __bf16* __restrict__ Xb, int64_t R) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    constexpr int RING2 = Bf16PairRing<NS>::value;
+    constexpr int W = 16 * MT;
+    constexpr int SB = 2 * NS * 128 * ROWB, SC = NS * W * ROWB, STAGE = SB + SC;
+    constexpr int NB = 2 * NS;                         // B instructions per wave per stage
+    constexpr int NCI = NS * MT, NC = (NCI + 7) / 8;   // C instructions (total, per wave)
+    constexpr int LOADS = NB + NC;                     // VMEM ops per wave per stage
+    __shared__ __attribute__((aligned(16))) __bf16 ring[RING2 * STAGE];
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rg = wave & 3, pi = wave >> 2;
+    const int nt2 = (nt + 1) / 2, spi = 2 * nt;        // stages per item
+    const int npair = (n_aux + 1) / 2;
+    const int n_items = nt2 * npair;
+    const int G = gridDim.x;
+    const int mine = n_items > (int)blockIdx.x ? (n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
+    if (mine == 0) return;
+    const int64_t cplane = (int64_t)W * Npad;
+    const int lrow = lane >> 2, lch = lane & 3;
+    const int bvoff = (lrow * ROWB + 8 * swz(lrow, lch)) * 2;
+    const int cvoff = (lrow * Npad + 8 * swz(lrow, lch)) * 2;
+    // B instruction u of every wave: index u / NS, part u % NS, 16-row group
+    // `wave` of the 128 (tile wave / 4, rows 16 (wave % 4) ..)
+    const int bsoff = 16 * (wave & 3) * ROWB * 2;
+    const int btl = wave >> 2;
+    const __amdgpu_buffer_rsrc_t crs = rsrc(Ct, (int64_t)NS * cplane * 2);
+    int csoff[NC], cdst[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+        const int t = min(wave + 8 * u, NCI - 1), q = t / MT, mg = t % MT;
+        csoff[u] = (int)((q * cplane + (int64_t)16 * mg * Npad) * 2);
+        cdst[u] = SB + (q * W + 16 * mg) * ROWB;
+    }
+
+    int ij = 0, is = 0, islot = 0;                      // next stage to issue
+    int iI2 = (int)blockIdx.x % nt2, iPp = (int)blockIdx.x / nt2;
+    auto issue = [&]() {
+        const int J = is >> 1, ks = is & 1;
+        __bf16* st = ring + islot * STAGE;
+        const int I = min(2 * iI2 + btl, nt - 1);
+        const int hoff = ks * NS * 2048 * 2;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int P = min(2 * iPp + x, n_aux - 1);
+            const __amdgpu_buffer_rsrc_t brs = rsrc(B + (((int64_t)P * nt + I) * nt + J) * NS * 4096, NS * 4096 * 2);
+#pragma unroll
+            for (int p = 0; p < NS; ++p)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(brs, (lds_void_t)(st + ((x * NS + p) * 128 + 16 * wave) * ROWB),
+                                                         16, bvoff, hoff + p * 2048 * 2 + bsoff, 0, 0);
+        }
+        const int coff = (64 * J + 32 * ks) * 2;
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(crs, (lds_void_t)(st + cdst[u]), 16, cvoff, csoff[u] + coff, 0, 0);
+        islot = islot == RING2 - 1 ? 0 : islot + 1;
+        if (is + 1 < spi) ++is;
+        else if (ij + 1 < mine) {
+            is = 0;
+            ++ij;
+            const int item = (int)blockIdx.x + ij * G;
+            iI2 = item % nt2;
+            iPp = item / nt2;
+        }   // else: stay on the last stage (tail reloads land in a slot that is never read)
+    };
+
+    d4_t acc[2][MT];
+    f4_t corr[2][MT];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) { acc[f][m] = d4_t{0, 0, 0, 0}; corr[f][m] = f4_t{0.f, 0.f, 0.f, 0.f}; }
+    int cj = 0, cs = 0, cslot = 0;
+    int cI2 = (int)blockIdx.x % nt2, cPp = (int)blockIdx.x / nt2;
+    const int64_t xplane = (int64_t)Npad * R;
+#pragma unroll
+    for (int r = 0; r < RING2 - 1; ++r) issue();
+    while (true) {
+        wait_vm<LOADS * (RING2 - 2)>();
+        __builtin_amdgcn_s_barrier();
+        issue();
+        const __bf16* sb = ring + cslot * STAGE;
+        const __bf16* sc = sb + SB;
+        cslot = cslot == RING2 - 1 ? 0 : cslot + 1;
+        bf8_t a[2][NS];
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int p = 0; p < NS; ++p) a[f][p] = lds_frag(sb + (pi * NS + p) * 128 * ROWB, 32 * rg + 16 * f + li, lk);
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi) {
+            bf8_t c[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) c[q] = lds_frag(sc + q * W * ROWB, 16 * mi + li, lk);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) split_mfma<NS>(a[f], c, acc[f][mi], corr[f][mi]);
+        }
+        if ((cs & 7) == 7) {
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int mi = 0; mi < MT; ++mi) fold(acc[f][mi], corr[f][mi]);
+        }
+        if (++cs < spi) continue;
+        // item complete: write X parts of this wave's index, reset
+        const int P = 2 * cPp + pi;
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int mi = 0; mi < MT; ++mi) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int mu = 128 * cI2 + 32 * rg + 16 * f + 4 * lk + r, i = 16 * mi + li;
+                    if (P < n_aux && mu < 64 * nt && i < n_occ) {
+                        __bf16 pt[3];
+                        split_parts(acc[f][mi][r] + (double)corr[f][mi][r], NS, pt);
+                        const int64_t o = (int64_t)mu * R + (int64_t)P * n_occ + i;
+#pragma unroll
+                        for (int k = 0; k < NS; ++k) Xb[k * xplane + o] = pt[k];
+                    }
+                }
+                acc[f][mi] = d4_t{0, 0, 0, 0};
+                corr[f][mi] = f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+        if (++cj == mine) break;
+        cs = 0;
+        const int item = (int)blockIdx.x + cj * G;
+        cI2 = item % nt2;
+        cPp = item / nt2;
+    }
+    wait_vm<0>();
+#endif
+}
+
 // K partials over lower 128 x 128 tiles, split over the K index in multiples
 // of 32: part[z][mu][nu] = sum_r X[mu][r] X[nu][r] (split products).  Wave w
 // owns rows 64 (w % 2) .. +63 and columns 32 (w / 2) .. +31 of the tile.
@@ -456,10 +603,11 @@ hipError_t x_transform_bf16(const void* B, int prec, int N, int n_aux, int n_occ
         xb_pad_kernel<<<(unsigned)((padn + 255) / 256), 256, 0, st>>>(xb, ns, Npad, R, rows_written, cols);
         RI_TRY(hipGetLastError());
     }
-    const int64_t n_items = (int64_t)((nt + 1) / 2) * n_aux;
+    // items of two auxiliary indices each (one C slice per stage serves both)
+    const int64_t n_items = (int64_t)((nt + 1) / 2) * ((n_aux + 1) / 2);
     const unsigned grid = (unsigned)std::min<int64_t>(n_items, device_cus());
     const __bf16* b = (const __bf16*)B;
-#define XB(NS, M) case M: x_bf16_kernel<NS, M><<<grid, 512, 0, st>>>(b, nt, n_aux, ct, Npad, n_occ, xb, R); break;
+#define XB(NS, M) case M: x_bf16p_kernel<NS, M><<<grid, 512, 0, st>>>(b, nt, n_aux, ct, Npad, n_occ, xb, R); break;
     if (ns == 3) {
         switch (mt) { XB(3, 1) XB(3, 2) XB(3, 3) XB(3, 4) XB(3, 5) XB(3, 6) XB(3, 7) XB(3, 8) default: return hipErrorInvalidValue; }
     } else {

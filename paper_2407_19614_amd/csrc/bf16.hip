@@ -148,165 +148,18 @@ __device__ __forceinline__ void fold(d4_t& acc, f4_t& corr) {
     }
 }
 
-// X for items (row block I2 of 128 rows, auxiliary P), item = I2 + nt2 * P,
-// items b, b + G, ... for workgroup b of G (persistent).  D[mu][i] = sum_nu
-// B^P[mu][nu] C[nu][i].  Wave w owns rows 32 (w % 4) .. +31 of the item and
-// column half w / 4 (tiles 0 .. MA-1 or MA .. MT-1).  Both operands stream
-// through the LDS ring: per stage the B parts of the item's 128 rows and the
-// C parts of all columns, 32 deep.  Item, stage and slot advance by
-// counters; rows of a tile index >= nt load tile nt - 1 and are never
-// written.
-template <int NS, int MT>
-__global__ __launch_bounds__(512, 1) void x_bf16_kernel(const __bf16* __restrict__ B, int nt, int n_aux,
-                                                        const __bf16* __restrict__ Ct, int Npad, int n_occ,
-                                                        __bf16* __restrict__ Xb, int64_t R) {
-#if defined(__HIP_DEVICE_COMPILE__)   // buffer resources exist on the device side only
-    constexpr int W = 16 * MT, MA = (MT + 1) / 2;
-    constexpr int SB = NS * 128 * ROWB, SC = NS * W * ROWB, STAGE = SB + SC;
-    constexpr int NB = NS;                             // B instructions per wave per stage (8 NS / 8 waves)
-    constexpr int NCI = NS * MT, NC = (NCI + 7) / 8;   // C instructions (total, per wave)
-    constexpr int LOADS = NB + NC;                     // VMEM ops per wave per stage
-    __shared__ __attribute__((aligned(16))) __bf16 ring[RING * STAGE];
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int rg = wave & 3, cg = wave >> 2;
-    const int m0 = cg * MA, mcount = cg ? MT - MA : MA;
-    const int nt2 = (nt + 1) / 2, spi = 2 * nt;        // stages per item
-    const int n_items = nt2 * n_aux;
-    const int G = gridDim.x;
-    const int mine = n_items > (int)blockIdx.x ? (n_items - 1 - (int)blockIdx.x) / G + 1 : 0;
-    if (mine == 0) return;
-    const int64_t cplane = (int64_t)W * Npad;
-    const int lrow = lane >> 2, lch = lane & 3;
-    // lane byte offsets of (row lrow, chunk lch) of a 16-row group: B tile halves are 32 wide, C rows Npad
-    const int bvoff = (lrow * ROWB + 8 * swz(lrow, lch)) * 2;
-    const int cvoff = (lrow * Npad + 8 * swz(lrow, lch)) * 2;
-    // B instructions: part p, 16-row group g of the 128 (tile g / 4, rows 16 (g % 4) ..)
-    int bsoff[NB], btl[NB], bdst[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const int t = wave + 8 * u, p = t >> 3, g = t & 7;
-        bsoff[u] = (p * 2048 + 16 * (g & 3) * ROWB) * 2;
-        btl[u] = g >> 2;
-        bdst[u] = (p * 128 + 16 * g) * ROWB;
-    }
-    const __amdgpu_buffer_rsrc_t crs = rsrc(Ct, (int64_t)NS * cplane * 2);
-    int csoff[NC], cdst[NC];
-#pragma unroll
-    for (int u = 0; u < NC; ++u) {
-        const int t = min(wave + 8 * u, NCI - 1), q = t / MT, mg = t % MT;
-        csoff[u] = (int)((q * cplane + (int64_t)16 * mg * Npad) * 2);
-        cdst[u] = SB + (q * W + 16 * mg) * ROWB;
-    }
-
-    int ij = 0, is = 0, islot = 0;                      // next stage to issue
-    int iI2 = (int)blockIdx.x % nt2, iP = (int)blockIdx.x / nt2;
-    auto issue = [&]() {
-        const int J = is >> 1, ks = is & 1;
-        __bf16* st = ring + islot * STAGE;
-        __amdgpu_buffer_rsrc_t brs[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = min(2 * iI2 + h, nt - 1);
-            brs[h] = rsrc(B + (((int64_t)iP * nt + I) * nt + J) * NS * 4096, NS * 4096 * 2);
-        }
-        const int hoff = ks * NS * 2048 * 2;
-#pragma unroll
-        for (int u = 0; u < NB; ++u)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(brs[btl[u]], (lds_void_t)(st + bdst[u]), 16, bvoff,
-                                                     hoff + bsoff[u], 0, 0);
-        const int coff = (64 * J + 32 * ks) * 2;
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(crs, (lds_void_t)(st + cdst[u]), 16, cvoff, csoff[u] + coff, 0, 0);
-        islot = islot == RING - 1 ? 0 : islot + 1;
-        if (is + 1 < spi) ++is;
-        else if (ij + 1 < mine) {
-            is = 0;
-            ++ij;
-            const int item = (int)blockIdx.x + ij * G;
-            iI2 = item % nt2;
-            iP = item / nt2;
-        }   // else: stay on the last stage (tail reloads land in a slot that is never read)
-    };
-
-    d4_t acc[2][MA];
-    f4_t corr[2][MA];
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int m = 0; m < MA; ++m) { acc[f][m] = d4_t{0, 0, 0, 0}; corr[f][m] = f4_t{0.f, 0.f, 0.f, 0.f}; }
-    int cj = 0, cs = 0, cslot = 0;
-    int cI2 = (int)blockIdx.x % nt2, cP = (int)blockIdx.x / nt2;
-    const int64_t xplane = (int64_t)Npad * R;
-    issue();
-    issue();
-    while (true) {
-        wait_vm<LOADS>();
-        __builtin_amdgcn_s_barrier();
-        issue();
-        const __bf16* sb = ring + cslot * STAGE;
-        const __bf16* sc = sb + SB;
-        cslot = cslot == RING - 1 ? 0 : cslot + 1;
-        bf8_t a[2][NS];
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int p = 0; p < NS; ++p) a[f][p] = lds_frag(sb + p * 128 * ROWB, 32 * rg + 16 * f + li, lk);
-#pragma unroll
-        for (int mi = 0; mi < MA; ++mi) {
-            if (mi < mcount) {
-                bf8_t c[NS];
-#pragma unroll
-                for (int q = 0; q < NS; ++q) c[q] = lds_frag(sc + q * W * ROWB, 16 * (m0 + mi) + li, lk);
-#pragma unroll
-                for (int f = 0; f < 2; ++f) split_mfma<NS>(a[f], c, acc[f][mi], corr[f][mi]);
-            }
-        }
-        if ((cs & 7) == 7) {
-#pragma unroll
-            for (int f = 0; f < 2; ++f)
-#pragma unroll
-                for (int mi = 0; mi < MA; ++mi) fold(acc[f][mi], corr[f][mi]);
-        }
-        if (++cs < spi) continue;
-        // item complete: write X parts, reset
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int mi = 0; mi < MA; ++mi) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int mu = 128 * cI2 + 32 * rg + 16 * f + 4 * lk + r, i = 16 * (m0 + mi) + li;
-                    if (mi < mcount && mu < 64 * nt && i < n_occ) {
-                        __bf16 pt[3];
-                        split_parts(acc[f][mi][r] + (double)corr[f][mi][r], NS, pt);
-                        const int64_t o = (int64_t)mu * R + (int64_t)cP * n_occ + i;
-#pragma unroll
-                        for (int k = 0; k < NS; ++k) Xb[k * xplane + o] = pt[k];
-                    }
-                }
-                acc[f][mi] = d4_t{0, 0, 0, 0};
-                corr[f][mi] = f4_t{0.f, 0.f, 0.f, 0.f};
-            }
-        if (++cj == mine) break;
-        cs = 0;
-        const int item = (int)blockIdx.x + cj * G;
-        cI2 = item % nt2;
-        cP = item / nt2;
-    }
-    wait_vm<0>();
-#endif
-}
-
 // X for items (row block I2 of 128 rows, auxiliary pair P0 = 2 Pp, P0 + 1),
-// item = I2 + nt2 * Pp, persistent as above.  One ring stage holds the B
+// item = I2 + nt2 * Pp, items b, b + G, ... for workgroup b of G
+// (persistent).  D[mu][i] = sum_nu B^P[mu][nu] C[nu][i].  One ring stage holds the B
 // parts of both indices' 128 rows and one C slice, so each C slice serves
-// two auxiliary indices (it is about half of a one-index stage).  Waves 0-3
-// take index P0 and waves 4-7 index P0 + 1; wave w owns rows 32 (w % 4) ..
-// +31 and every occupied column tile.  RING2 slots (one or two stages in
-// flight while one is multiplied, as LDS allows).  With an odd n_aux the
-// last pair's second index reloads P0 and is not stored.
+// two auxiliary indices (it is about half of a one-index stage: with one
+// index per item the same kernel shape took 6.0 ms for BF16X6 at N=1000,
+// against 4.8).  Waves 0-3 take index P0 and waves 4-7 index P0 + 1; wave w
+// owns rows 32 (w % 4) .. +31 and every occupied column tile.  RING2 slots
+// (one or two stages in flight while one is multiplied, as LDS allows).
+// Item, stage and slot advance by counters; rows of a tile index >= nt load
+// tile nt - 1 and are never written.  With an odd n_aux the last pair's
+// second index reloads index n_aux - 1 and is not stored.
 template <int NS> struct Bf16PairRing { static constexpr int value = NS == 3 ? 2 : 3; };
 
 template <int NS, int MT>

@@ -275,11 +275,12 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None, K64=No
             pr.fock_jk_timed(C, J, K, g, e4)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
-        ph = np.array([pr.fock_phases(e4) for e4 in ev]).mean(0)
+        bf = prec in (P.BF16X3, P.BF16X6)
+        ph = np.array([pr.fock_phases(e4, bf16=bf) for e4 in ev]).mean(0)
         out[name] = {"builds_per_s": round(1.0 / dt, 3), "ms_per_build": round(dt * 1e3, 3),
                      "speedup_vs_fp64": round(ms_fp64 / (dt * 1e3), 3),
-                     "phases_ms": {"gamma_J": round(float(ph[0]), 3), "X": round(float(ph[1]), 3),
-                                   "K_syrk": round(float(ph[2]), 3)}}
+                     "phases_ms": {"gamma_J_beside_SYRK" if bf else "gamma_J_beside_X": round(float(ph[0]), 3),
+                                   "X": round(float(ph[1]), 3), "K_syrk": round(float(ph[2]), 3)}}
         if K64 is not None:
             out[name]["max_abs_dK_vs_fp64"] = float((K - K64).abs().max())
             out[name]["max_abs_K_fp64"] = float(K64.abs().max())

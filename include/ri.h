@@ -195,9 +195,10 @@ int32_t ri_pack_b(int32_t N, int32_t n_aux, const double* Bc, const int32_t* pai
  *   gamma   [n_aux] out (may be NULL).
  * Asynchronous: no host synchronisation.  The gamma/J part runs on a
  * library-owned side stream of the current device (one per device, default
- * priority, created on first use), concurrently with the exchange; `stream`
- * waits for it before any later work on `stream`, so the outputs are ordered
- * on `stream` as if all work ran there.  Also used by ri_energy's SCF loop. */
+ * priority, created on first use), concurrently with the exchange (for the
+ * split-BF16 forms with the SYRK only, after X); `stream` waits for it
+ * before any later work on `stream`, so the outputs are ordered on `stream`
+ * as if all work ran there.  Also used by ri_energy's SCF loop. */
 int32_t ri_fock_jk(int32_t N, int32_t n_aux, int32_t n_occ, const void* B, int32_t prec,
                    const double* Bc, const int32_t* pairs, int64_t n_pairs,
                    const double* C_occ, double* J, double* K, double* gamma,
@@ -228,7 +229,9 @@ int32_t ri_fock_jk_noalloc(int32_t N, int32_t n_aux, int32_t n_occ, const void* 
  * eq. k_ri_2, eq. tp, Algorithm 1 Fock-build loop): the gamma/J contraction
  * runs on the library's side stream beside the exchange.  Records
  *   events[0] on `stream` before both parts;
- *   events[1] on the side stream after gamma/J (gamma/J = events[0..1]);
+ *   events[1] on the side stream after gamma/J (gamma/J = events[0..1];
+ *             for the split-BF16 forms the side stream forks after X, and
+ *             gamma/J = events[2..1], beside the SYRK);
  *   events[2] on `stream` after the exchange half-transform X^P = B^P C_occ
  *             (X = events[0..2], measured while gamma/J runs beside it);
  *   events[3] on `stream` after the K = sum X X^T SYRK, its reduction and

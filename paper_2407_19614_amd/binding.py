@@ -308,7 +308,8 @@ class RIProblem:
     def fock_jk_timed(self, C_occ, J, K, gamma, events):
         """ri_fock_jk with four torch.cuda.Event objects recorded by the
         library: start, end of gamma/J (side stream), end of X, end.  Phases:
-        gamma/J = e0..e1, X = e0..e2, SYRK = e2..e3 (see fock_phases)."""
+        gamma/J = e0..e1 (e2..e1 for the split-BF16 forms, whose gamma/J
+        starts after X), X = e0..e2, SYRK = e2..e3 (see fock_phases)."""
         C_occ = C_occ.contiguous()
         ws, nb = self._ws_for(OP_FOCK)
         arr = (c_void_p * 4)(*[ctypes.c_void_p(e.cuda_event) for e in events])
@@ -318,10 +319,11 @@ class RIProblem:
         _check(code, "ri_fock_jk_timed")
 
     @staticmethod
-    def fock_phases(events):
-        """(gamma/J, X, SYRK) in ms from the events of one fock_jk_timed call."""
+    def fock_phases(events, bf16=False):
+        """(gamma/J, X, SYRK) in ms from the events of one fock_jk_timed call
+        (bf16: a split-BF16 build, whose gamma/J runs beside the SYRK)."""
         e0, e1, e2, e3 = events
-        return e0.elapsed_time(e1), e0.elapsed_time(e2), e2.elapsed_time(e3)
+        return (e2 if bf16 else e0).elapsed_time(e1), e0.elapsed_time(e2), e2.elapsed_time(e3)
 
     def pair_features(self):
         torch = self.torch

@@ -297,7 +297,8 @@ struct Fork {
 // side stream, concurrently with the exchange, and the caller's stream waits
 // for it before the call returns.  ev (phase-timed form): ev[0] on `st`
 // before both parts, ev[1] on the side stream after the Coulomb part, ev[2]
-// on `st` after X, ev[3] on `st` after the SYRK and the join.
+// on `st` after X, ev[3] on `st` after the SYRK and the join (for the
+// split-BF16 forms the side stream forks after X).
 // With side == false everything runs on `st` (no side stream, no events): the
 // same kernels and sums, so the same results bit for bit.
 int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const double* Bc, const int32_t* pairs,
@@ -306,6 +307,15 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
     double* g = gamma ? gamma : w.gamma;
     if (ev) HIPC(hipEventRecord(ev[0], st));
     Fork fk;
+    const bool bf = is_bf16(prec);
+    // The split-BF16 X holds every CU (one 141 KB-LDS workgroup each) and
+    // streams B at ~4 TB/s: gamma/J beside it took longer than X itself and
+    // ran on into the SYRK.  There the side stream forks after X, so
+    // gamma/J runs beside the SYRK only.
+    if (bf) {
+        HIPC(ri::x_transform_bf16(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
+        if (ev) HIPC(hipEventRecord(ev[2], st));
+    }
     const bool overlap = side && fk.open(st);
     if (ev && !overlap) {
         ri::set_hip_error("side stream or its events could not be created");
@@ -313,15 +323,13 @@ int32_t fock_impl(int N, int n_aux, int n_occ, const void* B, int prec, const do
     }
     // beside a large FP64 or FP32 exchange, gamma and J run on a capped grid so
     // that the X kernel's workgroups are not held back behind thousands of
-    // theirs; the split-BF16 exchange is shorter than capped gamma/J, which
-    // would then set the build time, so there they keep the full grid
-    const bool capped = overlap && !is_bf16(prec) && (int64_t)n_aux * n_pairs >= ri::GJ_SIDE_MIN;
+    // theirs; beside the split-BF16 SYRK, which is shorter than capped gamma/J
+    // would be, they keep the full grid
+    const bool capped = overlap && !bf && (int64_t)n_aux * n_pairs >= ri::GJ_SIDE_MIN;
     HIPC(ri::gamma_j(Bc, pairs, n_pairs, N, n_aux, n_occ, C, w.dpair, g, w.jpart, w.js, J, overlap ? fk.side : st,
                      capped ? ri::GJ_SIDE_CAP : 0));
     if (ev) HIPC(hipEventRecord(ev[1], fk.side));
-    if (is_bf16(prec)) {
-        HIPC(ri::x_transform_bf16(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, st));
-        if (ev) HIPC(hipEventRecord(ev[2], st));
+    if (bf) {
         HIPC(ri::k_syrk_bf16(w.Xt, prec, N, n_aux, n_occ, w.part, w.ks, K, st));
     } else {
         HIPC(x_any(B, prec, N, n_aux, n_occ, C, w.Cp, w.Xt, Bc, pairs, n_pairs, w.sw, st));

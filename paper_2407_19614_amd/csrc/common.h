@@ -169,10 +169,6 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
 hipError_t tri_inverse(const double* L, int n, int64_t lda, const double* Dinv, double* Linv, int64_t ldi,
                        hipStream_t s);
 
-// In place B <- L^{-1} B for lower L (n x n) whose 64 x 64 diagonal-block
-// inverses are in Dinv (as left by cholesky_inv); B has ncols columns.
-hipError_t trsm_lower_inplace(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols,
-                              int64_t ldb, hipStream_t s);
 hipError_t fill(double* p, double v, int64_t n, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t set_identity(double* p, int n, int64_t ld, hipStream_t s);

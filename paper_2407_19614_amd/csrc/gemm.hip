@@ -473,30 +473,6 @@ hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* Dinv, dou
                     ncols, ldb, s, r0 + n1, done);
 }
 
-hipError_t trsm_lower_inplace(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols,
-                              int64_t ldb, hipStream_t s) {
-    // B <- L^{-1} B by forward substitution over 64-row blocks (diagonal blocks
-    // applied through their inverses Dinv), right-looking inside 512-row
-    // panels, and one K = 512 update of the rows below each panel.
-    constexpr int PANEL = 512;
-    for (int K0 = 0; K0 < n; K0 += PANEL) {
-        const int K1 = min(n, K0 + PANEL);
-        for (int k0 = K0; k0 < K1; k0 += 64) {
-            const int w = min(64, K1 - k0), k1 = k0 + w;
-            double* Bk = B + (int64_t)k0 * ldb;
-            RI_TRY(gemm_f64(false, false, w, ncols, w, 1.0, Dinv + (int64_t)(k0 / 64) * 4096, 64, 0, Bk, ldb, 0,
-                            0.0, Bk, ldb, 0, 1, 0, 0, s));
-            if (k1 < K1)
-                RI_TRY(gemm_f64(false, false, K1 - k1, ncols, w, -1.0, L + (int64_t)k1 * lda + k0, lda, 0, Bk, ldb,
-                                0, 1.0, B + (int64_t)k1 * ldb, ldb, 0, 1, 0, 0, s));
-        }
-        if (K1 < n)
-            RI_TRY(gemm_f64(false, false, n - K1, ncols, K1 - K0, -1.0, L + (int64_t)K1 * lda + K0, lda, 0,
-                            B + (int64_t)K0 * ldb, ldb, 0, 1.0, B + (int64_t)K1 * ldb, ldb, 0, 1, 0, 0, s));
-    }
-    return hipSuccess;
-}
-
 hipError_t gemm_grouped(bool ta, bool tb, const GemmDesc* d, const int* prefix, int n, int total, hipStream_t s,
                         int tile) {
     if (total <= 0) return hipSuccess;

@@ -171,13 +171,8 @@ hipError_t tri_inverse(const double* L, int n, int64_t lda, const double* Dinv, 
 
 hipError_t fill(double* p, double v, int64_t n, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
-hipError_t set_identity(double* p, int n, int64_t ld, hipStream_t s);
-// out[k] = sum_i x[i] * y[i] for one pair of vectors, accumulated as
-// out[slot] (single block per call, deterministic).
-hipError_t dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
 // max |x_i| into *out; red: scratch of 256 doubles
 hipError_t max_abs(const double* x, int64_t n, double* out, double* red, hipStream_t s);
-hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s); // y = a x + b y
 hipError_t copy(double* dst, const double* src, int64_t n, hipStream_t s);
 hipError_t widen(const float* x, double* y, int64_t n, hipStream_t s);   // y = (double) x
 

@@ -306,11 +306,6 @@ __global__ void f32_to_f64_kernel(const float* x, double* y, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = (double)x[i];
 }
-__global__ void axpby_kernel(double* y, const double* x, double a, double b, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = a * x[i] + b * y[i];
-}
 
 __device__ double block_sum(double v) {
     __shared__ double sh[16];
@@ -335,13 +330,6 @@ __device__ double block_max(double v) {
     return r;
 }
 
-__global__ __launch_bounds__(1024) void dot_kernel(const double* x, const double* y, int64_t n,
-                                                    double* out) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * y[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) *out = s;
-}
 // max |x| in two stages: 256 workgroups over grid-stride shares, then one
 __global__ __launch_bounds__(1024) void maxabs_kernel(const double* x, int64_t n, double* out) {
     double s = 0.0;
@@ -499,22 +487,10 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
     fill_i32_kernel<<<nblk(n), 256, 0, s>>>(p, v, n);
     return hipGetLastError();
 }
-hipError_t set_identity(double* p, int n, int64_t ld, hipStream_t s) {
-    identity_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(p, n, ld);
-    return hipGetLastError();
-}
-hipError_t dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
-    dot_kernel<<<1, 1024, 0, s>>>(x, y, n, out);
-    return hipGetLastError();
-}
 hipError_t max_abs(const double* x, int64_t n, double* out, double* red, hipStream_t s) {
     maxabs_kernel<<<256, 1024, 0, s>>>(x, n, red);
     RI_TRY(hipGetLastError());
     maxabs_kernel<<<1, 1024, 0, s>>>(red, 256, out);
-    return hipGetLastError();
-}
-hipError_t axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
-    axpby_kernel<<<nblk(n), 256, 0, s>>>(y, x, a, b, n);
     return hipGetLastError();
 }
 hipError_t widen(const float* x, double* y, int64_t n, hipStream_t s) {

@@ -84,9 +84,6 @@ hipError_t diis_prep(double* Bfull, const double* row, const int* slots, int m, 
                      hipStream_t st);
 hipError_t diis_combine(const double* const* Fs, const double* coef, int m, double* out, int64_t n, hipStream_t st);
 hipError_t gershgorin(const double* F, int N, double* bounds, double* red, hipStream_t st);
-hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st);
-hipError_t traces(const double* X, const double* X2, int N, double* tr, hipStream_t st);
-hipError_t tc2_update(double* X, const double* X2, const double* tr, int n_occ, int64_t n, hipStream_t st);
 hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st);
 // ---- purification, one launch per step (tc2.hip).  part: 2 * tc2f_tiles(N)
 // doubles per parity; state: 8 ints per parity ([0] countdown, [1] done,

@@ -160,42 +160,6 @@ __global__ __launch_bounds__(256) void gersh_final_kernel(const double* red, int
     }
 }
 
-// X0 = (hi I - F) / (hi - lo): spectrum mapped into [0, 1], reversed.
-__global__ void tc2_init_kernel(const double* F, const double* bounds, int N, double* X) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
-    if (c >= N) return;
-    double lo = bounds[0], hi = bounds[1], s = 1.0 / (hi - lo);
-    int64_t i = (int64_t)r * N + c;
-    X[i] = ((r == c ? hi : 0.0) - F[i]) * s;
-}
-
-__global__ __launch_bounds__(1024) void traces_kernel(const double* X, const double* X2, int N, double* tr) {
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < N; i += 1024) {
-        a += X[(int64_t)i * N + i];
-        b += X2[(int64_t)i * N + i];
-    }
-    __shared__ double sa[16], sb[16];
-    for (int o = 32; o > 0; o >>= 1) { a += __shfl_down(a, o); b += __shfl_down(b, o); }
-    if ((threadIdx.x & 63) == 0) { sa[threadIdx.x >> 6] = a; sb[threadIdx.x >> 6] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        a = 0.0; b = 0.0;
-        for (int i = 0; i < 16; ++i) { a += sa[i]; b += sb[i]; }
-        tr[0] = a;
-        tr[1] = b;
-        tr[2] = a - b;   // idempotency measure tr(X - X^2)
-    }
-}
-
-// TC2 step: X <- X^2 if that moves the trace closer to n_occ, else 2X - X^2.
-__global__ void tc2_update_kernel(double* X, const double* X2, const double* tr, int n_occ, int64_t n) {
-    const double t1 = tr[0], t2 = tr[1];
-    const bool sq = fabs(t2 - n_occ) < fabs(2.0 * t1 - t2 - n_occ);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        X[i] = sq ? X2[i] : 2.0 * X[i] - X2[i];
-}
-
 // Counter-based pseudo-random values in [-1, 1) (a 32-bit integer hash of
 // the element index); any full-rank block serves as a subspace start.
 __global__ void hash_kernel(double* R, int64_t n, uint32_t seed) {
@@ -287,18 +251,6 @@ hipError_t gershgorin(const double* F, int N, double* bounds, double* red, hipSt
     gersh_rows_kernel<<<(N + 3) / 4, 256, 0, st>>>(F, N, red);
     RI_TRY(hipGetLastError());
     gersh_final_kernel<<<1, 256, 0, st>>>(red, N, bounds);
-    return hipGetLastError();
-}
-hipError_t tc2_init(const double* F, const double* bounds, int N, double* X, hipStream_t st) {
-    tc2_init_kernel<<<dim3((N + 255) / 256, N), 256, 0, st>>>(F, bounds, N, X);
-    return hipGetLastError();
-}
-hipError_t traces(const double* X, const double* X2, int N, double* tr, hipStream_t st) {
-    traces_kernel<<<1, 1024, 0, st>>>(X, X2, N, tr);
-    return hipGetLastError();
-}
-hipError_t tc2_update(double* X, const double* X2, const double* tr, int n_occ, int64_t n, hipStream_t st) {
-    tc2_update_kernel<<<nb(n), 256, 0, st>>>(X, X2, tr, n_occ, n);
     return hipGetLastError();
 }
 hipError_t hash_matrix(double* R, int64_t n, uint32_t seed, hipStream_t st) {

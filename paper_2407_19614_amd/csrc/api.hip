@@ -73,10 +73,11 @@ struct BuildWS { int32_t* counts; int64_t* offsets; };
 BuildWS carve_build(Arena& a, int N) { return {a.take<int32_t>(N), a.take<int64_t>(N + 1)}; }
 
 constexpr int64_t BC_CHUNK = 8192;
-struct MetricWS { double* dinv; int* bad; int32_t* map; double* tmp; };
+struct MetricWS { double* dinv; double* band; int* bad; int32_t* map; double* tmp; };
 MetricWS carve_metric(Arena& a, int N, int n_aux, int64_t n_pairs) {
     MetricWS w;
     w.dinv = a.take<double>((int64_t)((n_aux + 63) / 64) * 4096);
+    w.band = a.take<double>((int64_t)((n_aux + 63) / 64) * 4 * 4096);
     w.bad = a.take<int>(1);
     w.map = a.take<int32_t>((int64_t)N * N);
     w.tmp = nullptr;
@@ -504,9 +505,40 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
     MetricWS w = carve_metric(a, N, na, n_pairs);
     if (!a.ok()) return RI_E_WORKSPACE;
     *bad_pivot = -1;
+    // L^{-1} and the packing of each block of B rows run on the side stream:
+    // each block step of L^{-1} as soon as the Cholesky has made its block
+    // column final (beside the chain of diagonal factorisations, which keeps
+    // only a few CUs busy), each packing once the triangular solve has
+    // finished its rows (the solve is bound by MFMA throughput, the packing
+    // by memory bandwidth).  Small problems keep one stream: many callers'
+    // setups, as the batched workload's, would otherwise share the one side
+    // stream.
+    struct Events {
+        std::vector<hipEvent_t> e;
+        ~Events() {
+            for (hipEvent_t x : e) (void)hipEventDestroy(x);
+        }
+    } evs;
     HIPC(ri::metric(sys, L, st));
     HIPC(ri::fill_i32(w.bad, INT_MAX, 1, st));
-    HIPC(ri::cholesky_inv(L, na, na, nullptr, na, w.dinv, w.bad, st));
+    Fork fk;
+    const bool side = (int64_t)na * n_pairs >= ri::GJ_SIDE_MIN && fk.open(st);
+    hipStream_t ss = side ? fk.side : st;
+    // the side stream waits for everything enqueued on st so far
+    auto side_waits = [&]() -> hipError_t {
+        if (!side) return hipSuccess;
+        hipEvent_t e = nullptr;
+        RI_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        evs.e.push_back(e);
+        RI_TRY(hipEventRecord(e, st));
+        return hipStreamWaitEvent(ss, e, 0);
+    };
+    HIPC(ri::tri_inverse_begin(Linv, na, na, ss));
+    auto inverse_step = [&](int k) -> hipError_t {
+        RI_TRY(side_waits());
+        return ri::tri_inverse_steps(L, na, na, w.dinv, Linv, na, k, k + 1, ss);
+    };
+    HIPC(ri::cholesky_inv(L, na, na, nullptr, na, w.dinv, w.bad, st, inverse_step));
     int bad = INT_MAX;
     HIPC(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
@@ -514,40 +546,23 @@ int32_t ri_metric_factor(const ri_system* sys, const int32_t* pairs, int64_t n_p
         *bad_pivot = bad;
         return RI_E_NOT_PD;
     }
-    // L^{-1}, and the packing of each block of B rows once the triangular solve
-    // has finished them, run on the side stream beside the solve: the solve is
-    // bound by MFMA throughput, the packing by memory bandwidth.
-    // (Small problems keep one stream: many callers' setups, as the batched
-    // workload's, would otherwise share the one side stream.)
-    Fork fk;
-    const bool side = (int64_t)na * n_pairs >= ri::GJ_SIDE_MIN && fk.open(st);
-    hipStream_t ss = side ? fk.side : st;
-    HIPC(ri::tri_inverse(L, na, na, w.dinv, Linv, na, ss));
     if (B) HIPC(ri::pair_map(pairs, n_pairs, N, w.map, st));
-    struct Events {
-        std::vector<hipEvent_t> e;
-        ~Events() {
-            for (hipEvent_t x : e) (void)hipEventDestroy(x);
-        }
-    } evs;
     const int64_t b_row = B ? (int64_t)ri_packed_b_bytes(N, 1, prec) : 0;   // bytes of one auxiliary's packed tiles
     auto pack_rows = [&](int r0, int r1) -> hipError_t {
         if (!B) return hipSuccess;
-        if (side) {
-            hipEvent_t e = nullptr;
-            RI_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            evs.e.push_back(e);
-            RI_TRY(hipEventRecord(e, st));
-            RI_TRY(hipStreamWaitEvent(ss, e, 0));
-        }
+        RI_TRY(side_waits());
         const double* rows = T + (int64_t)r0 * n_pairs;
         void* out = (char*)B + r0 * b_row;
         return is_bf16(prec) ? ri::pack_b_bf16(rows, n_pairs, w.map, N, r1 - r0, out, prec, ss)
                              : ri::pack_b(rows, n_pairs, w.map, N, r1 - r0, out, prec, ss);
     };
     // Bc = L^{-1} T by recursive blocked forward substitution, in place over T.
-    if (n_pairs > 0) HIPC(ri::trsm_rec(L, na, na, w.dinv, T, (int)n_pairs, n_pairs, st, 0, pack_rows));
-    else HIPC(pack_rows(0, na));
+    if (n_pairs > 0) {
+        HIPC(ri::trsm_band(L, na, na, w.dinv, w.band, st));
+        HIPC(ri::trsm_rec(L, na, na, w.band, T, (int)n_pairs, n_pairs, st, 0, pack_rows));
+    } else {
+        HIPC(pack_rows(0, na));
+    }
     HIPC(fk.close());
     return RI_OK;
 }

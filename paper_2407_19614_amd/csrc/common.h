@@ -1,5 +1,6 @@
 // Internal declarations shared by the libri HIP sources (gfx950 only).
 #pragma once
+#include <functional>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
@@ -7,6 +8,7 @@
 #include "../../include/ri.h"
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 // LDS destination operand of __builtin_amdgcn_global_load_lds
 typedef __attribute__((address_space(3))) void* lds_void_t;
@@ -160,14 +162,24 @@ hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha,
 // In-place Cholesky A = L L^T (lower; upper triangle zeroed) of an n x n
 // matrix, plus Linv = L^{-1} when Linv != nullptr.  dwork >= ceil(n/64)*4096
 // doubles.  The first non-positive pivot index is atomically min-ed into
-// *d_bad (device int, caller initialises it to INT_MAX).
+// *d_bad (device int, caller initialises it to INT_MAX).  block_done(k), if
+// given, is called once block column k of L (rows k*64 onward) and its
+// diagonal-block inverse in dwork are enqueued as final on s, before the
+// trailing update of step k.
 hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi,
-                        double* dwork, int* d_bad, hipStream_t s);
+                        double* dwork, int* d_bad, hipStream_t s,
+                        const std::function<hipError_t(int)>& block_done = nullptr);
 
 // Linv = L^{-1} from the factor and its diagonal-block inverses (as left by
 // cholesky_inv with Linv == nullptr).
 hipError_t tri_inverse(const double* L, int n, int64_t lda, const double* Dinv, double* Linv, int64_t ldi,
                        hipStream_t s);
+// The same in parts, for callers that spread the launches out: begin sets
+// Linv to the identity, then steps k0 .. k1-1 (of ceil(n/64)) run in order,
+// all on one stream.
+hipError_t tri_inverse_begin(double* Linv, int n, int64_t ldi, hipStream_t s);
+hipError_t tri_inverse_steps(const double* L, int n, int64_t lda, const double* Dinv, double* Linv, int64_t ldi,
+                             int k0, int k1, hipStream_t s);
 
 hipError_t fill(double* p, double v, int64_t n, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

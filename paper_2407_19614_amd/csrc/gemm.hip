@@ -88,6 +88,31 @@ __device__ __forceinline__ void gemm_tile64(int M, int N, int K, double alpha, c
             acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
         }
     }
+    // With beta != 0 every C value of the tile is loaded before the first
+    // store (from addresses clamped into the matrix, so without branches):
+    // loads placed after stores to C would each wait out a full memory
+    // latency, since the compiler cannot prove the addresses distinct.
+    double cv[2][2][4];
+    if (beta != 0.0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gm = min(m0 + wm + 16 * i + 4 * r + lk, M - 1), gn = min(n0 + wn + 16 * j + li, N - 1);
+                    cv[i][j][r] = C[(int64_t)gm * ldc + gn];
+                }
+    }
+    // all results before the first store: stores count against the same
+    // wait counter as the loads
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                cv[i][j][r] = alpha * acc[i][j][r] + (beta != 0.0 ? beta * cv[i][j][r] : 0.0);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -96,10 +121,8 @@ __device__ __forceinline__ void gemm_tile64(int M, int N, int K, double alpha, c
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
                 if (gm < M && gn < N && !(sym && gm > gn)) {
-                    double* c = C + (int64_t)gm * ldc + gn;
-                    double v = alpha * acc[i][j][r];
-                    *c = (beta == 0.0) ? v : v + beta * *c;
-                    if (sym && gm != gn) C[(int64_t)gn * ldc + gm] = *c;
+                    C[(int64_t)gm * ldc + gn] = cv[i][j][r];
+                    if (sym && gm != gn) C[(int64_t)gn * ldc + gm] = cv[i][j][r];
                 }
             }
 }
@@ -217,20 +240,38 @@ __device__ __forceinline__ void gemm_tile128(int M, int N, int K, double alpha, 
                 for (int j = 0; j < 4; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
         }
     }
+    // Epilogue by 16-row slices: with beta != 0 the slice's 16 C values are
+    // loaded (clamped addresses, no branches) before its stores, so each
+    // slice waits out one memory latency rather than one per element.
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+        double cv[4][4];
+        if (beta != 0.0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gm = min(m0 + wm + 16 * i + 4 * r + lk, M - 1), gn = min(n0 + wn + 16 * j + li, N - 1);
+                    cv[j][r] = C[(int64_t)gm * ldc + gn];
+                }
+        }
+        // all 16 results before the first store: stores count against the
+        // same wait counter as the loads
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cv[j][r] = alpha * acc[i][j][r] + (beta != 0.0 ? beta * cv[j][r] : 0.0);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int gm = m0 + wm + 16 * i + 4 * r + lk, gn = n0 + wn + 16 * j + li;
                 if (gm < M && gn < N && !(sym && gm > gn)) {
-                    double* c = C + (int64_t)gm * ldc + gn;
-                    double v = alpha * acc[i][j][r];
-                    *c = (beta == 0.0) ? v : v + beta * *c;
-                    if (sym && gm != gn) C[(int64_t)gn * ldc + gm] = *c;
+                    C[(int64_t)gm * ldc + gn] = cv[j][r];
+                    if (sym && gm != gn) C[(int64_t)gn * ldc + gm] = cv[j][r];
                 }
             }
+    }
 }
 
 template <bool TA, bool TB, int SBK = BK>
@@ -339,6 +380,133 @@ __global__ __launch_bounds__(1024) void maxabs_kernel(const double* x, int64_t n
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// Band of the factor in the leaf kernel's operand order: slot (k, d) of
+// P (4096 doubles each, 4 slots per 64-row block k) holds Dinv_k for d = 0
+// and -L_{k+d, k} (zero beyond row n) for d = 1..3, element
+// ((4 q + t) 64 + l) 4 + u being entry (16 q + l % 16, 16 t + 4 u + l / 16)
+// of the 64 x 64 block: lane l's four A operands of one 16 x 16 MFMA slice
+// pass are contiguous, and the 64 lanes read 2 KB in one run.
+__global__ void trsm_band_kernel(const double* __restrict__ L, int n, int64_t lda, const double* __restrict__ Dinv,
+                                 double* __restrict__ P) {
+    const int nb = (n + 63) / 64;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nb * 4 * 4096) return;
+    const int slot = (int)(e >> 12), k = slot >> 2, d = slot & 3, w = (int)(e & 4095);
+    if (k + d >= nb) return;
+    const int u = w & 3, l = (w >> 2) & 63, t = (w >> 8) & 3, q = w >> 10;
+    const int row = 16 * q + (l & 15), col = 16 * t + 4 * u + (l >> 4);
+    double v;
+    if (d == 0) {
+        v = Dinv[(int64_t)k * 4096 + row * 64 + col];
+    } else {
+        const int gr = 64 * (k + d) + row;
+        v = gr < n ? -L[(int64_t)gr * lda + 64 * k + col] : 0.0;
+    }
+    P[e] = v;
+}
+
+// Leaf of the blocked forward substitution B <- L^{-1} B for n <= 64 NB rows,
+// held in registers: each wave owns 16 columns of B (n x 16 as 4 NB MFMA
+// accumulator tiles, zero beyond row n) and runs the 64-row block steps
+// X_k = Dinv_k B_k, then B_m -= L_mk X_k for every block m below k, with
+// FP64 MFMA, reading the band P (above) straight from memory: every wave
+// reads the same slots, so they are cache hits.  The reduction index of each
+// MFMA is k = 16 t + 4 s + g for lane group g and slice s: an accumulator
+// tile in the C layout (element s of lane (c, g) holds row 4s + g of column
+// c) is then already the B operand of the four slices over its 16 rows.
+// The work runs in chunks of 16 MFMAs (one 16-deep slice t against the four
+// 16-row tiles of one block, four independent accumulators), each chunk's
+// 16 A values loaded one chunk ahead.  Dinv_k carries identity padding
+// beyond the last row of a ragged final block and the band is zero there,
+// so padded rows stay zero.  B is read and written once.
+template <int NB>
+__global__ __launch_bounds__(256, 2) void trsm_leaf_kernel(const double* __restrict__ P, double* __restrict__ B,
+                                                           int n, int ncols, int64_t ldb) {
+    constexpr int NT = 4 * NB;
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int c0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (c0 >= ncols) return;
+    const int col = min(c0 + r, ncols - 1);
+    d4_t acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * j + 4 * i + g;
+            const double v = B[(int64_t)min(row, n - 1) * ldb + col];
+            acc[j][i] = row < n ? v : 0.0;
+        }
+    // A values of chunk (kb, mb, t): block mb's four row tiles against the
+    // 16-deep slice t of block kb, from band slot (kb, mb - kb).  Buffer
+    // loads: the lane offset is fixed and the chunk's offset is a scalar, so
+    // no vector address is formed (or kept) per chunk.
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(P), (short)0, NB * 4 * 4096 * 8, 0x00020000);
+    const int voff = lane * 32;
+    auto fetch = [&](int kb, int mb, int t, double (&a)[4][4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int so = ((kb * 4 + (mb - kb)) * 4096 + (4 * q + t) * 256) * 8;
+            const d2_t lo = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so, 0));
+            const d2_t hi = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so + 16, 0));
+            a[q][0] = lo[0]; a[q][1] = lo[1]; a[q][2] = hi[0]; a[q][3] = hi[1];
+        }
+    };
+    double cur[4][4], nxt[4][4];
+    fetch(0, 0, 0, cur);
+    d4_t x[4];
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mb = kb; mb < NB; ++mb) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int nkb = kb, nmb = mb, ntt = t + 1;
+                if (ntt == 4) {
+                    ntt = 0;
+                    if (++nmb == NB) nmb = ++nkb;
+                }
+                if (nkb < NB) fetch(nkb, nmb, ntt, nxt);
+                if (mb == kb) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) x[q] = mfma_f64(cur[q][u], acc[4 * kb + t][u], x[q]);
+                    if (t == 3) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[4 * kb + q] = x[q];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc[4 * mb + q] = mfma_f64(cur[q][u], acc[4 * kb + t][u], acc[4 * mb + q]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) cur[q][u] = nxt[q][u];
+            }
+        }
+    }
+    // The store's lane indices pass through an empty asm so that they are
+    // formed here, not kept live (from the loads) across the whole solve.
+    int gs = g, cs = c0 + r;
+    asm volatile("" : "+v"(gs), "+v"(cs));
+    if (cs < ncols) {
+        double* bp = B + (int64_t)gs * ldb + cs;
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (16 * j + 4 * i + gs < n) bp[(int64_t)(16 * j + 4 * i) * ldb] = acc[j][i];
+    }
+}
+
 inline unsigned nblk(int64_t n, int b = 256) {
     int64_t g = (n + b - 1) / b;
     return (unsigned)(g > 65535 * 16 ? 65535 * 16 : (g < 1 ? 1 : g));
@@ -392,7 +560,7 @@ hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const d
 }
 
 hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi, double* dwork,
-                        int* d_bad, hipStream_t s) {
+                        int* d_bad, hipStream_t s, const std::function<hipError_t(int)>& block_done) {
     const int nb = (n + 63) / 64;
     for (int k = 0; k < nb; ++k) {
         const int o = k * 64, w = min(64, n - o), rest = n - o - w;
@@ -403,6 +571,10 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
             // panel <- panel * Dinv^T  (rows below the diagonal block)
             RI_TRY(gemm_f64(false, true, rest, w, w, 1.0, panel, lda, 0, dwork + (int64_t)k * 4096, 64, 0,
                             0.0, panel, lda, 0, 1, 0, 0, s));
+        }
+        if (block_done) RI_TRY(block_done(k));
+        if (rest > 0) {
+            double* panel = A + (int64_t)(o + w) * lda + o;
             // trailing lower update
             double* trail = A + (int64_t)(o + w) * lda + o + w;
             RI_TRY(gemm_f64(false, true, rest, rest, w, -1.0, panel, lda, 0, panel, lda, 0, 1.0, trail,
@@ -415,13 +587,15 @@ hipError_t cholesky_inv(double* A, int n, int64_t lda, double* Linv, int64_t ldi
     return tri_inverse(A, n, lda, dwork, Linv, ldi, s);
 }
 
-hipError_t tri_inverse(const double* A, int n, int64_t lda, const double* dwork, double* Linv, int64_t ldi,
-                       hipStream_t s) {
-    const int nb = (n + 63) / 64;
-    // Solve L X = I by blocks: X_k = Dinv_k (I_k - L_{k,<k} X_{<k}).
+hipError_t tri_inverse_begin(double* Linv, int n, int64_t ldi, hipStream_t s) {
     identity_kernel<<<nblk((int64_t)n * n), 256, 0, s>>>(Linv, n, ldi);
-    RI_TRY(hipGetLastError());
-    for (int k = 0; k < nb; ++k) {
+    return hipGetLastError();
+}
+
+hipError_t tri_inverse_steps(const double* A, int n, int64_t lda, const double* dwork, double* Linv, int64_t ldi,
+                             int k0, int k1, hipStream_t s) {
+    // Solve L X = I by blocks: X_k = Dinv_k (I_k - L_{k,<k} X_{<k}).
+    for (int k = k0; k < k1; ++k) {
         const int o = k * 64, w = min(64, n - o), rest = n - o - w, cols = o + w;
         double* Xk = Linv + (int64_t)o * ldi;
         RI_TRY(gemm_f64(false, false, w, cols, w, 1.0, dwork + (int64_t)k * 4096, 64, 0, Xk, ldi, 0, 0.0,
@@ -433,31 +607,47 @@ hipError_t tri_inverse(const double* A, int n, int64_t lda, const double* dwork,
     return hipSuccess;
 }
 
+hipError_t tri_inverse(const double* A, int n, int64_t lda, const double* dwork, double* Linv, int64_t ldi,
+                       hipStream_t s) {
+    RI_TRY(tri_inverse_begin(Linv, n, ldi, s));
+    return tri_inverse_steps(A, n, lda, dwork, Linv, ldi, 0, (n + 63) / 64, s);
+}
+
 // Recursive form: B1 = L11^{-1} B1, B2 -= L21 B1, B2 = L22^{-1} B2, splitting
 // at a multiple of 64 near the middle, so that half the flops run in one GEMM
 // with K = n/2, a quarter in two with K = n/4, and so on; blocks of at most
-// TRSM_LEAF rows use the 64-row scheme below.  done(r0, r1) is called (in
-// stream order) once rows r0 .. r1 of B are final.
+// TRSM_LEAF rows are solved in one launch of the register-resident leaf
+// kernel.  done(r0, r1) is called (in stream order) once rows r0 .. r1 of B
+// are final.
 constexpr int TRSM_LEAF = 256;
-hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols, int64_t ldb,
+static_assert(TRSM_LEAF <= 256, "the leaf kernel holds at most four 64-row blocks");
+hipError_t trsm_band(const double* L, int n, int64_t lda, const double* Dinv, double* P, hipStream_t s) {
+    const int64_t total = (int64_t)((n + 63) / 64) * 4 * 4096;
+    trsm_band_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(L, n, lda, Dinv, P);
+    return hipGetLastError();
+}
+
+hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* P, double* B, int ncols, int64_t ldb,
                     hipStream_t s, int r0, const std::function<hipError_t(int, int)>& done) {
+    if (n <= 0) return hipSuccess;
     if (n <= TRSM_LEAF) {
-        for (int k0 = 0; k0 < n; k0 += 64) {
-            const int w = min(64, n - k0), k1 = k0 + w;
-            double* Bk = B + (int64_t)k0 * ldb;
-            RI_TRY(gemm_f64(false, false, w, ncols, w, 1.0, Dinv + (int64_t)(k0 / 64) * 4096, 64, 0, Bk, ldb, 0,
-                            0.0, Bk, ldb, 0, 1, 0, 0, s));
-            if (k1 < n)
-                RI_TRY(gemm_f64(false, false, n - k1, ncols, w, -1.0, L + (int64_t)k1 * lda + k0, lda, 0, Bk, ldb, 0,
-                                1.0, B + (int64_t)k1 * ldb, ldb, 0, 1, 0, 0, s));
+        if (ncols > 0) {
+            const unsigned grid = (unsigned)((ncols + 63) / 64);
+            switch ((n + 63) / 64) {
+                case 1: trsm_leaf_kernel<1><<<grid, 256, 0, s>>>(P, B, n, ncols, ldb); break;
+                case 2: trsm_leaf_kernel<2><<<grid, 256, 0, s>>>(P, B, n, ncols, ldb); break;
+                case 3: trsm_leaf_kernel<3><<<grid, 256, 0, s>>>(P, B, n, ncols, ldb); break;
+                default: trsm_leaf_kernel<4><<<grid, 256, 0, s>>>(P, B, n, ncols, ldb); break;
+            }
+            RI_TRY(hipGetLastError());
         }
         return done ? done(r0, r0 + n) : hipSuccess;
     }
     const int n1 = max(64, n / 2 / 64 * 64), n2 = n - n1;
-    RI_TRY(trsm_rec(L, n1, lda, Dinv, B, ncols, ldb, s, r0, done));
+    RI_TRY(trsm_rec(L, n1, lda, P, B, ncols, ldb, s, r0, done));
     RI_TRY(gemm_f64(false, false, n2, ncols, n1, -1.0, L + (int64_t)n1 * lda, lda, 0, B, ldb, 0, 1.0,
                     B + (int64_t)n1 * ldb, ldb, 0, 1, 0, 0, s));
-    return trsm_rec(L + (int64_t)n1 * lda + n1, n2, lda, Dinv + (int64_t)(n1 / 64) * 4096, B + (int64_t)n1 * ldb,
+    return trsm_rec(L + (int64_t)n1 * lda + n1, n2, lda, P + (int64_t)(n1 / 64) * 4 * 4096, B + (int64_t)n1 * ldb,
                     ncols, ldb, s, r0 + n1, done);
 }
 

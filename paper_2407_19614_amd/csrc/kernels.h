@@ -6,9 +6,15 @@
 
 namespace ri {
 
-// Recursive in-place B <- L^{-1} B (see gemm.hip); done(r0, r1) runs in stream
-// order once rows r0 .. r1 of B are final (r0 offsets the row numbers).
-hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* Dinv, double* B, int ncols, int64_t ldb,
+// Band of the factor for the solve's leaves: 4 ceil(n/64) slots of 4096
+// doubles (Dinv_k and -L_{k+d,k}, d = 1..3, in MFMA operand order), from the
+// factor L and the diagonal-block inverses Dinv left by cholesky_inv.
+hipError_t trsm_band(const double* L, int n, int64_t lda, const double* Dinv, double* P, hipStream_t s);
+
+// Recursive in-place B <- L^{-1} B (see gemm.hip) with P from trsm_band;
+// done(r0, r1) runs in stream order once rows r0 .. r1 of B are final (r0
+// offsets the row numbers).
+hipError_t trsm_rec(const double* L, int n, int64_t lda, const double* P, double* B, int ncols, int64_t ldb,
                     hipStream_t s, int r0, const std::function<hipError_t(int, int)>& done);
 
 // ---- integrals

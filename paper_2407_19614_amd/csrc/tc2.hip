@@ -17,23 +17,42 @@
 // doubles it on the other, so the two steps take a summed distance of
 // 1e-11 n_occ down to rounding.)
 //
-// Layout of a step: 64 x 64 output tiles, one workgroup of 8 waves each.
-// Waves 0-3 and 4-7 take the two halves of the reduction index (split-K
-// inside the workgroup), each half staging 16-deep slices of the tile's
-// row panel X[64I .., :] and column panel X[64J .., :] (rows of X, by
-// symmetry) through a double-buffered LDS ring with one barrier per slice;
-// each wave owns a 32 x 32 quadrant (2 x 2 FP64 MFMA tiles).  The second
-// half's accumulators are added through LDS, then the update, the output
-// write and the partial sums run in the epilogue.
+// Layout of a step: X^2 is symmetric, so only the upper 48 x 48 output tiles
+// are formed (for N = 1000, 231 of them: one workgroup per CU) and each is
+// written with its mirror, which keeps X exactly symmetric by construction.
+// The four waves of a workgroup take the four quarters of the reduction
+// index; each wave owns the whole tile as 3 x 3 FP64 MFMA tiles and reads
+// its operands straight from X: the A operand of row tile i is
+// X[k][m0 + 16 i + ..] (a row of X, by symmetry) and the B operand of
+// column tile j is X[k][n0 + 16 j + ..], so the 16 lanes of each group read
+// 16 consecutive doubles.  Buffer loads return zero past the end of X (rows
+// k >= N), and the operands of the k-step four ahead are in flight while a
+// step's 9 MFMAs run.  The four
+// partial tiles are summed through LDS in one fixed order, then the update,
+// the tile and mirror writes and the partial sums run in the epilogue.
 #include "kernels.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace {
 
-constexpr int TT = 64;        // output tile edge
-constexpr int SK = 16;        // slice depth
+constexpr int TT = 48;        // output tile edge (3 MFMA tiles)
 constexpr int LDT = TT + 1;   // padded LDS row
+constexpr int PD = 4;         // k-steps of operands in flight
+
+__host__ __device__ inline int n_tiles_edge(int N) { return (N + TT - 1) / TT; }
+
+// upper tile t (row-major over I <= J) of an nt x nt tiling
+__device__ inline void upper_tile48(int t, int nt, int& I, int& J) {
+    int i = 0, rem = t;
+    while (rem >= nt - i) {
+        rem -= nt - i;
+        ++i;
+    }
+    I = i;
+    J = i + rem;
+}
 
 // state fields (int[8] per parity buffer)
 constexpr int S_CD = 0, S_DONE = 1, S_STEPS = 2, S_LAST = 3;
@@ -51,23 +70,28 @@ __device__ __forceinline__ double wg_sum_fixed(double v, double* sh) {
     return r;
 }
 
-// X0 = (hi I - (F + F^T)/2) / (hi - lo) on 64 x 64 tiles, with each tile's
-// partial sums of tr X0 and sum X0_ij^2, and the purification state reset.
+// X0 = (hi I - (F + F^T)/2) / (hi - lo) on the upper 48 x 48 tiles (each
+// written with its mirror), with each tile's partial sums of tr X0 and
+// sum X0_ij^2 over the entries it stands for, and the purification state
+// reset.
 __global__ __launch_bounds__(256) void tc2f_init_kernel(const double* __restrict__ F,
                                                         const double* __restrict__ bounds, int N,
                                                         double* __restrict__ X, double* __restrict__ part,
                                                         int* __restrict__ st) {
     __shared__ double sh[4];
-    const int nt = (N + TT - 1) / TT, I = blockIdx.x / nt, J = blockIdx.x % nt;
+    const int nt = n_tiles_edge(N);
+    int I, J;
+    upper_tile48(blockIdx.x, nt, I, J);
     const double lo = bounds[0], hi = bounds[1], s = 1.0 / (hi - lo);
     double f2 = 0.0, tr = 0.0;
     for (int e = threadIdx.x; e < TT * TT; e += 256) {
-        const int r = TT * I + (e >> 6), c = TT * J + (e & 63);
+        const int r = TT * I + e / TT, c = TT * J + e % TT;
         if (r < N && c < N) {
             const double fs = 0.5 * (F[(int64_t)r * N + c] + F[(int64_t)c * N + r]);
             const double x = ((r == c ? hi : 0.0) - fs) * s;
             X[(int64_t)r * N + c] = x;
-            f2 += x * x;
+            if (I != J) X[(int64_t)c * N + r] = x;
+            f2 += (I == J ? 1.0 : 2.0) * x * x;
             if (r == c) tr += x;
         }
     }
@@ -80,27 +104,74 @@ __global__ __launch_bounds__(256) void tc2f_init_kernel(const double* __restrict
     if (blockIdx.x == 0 && threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == S_CD ? -1 : 0;
 }
 
-__global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict__ X, double* __restrict__ Y, int N,
+// One wave's share of a 48 x 48 tile of X^2: k-steps kbeg + 4 s, s < nks,
+// as 3 x 3 MFMA tiles (DIAG: the row and column panels coincide).  Buffer
+// loads over X with the whole offset in the lane's offset, so that rows
+// k >= N read as zero (range check) and the prefetch past the last k-step
+// stays inside the check.
+template <bool DIAG>
+__device__ __forceinline__ void tc2_accumulate(const double* X, int N, int kbeg, int nks, int m0, int n0, int r,
+                                               int g, d4_t (&acc)[3][3]) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X), (short)0, N * N * 8, 0x00020000);
+    int vA[3], vB[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        vA[i] = ((kbeg + g) * N + m0 + 16 * i + r) * 8;
+        vB[i] = ((kbeg + g) * N + n0 + 16 * i + r) * 8;
+    }
+    const int step = 4 * N * 8;
+    auto ld = [&](int s, double (&pa)[3], double (&pb)[3]) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            pa[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vA[i] + s * step, 0, 0));
+        if (!DIAG) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                pb[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vB[i] + s * step, 0, 0));
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    double pa[PD][3], pb[PD][3];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) ld(p, pa[p], pb[p]);
+    for (int s0 = 0; s0 < nks; s0 += PD) {
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+            if (s0 + p < nks) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) acc[i][j] = mfma_f64(pa[p][i], DIAG ? pa[p][j] : pb[p][j], acc[i][j]);
+                ld(s0 + p + PD, pa[p], pb[p]);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void tc2f_step_kernel(const double* __restrict__ X, double* __restrict__ Y, int N,
                                                         int n_occ, const double* __restrict__ part_in,
                                                         double* __restrict__ part_out, const int* __restrict__ st_in,
                                                         int* __restrict__ st_out, int out_id) {
-    __shared__ double sh[8];
-    __shared__ double As[2][2][SK][LDT];   // [half][stage][k][row]
-    __shared__ double Bs[2][2][SK][LDT];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, half = wave >> 2, w4 = wave & 3;
-    const int nt = (N + TT - 1) / TT, tiles = nt * nt;
+    __shared__ double sh[4];
+    __shared__ double red[4][TT][LDT];   // the four waves' partial tiles
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nt = n_tiles_edge(N), tiles = nt * (nt + 1) / 2;
     if (st_in[S_DONE]) {
         if (blockIdx.x == 0 && tid < 8) st_out[tid] = st_in[tid];
         return;
     }
     // tr X and tr X^2 from the previous step's partial sums (same order everywhere)
     double a = 0.0, b = 0.0;
-    for (int i = tid; i < tiles; i += 512) {
+    for (int i = tid; i < tiles; i += 256) {
         a += part_in[2 * i];
         b += part_in[2 * i + 1];
     }
-    const double t1 = wg_sum_fixed<512>(a, sh);
-    const double t2 = wg_sum_fixed<512>(b, sh);
+    const double t1 = wg_sum_fixed<256>(a, sh);
+    const double t2 = wg_sum_fixed<256>(b, sh);
     int cd = st_in[S_CD];
     if (cd < 0) {
         if (fabs(t1 - t2) < 1e-11 * (double)max(1, n_occ)) cd = 1;
@@ -116,108 +187,64 @@ __global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict
         for (int k = 4; k < 8; ++k) st_out[k] = st_in[k];
     }
     const int L = xcd_remap(blockIdx.x, tiles);
-    const int m0 = TT * (L / nt), n0 = TT * (L % nt);
-    // reduction halves, rounded to whole slices
-    const int Kh = min(N, ((N + 1) / 2 + SK - 1) / SK * SK);
-    const int kb = half ? Kh : 0, ke = half ? N : Kh;
-    const int nsl = (max(Kh, N - Kh) + SK - 1) / SK;   // the same count in both halves
-    // loader lanes: 256 per half; element gt + 256 i of the 64 x SK slice is
-    // row (gt + 256 i) / SK, k = gt % SK, so SK consecutive lanes read one
-    // row's SK consecutive doubles (whole cache lines per instruction)
-    constexpr int KQ = SK / 4, RS = 256 / SK;
-    const int gt = tid & 255, lk0 = gt % SK, lr0 = gt / SK;
-    double ra[KQ], rb[KQ];
-    // unconditional loads from clamped addresses, zeroed by a select only
-    // when they are stored (no branch around each load, and no wait for the
-    // load before the MFMAs of the current slice)
-    bool kin = false;
-    auto load = [&](int s) {
-        const int k = kb + s * SK + lk0;
-        kin = k < ke;
-        const int kc = min(k, N - 1);
+    int I, J;
+    upper_tile48(L, nt, I, J);
+    const int m0 = TT * I, n0 = TT * J;
+    const bool diag = I == J;
+    // this wave's quarter of the reduction index, in whole 4-deep k-steps
+    const int Kq = ((N + 3) / 4 + 3) / 4 * 4;
+    const int kbeg = wave * Kq, kend = min(N, kbeg + Kq), nks = max(0, (kend - kbeg + 3) / 4);
+    const int r = lane & 15, g = lane >> 4;
+    d4_t acc[3][3];
+    if (diag) tc2_accumulate<true>(X, N, kbeg, nks, m0, n0, r, g, acc);
+    else tc2_accumulate<false>(X, N, kbeg, nks, m0, n0, r, g, acc);
+    // partial tiles to LDS: element q of lane (c, g) in MFMA tile (i, j) is
+    // row 16 i + 4 q + g, column 16 j + c
 #pragma unroll
-        for (int i = 0; i < KQ; ++i) {
-            const int r = lr0 + RS * i;
-            ra[i] = X[(int64_t)min(m0 + r, N - 1) * N + kc];
-            rb[i] = X[(int64_t)min(n0 + r, N - 1) * N + kc];
-        }
-    };
-    auto store = [&](int stg) {
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int i = 0; i < KQ; ++i) {
-            const int r = lr0 + RS * i;
-            As[half][stg][lk0][r] = (kin && m0 + r < N) ? ra[i] : 0.0;
-            Bs[half][stg][lk0][r] = (kin && n0 + r < N) ? rb[i] : 0.0;
-        }
-    };
-    d4_t acc[2][2];
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-    const int wm = (w4 >> 1) * 32, wn = (w4 & 1) * 32, li = lane & 15, lk = lane >> 4;
-    load(0);
-    store(0);
+            for (int q = 0; q < 4; ++q) red[wave][16 * i + 4 * q + g][16 * j + r] = acc[i][j][q];
     __syncthreads();
-    for (int s = 0; s < nsl; ++s) {
-        const int cur = s & 1;
-        if (s + 1 < nsl) load(s + 1);
-        // operands of the next k-step are read from LDS before this step's
-        // MFMAs, so their latency hides under the MFMAs
-        double a0 = As[half][cur][lk][wm + li], a1 = As[half][cur][lk][wm + 16 + li];
-        double b0 = Bs[half][cur][lk][wn + li], b1 = Bs[half][cur][lk][wn + 16 + li];
+    // sum of the four quarters in one fixed order, the update, the tile's
+    // write (diagonal tiles: the upper triangle) and the partial sums
+    // (9 elements per thread; for 2X - X^2 the nine entries of X are loaded,
+    // from clamped addresses, before the first store)
+    constexpr int EP = TT * TT / 256;
+    static_assert(EP * 256 == TT * TT, "whole elements per thread");
+    double xo[EP];
+    if (!sq) {
 #pragma unroll
-        for (int kk = 0; kk < SK; kk += 4) {
-            double na0 = 0.0, na1 = 0.0, nb0 = 0.0, nb1 = 0.0;
-            if (kk + 4 < SK) {
-                na0 = As[half][cur][kk + 4 + lk][wm + li];
-                na1 = As[half][cur][kk + 4 + lk][wm + 16 + li];
-                nb0 = Bs[half][cur][kk + 4 + lk][wn + li];
-                nb1 = Bs[half][cur][kk + 4 + lk][wn + 16 + li];
-            }
-            __builtin_amdgcn_sched_barrier(0);   // keep those reads ahead of the MFMAs
-            acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-            acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-            acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-            acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
-            a0 = na0; a1 = na1; b0 = nb0; b1 = nb1;
+        for (int t = 0; t < EP; ++t) {
+            const int e = tid + 256 * t, gm = min(m0 + e / TT, N - 1), gn = min(n0 + e % TT, N - 1);
+            xo[t] = X[(int64_t)gm * N + gn];
         }
-        if (s + 1 < nsl) store(cur ^ 1);
-        __syncthreads();
     }
-    // second half's sums through LDS (the ring is free now: 4 x 16 rows of 65)
-    double (*R)[LDT] = reinterpret_cast<double (*)[LDT]>(&As[0][0][0][0]);
-    if (half == 1) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) R[wm + 16 * i + 4 * r + lk][wn + 16 * j + li] = acc[i][j][r];
-    }
-    __syncthreads();
     double f2 = 0.0, tr = 0.0;
-    if (half == 0) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int rr = wm + 16 * i + 4 * r + lk, cc = wn + 16 * j + li;
-                    const int gm = m0 + rr, gn = n0 + cc;
-                    if (gm < N && gn < N) {
-                        const double x2 = acc[i][j][r] + R[rr][cc];
-                        const int64_t idx = (int64_t)gm * N + gn;
-                        const double v = sq ? x2 : 2.0 * X[idx] - x2;
-                        Y[idx] = v;
-                        f2 += v * v;
-                        if (gm == gn) tr += v;
-                    }
-                }
+    for (int t = 0; t < EP; ++t) {
+        const int e = tid + 256 * t, rr = e / TT, cc = e % TT, gm = m0 + rr, gn = n0 + cc;
+        double v = 0.0;
+        if (gm < N && gn < N && (!diag || rr <= cc)) {
+            const double x2 = ((red[0][rr][cc] + red[1][rr][cc]) + red[2][rr][cc]) + red[3][rr][cc];
+            v = sq ? x2 : 2.0 * xo[t] - x2;
+            Y[(int64_t)gm * N + gn] = v;
+            f2 += (gm == gn ? 1.0 : 2.0) * v * v;
+            if (gm == gn) tr += v;
+        }
+        red[0][rr][cc] = v;   // each element is read and rewritten by one thread
     }
-    tr = wg_sum_fixed<512>(tr, sh);
-    f2 = wg_sum_fixed<512>(f2, sh);
+    __syncthreads();
+    // mirror: Y[n][m] = Y[m][n], read transposed from LDS so that the writes
+    // run along rows of Y
+#pragma unroll
+    for (int t = 0; t < EP; ++t) {
+        const int e = tid + 256 * t, cc = e / TT, rr = e % TT, gm = m0 + rr, gn = n0 + cc;
+        if (gm < N && gn < N && (diag ? rr < cc : true)) Y[(int64_t)gn * N + gm] = red[0][rr][cc];
+    }
+    tr = wg_sum_fixed<256>(tr, sh);
+    f2 = wg_sum_fixed<256>(f2, sh);
     if (tid == 0) {
         part_out[2 * L] = tr;
         part_out[2 * L + 1] = f2;
@@ -236,8 +263,8 @@ __global__ void tc2f_final_kernel(double* X, const double* Y, int64_t n, const i
 namespace ri {
 
 int tc2f_tiles(int N) {
-    const int nt = (N + TT - 1) / TT;
-    return nt * nt;
+    const int nt = n_tiles_edge(N);
+    return nt * (nt + 1) / 2;
 }
 
 hipError_t tc2f_init(const double* F, const double* bounds, int N, double* X, double* part, int* state,
@@ -248,7 +275,9 @@ hipError_t tc2f_init(const double* F, const double* bounds, int N, double* X, do
 
 hipError_t tc2f_step(const double* X, double* Y, int N, int n_occ, const double* part_in, double* part_out,
                      const int* st_in, int* st_out, int out_id, hipStream_t st) {
-    tc2f_step_kernel<<<tc2f_tiles(N), 512, 0, st>>>(X, Y, N, n_occ, part_in, part_out, st_in, st_out, out_id);
+    // buffer offsets into X, including the prefetch past the last k-step, are 32-bit
+    if ((int64_t)(N + 4 * PD + 8) * N * 8 > INT_MAX) return hipErrorInvalidValue;
+    tc2f_step_kernel<<<tc2f_tiles(N), 256, 0, st>>>(X, Y, N, n_occ, part_in, part_out, st_in, st_out, out_id);
     return hipGetLastError();
 }
 

@@ -118,7 +118,9 @@ def test_bf16_split_energy_and_gradient(ref, prec_name, final):
     pr = problem(s, prec)
     # with the final FP64 build the density's error enters the energy only to
     # second order, so the split iterations stop above their noise floor
-    tol = (1e-6, 3e-5) if final else (1e-9, 1e-6)
+    # (BF16X3's iteration energies carry ~1e-5 Eh of rounding noise: its energy
+    # test sits above that and the commutator test governs)
+    tol = ((1e-4 if prec_name == "BF16X3" else 1e-6), 3e-5) if final else (1e-9, 1e-6)
     r, *_ = pr.energy(tol_E=tol[0], tol_err=tol[1], max_iter=60, final_fp64=final)
     assert r["converged"]
     dE = abs(r["E_total"] - res.E)
@@ -153,7 +155,7 @@ def test_bf16_final_fp64_n400():
     for name, prec in (("BF16X3", P.BF16X3), ("BF16X6", P.BF16X6)):
         print(f"case: N=400 {name} + final fp64", flush=True)
         pb = problem(s4, prec)
-        rb, *_ = pb.energy(tol_E=1e-6, tol_err=3e-5, final_fp64=True)
+        rb, *_ = pb.energy(tol_E=1e-4 if name == "BF16X3" else 1e-6, tol_err=3e-5, final_fp64=True)
         dE = abs(rb["E_total"] - r64["E_total"])
         dg = np.abs(to_np(pb.gradient()) - g64).max()
         print(f"N=400 {name}: |dE|={dE:.2e} iters={rb['n_iter']} max|dg|={dg:.2e}", flush=True)

@@ -20,16 +20,16 @@
 // Layout of a step: X^2 is symmetric, so only the upper 48 x 48 output tiles
 // are formed (for N = 1000, 231 of them: one workgroup per CU) and each is
 // written with its mirror, which keeps X exactly symmetric by construction.
-// The four waves of a workgroup take the four quarters of the reduction
-// index; each wave owns the whole tile as 3 x 3 FP64 MFMA tiles and reads
-// its operands straight from X: the A operand of row tile i is
+// The eight waves of a workgroup (two per SIMD) take the eighths of the
+// reduction index; each wave owns the whole tile as 3 x 3 FP64 MFMA tiles
+// and reads its operands straight from X: the A operand of row tile i is
 // X[k][m0 + 16 i + ..] (a row of X, by symmetry) and the B operand of
 // column tile j is X[k][n0 + 16 j + ..], so the 16 lanes of each group read
 // 16 consecutive doubles.  Buffer loads return zero past the end of X (rows
 // k >= N), and the operands of the k-step four ahead are in flight while a
-// step's 9 MFMAs run.  The four
-// partial tiles are summed through LDS in one fixed order, then the update,
-// the tile and mirror writes and the partial sums run in the epilogue.
+// step's 9 MFMAs run.  The eight partial tiles are summed through LDS in one
+// fixed order, then the update, the tile and mirror writes and the partial
+// sums run in the epilogue.
 #include "kernels.h"
 
 #include <algorithm>
@@ -152,12 +152,12 @@ __device__ __forceinline__ void tc2_accumulate(const double* X, int N, int kbeg,
     }
 }
 
-__global__ __launch_bounds__(256) void tc2f_step_kernel(const double* __restrict__ X, double* __restrict__ Y, int N,
+__global__ __launch_bounds__(512) void tc2f_step_kernel(const double* __restrict__ X, double* __restrict__ Y, int N,
                                                         int n_occ, const double* __restrict__ part_in,
                                                         double* __restrict__ part_out, const int* __restrict__ st_in,
                                                         int* __restrict__ st_out, int out_id) {
-    __shared__ double sh[4];
-    __shared__ double red[4][TT][LDT];   // the four waves' partial tiles
+    __shared__ double sh[8];
+    __shared__ double red[4][TT][LDT];   // partial tiles: waves w and w + 4 in slot w
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nt = n_tiles_edge(N), tiles = nt * (nt + 1) / 2;
     if (st_in[S_DONE]) {
@@ -166,12 +166,12 @@ __global__ __launch_bounds__(256) void tc2f_step_kernel(const double* __restrict
     }
     // tr X and tr X^2 from the previous step's partial sums (same order everywhere)
     double a = 0.0, b = 0.0;
-    for (int i = tid; i < tiles; i += 256) {
+    for (int i = tid; i < tiles; i += 512) {
         a += part_in[2 * i];
         b += part_in[2 * i + 1];
     }
-    const double t1 = wg_sum_fixed<256>(a, sh);
-    const double t2 = wg_sum_fixed<256>(b, sh);
+    const double t1 = wg_sum_fixed<512>(a, sh);
+    const double t2 = wg_sum_fixed<512>(b, sh);
     int cd = st_in[S_CD];
     if (cd < 0) {
         if (fabs(t1 - t2) < 1e-11 * (double)max(1, n_occ)) cd = 1;
@@ -191,60 +191,77 @@ __global__ __launch_bounds__(256) void tc2f_step_kernel(const double* __restrict
     upper_tile48(L, nt, I, J);
     const int m0 = TT * I, n0 = TT * J;
     const bool diag = I == J;
-    // this wave's quarter of the reduction index, in whole 4-deep k-steps
-    const int Kq = ((N + 3) / 4 + 3) / 4 * 4;
+    // this wave's eighth of the reduction index, in whole 4-deep k-steps
+    const int Kq = ((N + 7) / 8 + 3) / 4 * 4;
     const int kbeg = wave * Kq, kend = min(N, kbeg + Kq), nks = max(0, (kend - kbeg + 3) / 4);
     const int r = lane & 15, g = lane >> 4;
     d4_t acc[3][3];
     if (diag) tc2_accumulate<true>(X, N, kbeg, nks, m0, n0, r, g, acc);
     else tc2_accumulate<false>(X, N, kbeg, nks, m0, n0, r, g, acc);
     // partial tiles to LDS: element q of lane (c, g) in MFMA tile (i, j) is
-    // row 16 i + 4 q + g, column 16 j + c
+    // row 16 i + 4 q + g, column 16 j + c.  Waves 4-7 write slot w - 4, then
+    // waves 0-3 add theirs to slot w (each lane to the entries it wrote).
+    if (wave >= 4) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+            for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) red[wave][16 * i + 4 * q + g][16 * j + r] = acc[i][j][q];
+                for (int q = 0; q < 4; ++q) red[wave - 4][16 * i + 4 * q + g][16 * j + r] = acc[i][j][q];
+    }
     __syncthreads();
-    // sum of the four quarters in one fixed order, the update, the tile's
-    // write (diagonal tiles: the upper triangle) and the partial sums
-    // (9 elements per thread; for 2X - X^2 the nine entries of X are loaded,
-    // from clamped addresses, before the first store)
-    constexpr int EP = TT * TT / 256;
-    static_assert(EP * 256 == TT * TT, "whole elements per thread");
+    if (wave < 4) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) red[wave][16 * i + 4 * q + g][16 * j + r] += acc[i][j][q];
+    }
+    __syncthreads();
+    // sum of the slots in one fixed order, the update, the tile's write
+    // (diagonal tiles: the upper triangle) and the partial sums; for 2X - X^2
+    // the entries of X are loaded, from clamped addresses, before the first
+    // store
+    constexpr int EP = (TT * TT + 511) / 512;
     double xo[EP];
     if (!sq) {
 #pragma unroll
         for (int t = 0; t < EP; ++t) {
-            const int e = tid + 256 * t, gm = min(m0 + e / TT, N - 1), gn = min(n0 + e % TT, N - 1);
+            const int e = min(tid + 512 * t, TT * TT - 1), gm = min(m0 + e / TT, N - 1), gn = min(n0 + e % TT, N - 1);
             xo[t] = X[(int64_t)gm * N + gn];
         }
     }
     double f2 = 0.0, tr = 0.0;
 #pragma unroll
     for (int t = 0; t < EP; ++t) {
-        const int e = tid + 256 * t, rr = e / TT, cc = e % TT, gm = m0 + rr, gn = n0 + cc;
-        double v = 0.0;
-        if (gm < N && gn < N && (!diag || rr <= cc)) {
-            const double x2 = ((red[0][rr][cc] + red[1][rr][cc]) + red[2][rr][cc]) + red[3][rr][cc];
-            v = sq ? x2 : 2.0 * xo[t] - x2;
-            Y[(int64_t)gm * N + gn] = v;
-            f2 += (gm == gn ? 1.0 : 2.0) * v * v;
-            if (gm == gn) tr += v;
+        const int e = tid + 512 * t;
+        if (e < TT * TT) {
+            const int rr = e / TT, cc = e % TT, gm = m0 + rr, gn = n0 + cc;
+            double v = 0.0;
+            if (gm < N && gn < N && (!diag || rr <= cc)) {
+                const double x2 = ((red[0][rr][cc] + red[1][rr][cc]) + red[2][rr][cc]) + red[3][rr][cc];
+                v = sq ? x2 : 2.0 * xo[t] - x2;
+                Y[(int64_t)gm * N + gn] = v;
+                f2 += (gm == gn ? 1.0 : 2.0) * v * v;
+                if (gm == gn) tr += v;
+            }
+            red[0][rr][cc] = v;   // each element is read and rewritten by one thread
         }
-        red[0][rr][cc] = v;   // each element is read and rewritten by one thread
     }
     __syncthreads();
     // mirror: Y[n][m] = Y[m][n], read transposed from LDS so that the writes
     // run along rows of Y
 #pragma unroll
     for (int t = 0; t < EP; ++t) {
-        const int e = tid + 256 * t, cc = e / TT, rr = e % TT, gm = m0 + rr, gn = n0 + cc;
-        if (gm < N && gn < N && (diag ? rr < cc : true)) Y[(int64_t)gn * N + gm] = red[0][rr][cc];
+        const int e = tid + 512 * t;
+        if (e < TT * TT) {
+            const int cc = e / TT, rr = e % TT, gm = m0 + rr, gn = n0 + cc;
+            if (gm < N && gn < N && (diag ? rr < cc : true)) Y[(int64_t)gn * N + gm] = red[0][rr][cc];
+        }
     }
-    tr = wg_sum_fixed<256>(tr, sh);
-    f2 = wg_sum_fixed<256>(f2, sh);
+    tr = wg_sum_fixed<512>(tr, sh);
+    f2 = wg_sum_fixed<512>(f2, sh);
     if (tid == 0) {
         part_out[2 * L] = tr;
         part_out[2 * L + 1] = f2;
@@ -277,7 +294,7 @@ hipError_t tc2f_step(const double* X, double* Y, int N, int n_occ, const double*
                      const int* st_in, int* st_out, int out_id, hipStream_t st) {
     // buffer offsets into X, including the prefetch past the last k-step, are 32-bit
     if ((int64_t)(N + 4 * PD + 8) * N * 8 > INT_MAX) return hipErrorInvalidValue;
-    tc2f_step_kernel<<<tc2f_tiles(N), 256, 0, st>>>(X, Y, N, n_occ, part_in, part_out, st_in, st_out, out_id);
+    tc2f_step_kernel<<<tc2f_tiles(N), 512, 0, st>>>(X, Y, N, n_occ, part_in, part_out, st_in, st_out, out_id);
     return hipGetLastError();
 }
 

@@ -251,13 +251,16 @@ def precision_leg(s, C, res64, args, P, torch, np, ms_fp64, scf_s64=None, K64=No
     N, na = s.N, s.n_aux
     out = {}
     # (final build?, SCF thresholds): plain forms iterate to just above their
-    # energy noise floor; with the final FP64 build the density's error enters
-    # the energy to second order, so 1e-6 / 3e-5 suffices (see batched_leg).
-    # BF16X3's iteration energies move by ~1e-5 Eh from rounding alone, so its
-    # energy test sits above that (1e-4) and the commutator test governs.
-    forms = (("fp32", P.FP32, ((False, (1e-7, 1e-5)), (True, (1e-6, 3e-5)))),
+    # energy noise floor (once converged, the iteration energy still moves by
+    # up to ~1.5e-7 Eh for FP32 and ~3e-8 Eh for BF16X6 from rounding alone,
+    # so a lower energy threshold is met only by chance); with the final FP64
+    # build the density's error enters the energy to second order, so
+    # 1e-6 / 3e-5 suffices (see batched_leg).  BF16X3's iteration energies
+    # move by ~1e-5 Eh, so its energy test sits above that (1e-4) and the
+    # commutator test governs.
+    forms = (("fp32", P.FP32, ((False, (3e-7, 1e-5)), (True, (1e-6, 3e-5)))),
              ("bf16x3", P.BF16X3, ((True, (1e-4, 3e-5)),)),
-             ("bf16x6", P.BF16X6, ((False, (1e-9, 1e-6)), (True, (1e-6, 3e-5)))))
+             ("bf16x6", P.BF16X6, ((False, (1e-7, 1e-6)), (True, (1e-6, 3e-5)))))
     for name, prec, scfs in forms:
         pr = P.RIProblem(s, device=dev, prec=prec)
         pr.build_3c()

@@ -353,7 +353,7 @@ __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* 
         acc[m][0] = acc[m][1] = f4_t{0, 0, 0, 0};
         acc64[m][0] = acc64[m][1] = d4_t{0, 0, 0, 0};
     }
-    const int nsl = nt * 4;
+    const int nsl = (N + 15) / 16;                 // 16-deep k-slices that hold a basis function
     load_b(0, 0);
     load_c(0, 0);
     for (int sl = 0; sl < nsl; ++sl) {
@@ -375,7 +375,7 @@ __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* 
             if (kk == 0 && more) load_b(Jn, kn);
             if (kk == 4 && more) load_c(Jn, kn);
         }
-        if ((sl & 3) == 3) {   // FP32 over one 64-wide nu tile, FP64 across tiles
+        if ((sl & 3) == 3 || !more) {   // FP32 over one 64-wide nu tile, FP64 across tiles
 #pragma unroll
             for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -402,10 +402,10 @@ __device__ __forceinline__ void x2_body_f32(int I, int P0, int i0, const float* 
 
 template <int MT>
 __global__ __launch_bounds__(256, 2) void x2_kernel_f32(const float* __restrict__ B, int nt, int64_t ntl,
-                                                        const float* __restrict__ Cf, int cld, int n_occ, int n_aux,
-                                                        float* __restrict__ Xt, int Npad) {
+                                                        const float* __restrict__ Cf, int cld, int N, int n_occ,
+                                                        int n_aux, float* __restrict__ Xt, int Npad) {
     const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    x2_body_f32<MT, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, nullptr, Cf, cld, 0,
+    x2_body_f32<MT, true>(L % gridDim.x, 2 * (L / gridDim.x), blockIdx.z * 128, B, nt, ntl, nullptr, Cf, cld, N,
                           n_occ, n_aux, Xt, Npad);
 }
 
@@ -808,7 +808,7 @@ hipError_t x_transform(const void* B, int prec, int N, int n_aux, int n_occ, con
         cpad_f32_kernel<<<(unsigned)(((int64_t)rows * cld + 255) / 256), 256, 0, st>>>(C, N, n_occ, rows, cld, Cf);
         RI_TRY(hipGetLastError());
         switch (mt) {
-#define XCASE(k) case k: x2_kernel_f32<k><<<grid, 256, 0, st>>>(b, nt, ntl, Cf, cld, n_occ, n_aux, x, Npad); break;
+#define XCASE(k) case k: x2_kernel_f32<k><<<grid, 256, 0, st>>>(b, nt, ntl, Cf, cld, N, n_occ, n_aux, x, Npad); break;
             XCASE(1) XCASE(2) XCASE(3) XCASE(4) XCASE(5) XCASE(6) XCASE(7) XCASE(8)
 #undef XCASE
             default: return hipErrorInvalidValue;

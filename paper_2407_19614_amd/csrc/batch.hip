@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64) void small_chol_b(const MolDesc* d, int n_mol) 
     __syncthreads();
     int* bad = m.state + ST_BAD;
     double* out = m.LinvM;
-    chol_inv64_wave(S, nb, [&](int) { atomicAdd(bad, 1); }, [&](int i, int c, double v) { out[i * 64 + c] = v; });
+    chol_inv64_blocked(S, nb, [&](int) { atomicAdd(bad, 1); }, [&](int i, int c, double v) { out[i * 64 + c] = v; });
 }
 
 __global__ void count_active_b(const MolDesc* d, int n_mol, int* out) {

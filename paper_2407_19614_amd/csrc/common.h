@@ -76,74 +76,128 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // wave (the workgroup is exactly 64 lanes), with no waits on other waves.
 // S[64][65] in LDS holds the block on entry (row-major; rows and columns at
 // or beyond nb set to the identity by the caller; only the lower triangle is
-// read) and the factor L (zero above the diagonal) on exit.
-// - Factor, right-looking: lane r keeps row r in registers.  At step j the
-//   pivot comes from lane j, every lane forms its L[r][j] and writes it to an
-//   LDS column, and the trailing update a[c] -= L[r][j] L[c][j] (r >= c)
-//   reads that column back as broadcast loads, 16 entries ahead of their use.
-// - Inverse, forward substitution: lane c forms column c of X = L^{-1},
-//   X[r][c] = (delta_rc - sum_{k<r} L[r][k] X[k][c]) / L[r][r], reading the
-//   rows of L as broadcast loads, and passes it to store(r, c, value) (row r
-//   across lanes is contiguous).
-// A pivot that is not positive is reported through bad(j) and replaced by 1.
-// Each pivot's reciprocal is formed once (hardware estimate and two Newton
-// steps, within an ulp of 1/piv) and multiplies instead of dividing, which
-// keeps the fully unrolled steps free of the division sequence.
+// read) and the factor L (zero above the diagonal) on exit; X = L^{-1}
+// (lower, zero above the diagonal) is passed entry by entry to
+// store(row, column, value).  A pivot that is not positive is reported
+// through bad(j) (the first one) and replaced by 1.
+// The work runs in 16 x 16 blocks.  For each diagonal block k: its 16 x 16
+// factor and the inverse of that factor by lanes 0-15 (lane r keeps row r;
+// broadcasts by lane reads; each pivot's reciprocal from the hardware
+// estimate and two Newton steps), and then the panel blocks
+// L_ik = A_ik (L_kk^{-1})^T and the trailing updates A_ij -= L_ik L_jk^T on
+// FP64 MFMA with operands read from S.  The latency chains are 16 steps
+// long instead of 64.  Then L^{-1} by block forward substitution,
+// X_ij = -L_ii^{-1} sum_{j<=k<i} L_ik X_kj, also on MFMA, with the X blocks
+// in registers: an accumulator tile (element q of lane (c, g) holds row
+// 4q + g of column c) is already the B operand of the next product over its
+// 16 rows.
 template <class Bad, class Store>
-__device__ __forceinline__ void chol_inv64_wave(double (*S)[65], int nb, Bad bad, Store store) {
-    const int lane = threadIdx.x & 63;
-    __shared__ double rdiag[64];
-    __shared__ double col[64];
-    double a[64];
-    int first_bad = 64;   // branch-free inside the unrolled steps; reported once
+__device__ __forceinline__ void chol_inv64_blocked(double (*S)[65], int nb, Bad bad, Store store) {
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    __shared__ double Di[4][16][17];   // inverses of the diagonal 16 x 16 factors
+    int first_bad = 64;
 #pragma unroll
-    for (int c = 0; c < 64; ++c) a[c] = S[lane][c];
-#pragma clang loop unroll(full)
-    for (int j = 0; j < 64; ++j) {
-        const double d = lane_bcast(a[j], j);
-        first_bad = (j < nb && !(d > 0.0) && first_bad == 64) ? j : first_bad;
-        const double piv = sqrt(d > 0.0 ? d : 1.0);
-        double rp = __builtin_amdgcn_rcp(piv);
-        rp = fma(rp, fma(-piv, rp, 1.0), rp);
-        rp = fma(rp, fma(-piv, rp, 1.0), rp);
-        rdiag[j] = rp;   // every lane writes the same value
-        a[j] = lane > j ? a[j] * rp : (lane == j ? piv : 0.0);
-        col[lane] = a[j];
-        __syncthreads();
-        // column j read back 16 entries at a time ahead of their updates
+    for (int kb = 0; kb < 4; ++kb) {
+        const int o = 16 * kb;
+        // factor of the diagonal block: lane r keeps its row
+        double a[16];
+        double rd = 1.0;
 #pragma unroll
-        for (int c0 = j + 1; c0 < 64; c0 += 16) {
-            double l[16];
+        for (int c = 0; c < 16; ++c) a[c] = (lane < 16 && c <= lane) ? S[o + r][o + c] : 0.0;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) l[t] = c0 + t < 64 ? col[c0 + t] : 0.0;
+        for (int j = 0; j < 16; ++j) {
+            const double d = lane_bcast(a[j], j);
+            first_bad = (o + j < nb && !(d > 0.0) && first_bad == 64) ? o + j : first_bad;
+            const double piv = sqrt(d > 0.0 ? d : 1.0);
+            double rp = __builtin_amdgcn_rcp(piv);
+            rp = fma(rp, fma(-piv, rp, 1.0), rp);
+            rp = fma(rp, fma(-piv, rp, 1.0), rp);
+            rd = lane == j ? rp : rd;
+            a[j] = lane > j ? a[j] * rp : (lane == j ? piv : 0.0);
 #pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (c0 + t < 64 && lane >= c0 + t) a[c0 + t] -= a[j] * l[t];
+            for (int c = j + 1; c < 16; ++c) a[c] = fma(-a[j], lane_bcast(a[j], c), a[c]);
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) S[o + r][o + c] = c <= lane ? a[c] : 0.0;
+        }
+        // inverse of the diagonal factor: lane c forms its column
+        {
+            double x[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                double v = rr == lane ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < rr; ++k) v -= lane_bcast(a[k], rr) * x[k];
+                x[rr] = v * lane_bcast(rd, rr);
+                if (lane < 16) Di[kb][rr][lane] = x[rr];
+            }
         }
         __syncthreads();
+        // panel: L_ik = A_ik (L_kk^{-1})^T, B[k][c] = Di[c][k]
+#pragma unroll
+        for (int ib = kb + 1; ib < 4; ++ib) {
+            d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                acc = mfma_f64(S[16 * ib + r][o + 4 * s4 + g], Di[kb][r][4 * s4 + g], acc);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][o + r] = acc[q];
+        }
+        __syncthreads();
+        // trailing: A_ij -= L_ik L_jk^T, B[k][c] = L_jk[c][k]
+#pragma unroll
+        for (int jb = kb + 1; jb < 4; ++jb)
+#pragma unroll
+            for (int ib = jb; ib < 4; ++ib) {
+                d4_t acc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = S[16 * ib + 4 * q + g][16 * jb + r];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    acc = mfma_f64(-S[16 * ib + r][o + 4 * s4 + g], S[16 * jb + r][o + 4 * s4 + g], acc);
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][16 * jb + r] = acc[q];
+                __syncthreads();
+            }
     }
     if (lane == 0 && first_bad < 64) bad(first_bad);
+    // zero above the diagonal (the diagonal blocks were written lower only)
 #pragma unroll
-    for (int c = 0; c < 64; ++c) S[lane][c] = c <= lane ? a[c] : 0.0;
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = ib + 1; jb < 4; ++jb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][16 * jb + r] = 0.0;
     __syncthreads();
-    // row r of L read 16 entries at a time ahead of its products, into four
-    // partial sums (independent chains)
-    double x[64];
-#pragma clang loop unroll(full)
-    for (int r = 0; r < 64; ++r) {
-        double v[4] = {r == lane ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+    // X = L^{-1}: X_ii = Di[i]; X_ij = -Di[i] sum_{j<=k<i} L_ik X_kj
+    d4_t X[4][4];
 #pragma unroll
-        for (int k0 = 0; k0 < r; k0 += 16) {
-            double l[16];
+    for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-            for (int t = 0; t < 16; ++t) l[t] = k0 + t < r ? S[r][k0 + t] : 0.0;
+        for (int q = 0; q < 4; ++q) X[ib][ib][q] = Di[ib][4 * q + g][r];
 #pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (k0 + t < r) v[t & 3] -= l[t] * x[k0 + t];
+    for (int ib = 1; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < ib; ++jb) {
+            d4_t t = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kb = jb; kb < ib; ++kb)
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) t = mfma_f64(S[16 * ib + r][16 * kb + 4 * s4 + g], X[kb][jb][s4], t);
+            d4_t xij = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) xij = mfma_f64(-Di[ib][r][4 * s4 + g], t[s4], xij);
+            X[ib][jb] = xij;
         }
-        x[r] = ((v[0] + v[1]) + (v[2] + v[3])) * rdiag[r];
-        store(r, lane, x[r]);
-    }
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) store(16 * ib + 4 * q + g, 16 * jb + r, jb <= ib ? X[ib][jb][q] : 0.0);
 }
 
 // ------------------------------------------------------------ launch helpers

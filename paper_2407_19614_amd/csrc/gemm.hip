@@ -314,7 +314,7 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int n, int64_
     for (int r = 0; r < 64; ++r)
         S[r][lane] = (r < nb && lane < nb) ? A[(int64_t)(o + r) * lda + o + lane] : (r == lane ? 1.0 : 0.0);
     __syncthreads();
-    chol_inv64_wave(S, nb, [&](int j) { atomicMin(bad, o + j); }, [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
+    chol_inv64_blocked(S, nb, [&](int j) { atomicMin(bad, o + j); }, [&](int i, int c, double v) { Dinv[i * 64 + c] = v; });
     __syncthreads();
     for (int r = 0; r < nb; ++r)
         if (lane < nb) A[(int64_t)(o + r) * lda + o + lane] = S[r][lane];

@@ -134,34 +134,58 @@ __device__ __forceinline__ void chol_inv64_blocked(double (*S)[65], int nb, Bad 
             }
         }
         __syncthreads();
-        // panel: L_ik = A_ik (L_kk^{-1})^T, B[k][c] = Di[c][k]
+        // panel: L_ik = A_ik (L_kk^{-1})^T, B[k][c] = Di[c][k]; the blocks are
+        // independent, so their MFMA chains interleave, and each block reads
+        // only the entries it rewrites (one wave: program order suffices)
+        {
+            d4_t acc[3];
 #pragma unroll
-        for (int ib = kb + 1; ib < 4; ++ib) {
-            d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+            for (int ib = kb + 1; ib < 4; ++ib) acc[ib - kb - 1] = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4)
-                acc = mfma_f64(S[16 * ib + r][o + 4 * s4 + g], Di[kb][r][4 * s4 + g], acc);
-            __syncthreads();
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double bk = Di[kb][r][4 * s4 + g];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][o + r] = acc[q];
+                for (int ib = kb + 1; ib < 4; ++ib)
+                    acc[ib - kb - 1] = mfma_f64(S[16 * ib + r][o + 4 * s4 + g], bk, acc[ib - kb - 1]);
+            }
+#pragma unroll
+            for (int ib = kb + 1; ib < 4; ++ib)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][o + r] = acc[ib - kb - 1][q];
         }
         __syncthreads();
-        // trailing: A_ij -= L_ik L_jk^T, B[k][c] = L_jk[c][k]
+        // trailing: A_ij -= L_ik L_jk^T, B[k][c] = L_jk[c][k]; the blocks read
+        // the panel and write disjoint blocks, so they interleave too
+        {
+            constexpr int NTB = 6;   // at most 6 blocks (k = 0)
+            d4_t acc[NTB];
+            int n = 0;
 #pragma unroll
-        for (int jb = kb + 1; jb < 4; ++jb)
+            for (int jb = kb + 1; jb < 4; ++jb)
 #pragma unroll
-            for (int ib = jb; ib < 4; ++ib) {
-                d4_t acc;
+                for (int ib = jb; ib < 4; ++ib, ++n)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = S[16 * ib + 4 * q + g][16 * jb + r];
+                    for (int q = 0; q < 4; ++q) acc[n][q] = S[16 * ib + 4 * q + g][16 * jb + r];
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
-                    acc = mfma_f64(-S[16 * ib + r][o + 4 * s4 + g], S[16 * jb + r][o + 4 * s4 + g], acc);
-                __syncthreads();
+            for (int s4 = 0; s4 < 4; ++s4) {
+                double pj[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][16 * jb + r] = acc[q];
-                __syncthreads();
+                for (int b = kb + 1; b < 4; ++b) pj[b] = S[16 * b + r][o + 4 * s4 + g];
+                n = 0;
+#pragma unroll
+                for (int jb = kb + 1; jb < 4; ++jb)
+#pragma unroll
+                    for (int ib = jb; ib < 4; ++ib, ++n) acc[n] = mfma_f64(-pj[ib], pj[jb], acc[n]);
             }
+            n = 0;
+#pragma unroll
+            for (int jb = kb + 1; jb < 4; ++jb)
+#pragma unroll
+                for (int ib = jb; ib < 4; ++ib, ++n)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) S[16 * ib + 4 * q + g][16 * jb + r] = acc[n][q];
+        }
+        __syncthreads();
     }
     if (lane == 0 && first_bad < 64) bad(first_bad);
     // zero above the diagonal (the diagonal blocks were written lower only)
@@ -178,20 +202,29 @@ __device__ __forceinline__ void chol_inv64_blocked(double (*S)[65], int nb, Bad 
     for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
         for (int q = 0; q < 4; ++q) X[ib][ib][q] = Di[ib][4 * q + g][r];
+    // block row i at a time; its blocks j < i are independent chains
 #pragma unroll
-    for (int ib = 1; ib < 4; ++ib)
+    for (int ib = 1; ib < 4; ++ib) {
+        d4_t t[3];
 #pragma unroll
-        for (int jb = 0; jb < ib; ++jb) {
-            d4_t t = d4_t{0.0, 0.0, 0.0, 0.0};
+        for (int jb = 0; jb < ib; ++jb) t[jb] = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kb = jb; kb < ib; ++kb)
+        for (int kb = 0; kb < ib; ++kb)
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) t = mfma_f64(S[16 * ib + r][16 * kb + 4 * s4 + g], X[kb][jb][s4], t);
-            d4_t xij = d4_t{0.0, 0.0, 0.0, 0.0};
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double l = S[16 * ib + r][16 * kb + 4 * s4 + g];
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) xij = mfma_f64(-Di[ib][r][4 * s4 + g], t[s4], xij);
-            X[ib][jb] = xij;
+                for (int jb = 0; jb <= kb; ++jb) t[jb] = mfma_f64(l, X[kb][jb][s4], t[jb]);
+            }
+#pragma unroll
+        for (int jb = 0; jb < ib; ++jb) X[ib][jb] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const double di = -Di[ib][r][4 * s4 + g];
+#pragma unroll
+            for (int jb = 0; jb < ib; ++jb) X[ib][jb] = mfma_f64(di, t[jb][s4], X[ib][jb]);
         }
+    }
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib)
 #pragma unroll

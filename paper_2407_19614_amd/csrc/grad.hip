@@ -31,59 +31,120 @@ __device__ void flush_add(double* g, int nc3, double* part) {
     for (int i = threadIdx.x; i < nc3; i += blockDim.x) row[i] += g[i];
 }
 
-// sum over all (mu, nu) of D h'_mu_nu - W S'_mu_nu.
+// F0(t) and F1(t) together.  Below t = 1, F1 from its Taylor series
+// F1(t) = sum_k (-t)^k / (k! (2k + 3)), 19 terms (the first omitted term is
+// below 3e-18), and F0 = 2t F1 + exp(-t) (the downward relation, all terms
+// positive); above, F0 = (sqrt(pi)/2) erf(sqrt t) / sqrt t and
+// F1 = (F0 - exp(-t)) / (2t).
+struct BoysTaylor {
+    double c[19];
+    constexpr BoysTaylor() : c() {
+        double f = 1.0;   // (-1)^k / k!
+        for (int k = 0; k < 19; ++k) {
+            c[k] = f / (2 * k + 3);
+            f = -f / (k + 1);
+        }
+    }
+};
+__device__ __forceinline__ void boys_f01(double t, double& f0, double& f1) {
+    const double e = exp(-t);
+    if (t < 1.0) {
+        constexpr BoysTaylor B{};
+        double s = B.c[18];
+#pragma unroll
+        for (int k = 17; k >= 0; --k) s = fma(s, t, B.c[k]);
+        f1 = s;
+        f0 = fma(2.0 * t, s, e);
+    } else {
+        const double r = sqrt(t);
+        f0 = 0.88622692545275801365 * erf(r) / r;
+        f1 = (f0 - e) / (2.0 * t);
+    }
+}
+
+// Sum over the wave; every lane receives the total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// sum over all (mu, nu) of D h'_mu_nu - W S'_mu_nu, taken over mu >= nu with
+// weight 2 off the diagonal (h, S, D and W are symmetric).  One lower pair
+// per thread; the nuclear-attraction loop over centres is uniform across the
+// wave, so each centre's share is summed over the wave before one LDS add.
+// g holds 3 * nc doubles of dynamic LDS.
 __global__ __launch_bounds__(256) void g1e_kernel(const double* xyz, const double* Z, int nc, const int32_t* fc,
                                                   const double* fe, int N, const double* D, const double* W,
                                                   double* part) {
-    __shared__ double g[3 * MAXC];
+    extern __shared__ double g[];
     for (int i = threadIdx.x; i < 3 * nc; i += 256) g[i] = 0.0;
     __syncthreads();
-    const int64_t total = (int64_t)N * N;
-    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        int mu = e / N, nu = e % N;
-        double d = D[e], w = W[e];
-        double a = fe[mu], b = fe[nu];
-        int ca = fc[mu], cb = fc[nu];
+    const int lane = threadIdx.x & 63;
+    const int64_t total = (int64_t)N * (N + 1) / 2;
+    const int64_t span = (int64_t)gridDim.x * 256;
+    const int64_t rounds = (total + span - 1) / span;   // every wave runs the same count: shuffles stay uniform
+    for (int64_t r = 0; r < rounds; ++r) {
+        const int64_t e = r * span + blockIdx.x * 256ll + threadIdx.x;
+        const bool in = e < total;
+        int mu = 0, nu = 0;
+        if (in) {
+            mu = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+            while ((int64_t)(mu + 1) * (mu + 2) / 2 <= e) ++mu;
+            while ((int64_t)mu * (mu + 1) / 2 > e) --mu;
+            nu = (int)(e - (int64_t)mu * (mu + 1) / 2);
+        }
+        const double wq = in ? (mu == nu ? 1.0 : 2.0) : 0.0;
+        const double d = wq * D[(int64_t)mu * N + nu], w = wq * W[(int64_t)mu * N + nu];
+        const double a = fe[mu], b = fe[nu];
+        const int ca = fc[mu], cb = fc[nu];
         const double* A = xyz + 3 * ca;
         const double* B = xyz + 3 * cb;
-        double p = a + b, ip = 1.0 / p, m = a * b * ip;
-        double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
-        double r2 = dx * dx + dy * dy + dz * dz;
-        double kn = norm_s(a) * norm_s(b) * exp(-m * r2);
+        const double p = a + b, ip = 1.0 / p, m = a * b * ip;
+        const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double kn = norm_s(a) * norm_s(b) * exp(-m * r2);
         // every term of this pair carries kn times D or W: below 1e-24 the pair
         // changes no gradient component by more than ~1e-20 (1e-14 over 1e6 pairs)
-        if (kn * (fabs(d) + fabs(w)) < 1e-24) continue;
-        double s = kn * pow(RI_PI * ip, 1.5);
-        double t = m * (3.0 - 2.0 * m * r2) * s;
+        const bool live = in && !(kn * (fabs(d) + fabs(w)) < 1e-24 * wq);
+        if (__ballot(live) == 0) continue;
+        const double s = kn * pow(RI_PI * ip, 1.5);
+        const double t = m * (3.0 - 2.0 * m * r2) * s;
         // dS/dA = -2 m (A-B) S ; dT/dA = -2 m (A-B) (2 m S + T)
-        double fS = -2.0 * m * s, fT = -2.0 * m * (2.0 * m * s + t);
-        double coef = d * fT - w * fS;
-        double gx = coef * dx, gy = coef * dy, gz = coef * dz;   // to atom of mu; minus to atom of nu
-        double Px = (a * A[0] + b * B[0]) * ip, Py = (a * A[1] + b * B[1]) * ip, Pz = (a * A[2] + b * B[2]) * ip;
+        const double fS = -2.0 * m * s, fT = -2.0 * m * (2.0 * m * s + t);
+        const double coef = live ? d * fT - w * fS : 0.0;
+        const double gx = coef * dx, gy = coef * dy, gz = coef * dz;   // to atom of mu; minus to atom of nu
+        const double Px = (a * A[0] + b * B[0]) * ip, Py = (a * A[1] + b * B[1]) * ip, Pz = (a * A[2] + b * B[2]) * ip;
+        const double dl = live ? d : 0.0;
         double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
         const double pre0 = 2.0 * RI_PI * ip * kn;
         for (int c = 0; c < nc; ++c) {
-            double zc = Z[c];
+            const double zc = Z[c];
             if (zc == 0.0) continue;
             const double* Cc = xyz + 3 * c;
-            double ex = Px - Cc[0], ey = Py - Cc[1], ez = Pz - Cc[2];
-            double x = p * (ex * ex + ey * ey + ez * ez);
-            double pre = zc * pre0;
-            double V = -pre * boys_f0(x);
-            double f1 = pre * boys_f1(x);
+            const double ex = Px - Cc[0], ey = Py - Cc[1], ez = Pz - Cc[2];
+            const double x = p * (ex * ex + ey * ey + ez * ez);
+            const double pre = zc * pre0;
+            double F0, F1;
+            boys_f01(x, F0, F1);
+            const double V = -pre * F0;
+            const double f1 = pre * F1;
             // dV/dA = V (-2 m (A-B)) + f1 2a (P-C);  dV/dB = V (2 m (A-B)) + f1 2b (P-C);  dV/dC = -f1 2p (P-C)
-            double va = -2.0 * m * V;
-            ax += d * (va * dx + f1 * 2.0 * a * ex);
-            ay += d * (va * dy + f1 * 2.0 * a * ey);
-            az += d * (va * dz + f1 * 2.0 * a * ez);
-            bx += d * (-va * dx + f1 * 2.0 * b * ex);
-            by += d * (-va * dy + f1 * 2.0 * b * ey);
-            bz += d * (-va * dz + f1 * 2.0 * b * ez);
-            double cc = -d * f1 * 2.0 * p;
-            lds_add3(g, c, cc * ex, cc * ey, cc * ez);
+            const double va = -2.0 * m * V;
+            ax += dl * (va * dx + f1 * 2.0 * a * ex);
+            ay += dl * (va * dy + f1 * 2.0 * a * ey);
+            az += dl * (va * dz + f1 * 2.0 * a * ez);
+            bx += dl * (-va * dx + f1 * 2.0 * b * ex);
+            by += dl * (-va * dy + f1 * 2.0 * b * ey);
+            bz += dl * (-va * dz + f1 * 2.0 * b * ez);
+            const double cc = -dl * f1 * 2.0 * p;
+            const double sx = wave_sum(cc * ex), sy = wave_sum(cc * ey), sz = wave_sum(cc * ez);
+            if (lane == 0) lds_add3(g, c, sx, sy, sz);
         }
-        lds_add3(g, ca, gx + ax, gy + ay, gz + az);
-        lds_add3(g, cb, -gx + bx, -gy + by, -gz + bz);
+        if (live) {
+            lds_add3(g, ca, gx + ax, gy + ay, gz + az);
+            lds_add3(g, cb, -gx + bx, -gy + by, -gz + bz);
+        }
     }
     flush(g, 3 * nc, part);
 }
@@ -116,45 +177,85 @@ __global__ __launch_bounds__(256) void g2c_kernel(const double* xyz, const int32
 }
 
 // sum_P sum_pairs w Y^P_mu_nu (mu nu|P)',  Y = c_P D_mu_nu - 2 (U^P C^T)_mu_nu,
-// U^P = C Xi^P.  Work items are (P, pair) with pairs fastest.
-// Auxiliary indices P0 .. P0 + np - 1: WY[P - P0][mu][nu] = (U^P C^T)_mu_nu
-// (mu >= nu); contributions are added to the block's partial row.
+// U^P = C Xi^P.  Auxiliary indices P0 .. P0 + np - 1: WY[P - P0][mu][nu] =
+// (U^P C^T)_mu_nu (mu >= nu); contributions are added to the block's partial
+// row.  Work items are (block of 256 pairs, chunk of G3_PC auxiliaries): one
+// pair per thread, its Gaussian product and prefactor formed once, then the
+// chunk's auxiliaries in turn (their exponents, normalisation and centres
+// staged in LDS).  The pair's two centres accumulate in registers; the
+// auxiliary's centre is the same for the whole wave at each step, so its
+// share is summed over the wave before one LDS add.  g holds 3 * nc doubles
+// of dynamic LDS.
+constexpr int G3_PC = 8;
+
 __global__ __launch_bounds__(256) void g3c_kernel(const double* xyz, const int32_t* fc, const double* fe,
                                                   const int32_t* ac, const double* ae, int P0, int np, int nc,
                                                   const int32_t* pairs, int64_t n_pairs, const double* WY,
                                                   const double* D, int N, const double* cv, double* part) {
-    __shared__ double g[3 * MAXC];
-    for (int i = threadIdx.x; i < 3 * nc; i += 256) g[i] = 0.0;
-    __syncthreads();
-    const int64_t total = (int64_t)np * n_pairs;
-    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int pl = (int)(e / n_pairs), P = P0 + pl;
-        int64_t q = e % n_pairs;
-        int mu = pairs[2 * q], nu = pairs[2 * q + 1];
-        const double v = WY[((int64_t)pl * N + mu) * N + nu];
-        double y = (cv[P] * D[(int64_t)mu * N + nu] - 2.0 * v) * (mu == nu ? 1.0 : 2.0);
-        double a = fe[mu], b = fe[nu];
-        int ca = fc[mu], cb = fc[nu], cp = ac[P];
+    extern __shared__ double g[];
+    __shared__ double sp[G3_PC][6];   // alpha, norm(alpha) / alpha, centre (3), c_P
+    __shared__ int sc[G3_PC];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < 3 * nc; i += 256) g[i] = 0.0;
+    const int64_t pb = (n_pairs + 255) / 256;
+    const int64_t items = pb * ((np + G3_PC - 1) / G3_PC);
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int pc0 = (int)(it / pb) * G3_PC, pcn = min(G3_PC, np - pc0);
+        const int64_t q = (it % pb) * 256 + tid;
+        __syncthreads();   // the previous item's reads of sp are done (g zeroed before the first)
+        if (tid < pcn) {
+            const int P = P0 + pc0 + tid, c = ac[P];
+            const double al = ae[P];
+            sp[tid][0] = al;
+            sp[tid][1] = norm_s(al) / al;
+            sp[tid][2] = xyz[3 * c];
+            sp[tid][3] = xyz[3 * c + 1];
+            sp[tid][4] = xyz[3 * c + 2];
+            sp[tid][5] = cv[P];
+            sc[tid] = c;
+        }
+        __syncthreads();
+        const bool live = q < n_pairs;
+        int mu = 0, nu = 0;
+        if (live) {
+            mu = pairs[2 * q];
+            nu = pairs[2 * q + 1];
+        }
+        const double wq = live ? (mu == nu ? 1.0 : 2.0) : 0.0;   // lanes past the pairs add zeros
+        const double dmn = D[(int64_t)mu * N + nu];
+        const double a = fe[mu], b = fe[nu];
+        const int ca = fc[mu], cb = fc[nu];
         const double* A = xyz + 3 * ca;
         const double* B = xyz + 3 * cb;
-        const double* R = xyz + 3 * cp;
-        double p = a + b, ip = 1.0 / p, m = a * b * ip;
-        double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
-        double kn = norm_s(a) * norm_s(b) * exp(-m * (dx * dx + dy * dy + dz * dz));
-        double al = ae[P], sa = p + al, w = p * al / sa;
-        double ex = (a * A[0] + b * B[0]) * ip - R[0], ey = (a * A[1] + b * B[1]) * ip - R[1],
-               ez = (a * A[2] + b * B[2]) * ip - R[2];
-        double x = w * (ex * ex + ey * ey + ez * ez);
-        double c0 = norm_s(al) * TWO_PI_52 / (p * al * sqrt(sa)) * kn;
-        double I = c0 * boys_f0(x);
-        double gg = c0 * boys_f1(x) * 2.0 * w;
-        // dI/dA = -2 m (A-B) I - gg (a/p) (P-R);  dI/dB = 2 m (A-B) I - gg (b/p) (P-R)
-        double t1 = -2.0 * m * I * y, ta = -gg * a * ip * y, tb = -gg * b * ip * y;
-        double Ax = t1 * dx + ta * ex, Ay = t1 * dy + ta * ey, Az = t1 * dz + ta * ez;
-        double Bx = -t1 * dx + tb * ex, By = -t1 * dy + tb * ey, Bz = -t1 * dz + tb * ez;
-        lds_add3(g, ca, Ax, Ay, Az);
-        lds_add3(g, cb, Bx, By, Bz);
-        lds_add3(g, cp, -(Ax + Bx), -(Ay + By), -(Az + Bz));
+        const double p = a + b, ip = 1.0 / p, m = a * b * ip;
+        const double dx = A[0] - B[0], dy = A[1] - B[1], dz = A[2] - B[2];
+        // c0 = norm(a) norm(b) norm(alpha) exp(-m |A-B|^2) 2 pi^{5/2} / (p alpha sqrt(p + alpha))
+        const double kp = norm_s(a) * norm_s(b) * exp(-m * (dx * dx + dy * dy + dz * dz)) * TWO_PI_52 * ip;
+        const double Px = (a * A[0] + b * B[0]) * ip, Py = (a * A[1] + b * B[1]) * ip, Pz = (a * A[2] + b * B[2]) * ip;
+        const double* wy = WY + ((int64_t)pc0 * N + mu) * N + nu;
+        double gax = 0, gay = 0, gaz = 0, gbx = 0, gby = 0, gbz = 0;
+        for (int k = 0; k < pcn; ++k) {
+            const double al = sp[k][0];
+            const double y = (sp[k][5] * dmn - 2.0 * wy[(int64_t)k * N * N]) * wq;
+            const double isa = 1.0 / (p + al), w = p * al * isa;
+            const double ex = Px - sp[k][2], ey = Py - sp[k][3], ez = Pz - sp[k][4];
+            double F0, F1;
+            boys_f01(w * (ex * ex + ey * ey + ez * ez), F0, F1);
+            const double c0 = kp * sp[k][1] * sqrt(isa);
+            const double I = c0 * F0, gg = c0 * F1 * 2.0 * w;
+            // dI/dA = -2 m (A-B) I - gg (a/p) (P-R);  dI/dB = 2 m (A-B) I - gg (b/p) (P-R)
+            const double t1 = -2.0 * m * I * y, ta = -gg * a * ip * y, tb = -gg * b * ip * y;
+            const double Ax = t1 * dx + ta * ex, Ay = t1 * dy + ta * ey, Az = t1 * dz + ta * ez;
+            const double Bx = -t1 * dx + tb * ex, By = -t1 * dy + tb * ey, Bz = -t1 * dz + tb * ez;
+            gax += Ax; gay += Ay; gaz += Az;
+            gbx += Bx; gby += By; gbz += Bz;
+            const double sx = wave_sum(Ax + Bx), sy = wave_sum(Ay + By), sz = wave_sum(Az + Bz);
+            if (lane == 0) lds_add3(g, sc[k], -sx, -sy, -sz);
+        }
+        if (live) {
+            lds_add3(g, ca, gax, gay, gaz);
+            lds_add3(g, cb, gbx, gby, gbz);
+        }
     }
     flush_add(g, 3 * nc, part);
 }
@@ -208,7 +309,7 @@ namespace ri {
 
 hipError_t grad_one_electron(const ri_system* s, const double* D, const double* W, double* part, hipStream_t st) {
     if (s->n_centres > MAXC) return hipErrorInvalidValue;
-    g1e_kernel<<<GRAD_BLOCKS, 256, 0, st>>>(s->xyz, s->Z, s->n_centres, s->fn_centre, s->fn_exp, s->n_fn, D, W, part);
+    g1e_kernel<<<GRAD_BLOCKS, 256, 3 * s->n_centres * sizeof(double), st>>>(s->xyz, s->Z, s->n_centres, s->fn_centre, s->fn_exp, s->n_fn, D, W, part);
     return hipGetLastError();
 }
 hipError_t grad_metric(const ri_system* s, const double* Zx, const double* c, double* part, hipStream_t st) {
@@ -233,7 +334,7 @@ hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n
         // WY[p] = U^{P0+p} C^T on the tiles holding mu >= nu
         RI_TRY(gemm_f64(false, true, N, N, n_occ, 1.0, U + (int64_t)P0 * N * n_occ, n_occ, (int64_t)N * n_occ, C,
                         n_occ, 0, 0.0, WY, N, (int64_t)N * N, np, 0, 1, st));
-        g3c_kernel<<<GRAD_BLOCKS, 256, 0, st>>>(s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, P0, np,
+        g3c_kernel<<<GRAD_BLOCKS, 256, 3 * s->n_centres * sizeof(double), st>>>(s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, P0, np,
                                                 s->n_centres, pairs, n_pairs, WY, D, N, c, part);
         RI_TRY(hipGetLastError());
     }

@@ -829,12 +829,13 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     } else {
         HIPC(x_any(B, prec, N, na, no, C, w.Cp, w.Xt, Bc, pairs, n_pairs, w.sw, st));
     }
-    HIPC(ri::gemm_f64(false, false, no, no, N, 1.0, (const double*)w.Xt, Npad, (int64_t)no * Npad, C, no, 0, 0.0,
-                      w.Bij, no, o2, na, 0, 0, st));
+    // one GEMM over all (P, i) rows: the rows of X^T are stacked P-major, as B_ij's
+    HIPC(ri::gemm_f64(false, false, na * no, no, N, 1.0, (const double*)w.Xt, Npad, 0, C, no, 0, 0.0, w.Bij, no, 0,
+                      1, 0, 0, st));
     // Xi = L^{-T} B_ij  (columns ij)
     HIPC(ri::gemm_f64(true, false, na, (int)o2, na, 1.0, Linv, na, 0, w.Bij, o2, 0, 0.0, w.Xi, o2, 0, 1, 2, 0, st));
     // Zx = -2 sum_ij Xi_ij Xi_ij^T (lower tiles); Z = c c^T + Zx inside the contraction
-    HIPC(ri::gemm_f64(false, true, na, na, (int)o2, -2.0, w.Xi, o2, 0, w.Xi, o2, 0, 0.0, w.Zx, na, 0, 1, 0, 1, st));
+    HIPC(ri::grad_metric_z(w.Xi, na, o2, w.WY, (int64_t)ri::grad_slab(N, na) * N * N, w.Zx, st));
     // U^P = C Xi^P  (stored over the X buffer)
     double* U = (double*)w.Xt;
     HIPC(ri::gemm_f64(false, false, N, no, no, 1.0, C, no, 0, w.Xi, no, o2, 0.0, U, no, (int64_t)N * no, na, 0, 0,

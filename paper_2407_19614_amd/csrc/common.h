@@ -239,12 +239,13 @@ namespace ri {
 // GEMM C = alpha op(A) op(B) + beta C over a batch (row-major, FP64 MFMA).
 // tri: 0 general; 1 op(A) lower triangular; 2 op(A) upper triangular;
 // 3 op(B) upper triangular.
-// lowerC: skip 64x64 tiles of C strictly above the diagonal.
+// lowerC: skip tiles of C strictly above the diagonal.
+// tile: 0 picks 64- or 128-wide tiles from the shape; 64 or 128 forces one.
 hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, int64_t lda, int64_t sA,
                     const double* B, int64_t ldb, int64_t sB, double beta,
                     double* C, int64_t ldc, int64_t sC, int batch, int tri, int lowerC,
-                    hipStream_t s);
+                    hipStream_t s, int tile = 0);
 
 // In-place Cholesky A = L L^T (lower; upper triangle zeroed) of an n x n
 // matrix, plus Linv = L^{-1} when Linv != nullptr.  dwork >= ceil(n/64)*4096

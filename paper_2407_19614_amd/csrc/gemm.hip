@@ -531,12 +531,12 @@ int device_cus() {
 hipError_t gemm_f64(bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
                     int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
                     double beta, double* C, int64_t ldc, int64_t sC, int batch, int tri,
-                    int lowerC, hipStream_t s) {
+                    int lowerC, hipStream_t s, int tile) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     // 128-wide tiles when they still give a few hundred workgroups and K is
     // long enough to amortise the larger tile's staging (short K: 64-wide)
     const int64_t big_tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128) * batch;
-    const bool big = M >= 128 && N >= 128 && big_tiles >= 200 && K > 128;
+    const bool big = tile ? tile == 128 : (M >= 128 && N >= 128 && big_tiles >= 200 && K > 128);
     if (big) {
         dim3 grid((N + 127) / 128, (M + 127) / 128, batch);
 #define G128(a, b) gemm_f64_128_kernel<a, b><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tri, lowerC)

@@ -274,12 +274,30 @@ __global__ __launch_bounds__(256) void gnuc_kernel(const double* xyz, const doub
     }
 }
 
-__global__ void greduce_kernel(const double* part, int rows, int nc3, double* grad) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nc3) return;
+// grad[i] = sum over rows of part[row][i]: one block per component, the rows
+// strided over the threads, then a fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void greduce_kernel(const double* part, int rows, int nc3, double* grad) {
+    const int i = blockIdx.x;
     double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += part[(int64_t)r * nc3 + i];
-    grad[i] = s;
+    for (int r = threadIdx.x; r < rows; r += 256) s += part[(int64_t)r * nc3 + i];
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[i] = sh[0];
+}
+
+// out[r][c] = sum_z part[z][r][c] for c <= r, z in order.
+__global__ void sum_lower_kernel(const double* part, int S, int64_t stride, int n, double* out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    if (e % n > e / n) return;
+    double s = part[e];
+    for (int z = 1; z < S; ++z) s += part[z * stride + e];
+    out[e] = s;
 }
 
 __global__ void gamma_dp_kernel(const int32_t* pairs, int64_t n_pairs, const double* C, int n_occ, double* dp) {
@@ -317,6 +335,30 @@ hipError_t grad_metric(const ri_system* s, const double* Zx, const double* c, do
     g2c_kernel<<<GRAD_BLOCKS, 256, 0, st>>>(s->xyz, s->aux_centre, s->aux_exp, s->n_aux, s->n_centres, Zx, c, part);
     return hipGetLastError();
 }
+// Zx = -2 Xi Xi^T on the lower tiles (Xi: n_aux x K, row-major).  The
+// reduction over K is split into S column ranges, one batch of the GEMM each,
+// into S partial products in `tmp` (tmp_elems doubles), then summed in order:
+// the unsplit form has only the lower 128-tiles as workgroups (300 at
+// n_aux = 3000), too few to fill the chip for a long K.
+hipError_t grad_metric_z(const double* Xi, int n_aux, int64_t K, double* tmp, int64_t tmp_elems, double* Zx,
+                         hipStream_t st) {
+    const int64_t n2 = (int64_t)n_aux * n_aux;
+    const int64_t t128 = (n_aux + 127) / 128, lower = t128 * (t128 + 1) / 2;
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>({(3 * 512 + lower / 2) / lower, 16, K / 256, tmp_elems / n2 - 1}));
+    if (S <= 1)
+        return gemm_f64(false, true, n_aux, n_aux, (int)K, -2.0, Xi, K, 0, Xi, K, 0, 0.0, Zx, n_aux, 0, 1, 0, 1, st);
+    // S equal ranges in one launch; the K % S columns left over, if any, in a
+    // launch of their own into one more partial
+    const int64_t kc = K / S, rem = K - S * kc;
+    RI_TRY(gemm_f64(false, true, n_aux, n_aux, (int)kc, -2.0, Xi, K, kc, Xi, K, kc, 0.0, tmp, n_aux, n2, S, 0, 1, st));
+    if (rem > 0) {
+        RI_TRY(gemm_f64(false, true, n_aux, n_aux, (int)rem, -2.0, Xi + S * kc, K, 0, Xi + S * kc, K, 0, 0.0,
+                        tmp + (int64_t)S * n2, n_aux, 0, 1, 0, 1, st));
+        ++S;
+    }
+    sum_lower_kernel<<<(unsigned)((n2 + 255) / 256), 256, 0, st>>>(tmp, S, n2, n_aux, Zx);
+    return hipGetLastError();
+}
 int grad_slab(int N, int n_aux) {
     const int64_t per = (int64_t)N * N * 8;
     return (int)std::max<int64_t>(1, std::min<int64_t>(n_aux, (int64_t(1) << 30) / per));
@@ -345,7 +387,7 @@ hipError_t grad_nuclear(const ri_system* s, double* part, hipStream_t st) {
     return hipGetLastError();
 }
 hipError_t grad_reduce(const double* part, int rows, int n_centres, double* grad, hipStream_t st) {
-    greduce_kernel<<<(3 * n_centres + 255) / 256, 256, 0, st>>>(part, rows, 3 * n_centres, grad);
+    greduce_kernel<<<3 * n_centres, 256, 0, st>>>(part, rows, 3 * n_centres, grad);
     return hipGetLastError();
 }
 hipError_t gamma_only(const double* Bc, const int32_t* pairs, int64_t n_pairs, int n_aux, int n_occ, const double* C,

@@ -113,6 +113,10 @@ namespace ri {
 constexpr int GRAD_BLOCKS = 1024;
 hipError_t grad_one_electron(const ri_system* s, const double* D, const double* W, double* part, hipStream_t st);
 hipError_t grad_metric(const ri_system* s, const double* Z, const double* c, double* part, hipStream_t st);
+// Zx = -2 Xi Xi^T (lower 128-tiles) for Xi [n_aux][K], split over K through
+// tmp (tmp_elems doubles of scratch).
+hipError_t grad_metric_z(const double* Xi, int n_aux, int64_t K, double* tmp, int64_t tmp_elems, double* Zx,
+                         hipStream_t st);
 // Three-centre term.  (U^P C^T)_mu_nu (U^P = C Xi^P, [n_aux][N][n_occ]) is formed
 // on MFMA for the lower 64 x 64 tiles, grad_slab(N, n_aux) auxiliary indices at
 // a time, into WY (workspace of grad_slab * N * N doubles), and the derivative

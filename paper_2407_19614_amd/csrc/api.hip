@@ -819,9 +819,16 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     HIPC(ri::gemm_f64(false, true, N, N, no, 2.0, C, no, 0, C, no, 0, 0.0, w.D, N, 0, 1, 0, 0, st));
     HIPC(ri::gemm_f64(false, false, N, N, N, 1.0, F, N, 0, w.D, N, 0, 0.0, w.T1, N, 0, 1, 0, 0, st));
     HIPC(ri::gemm_f64(false, false, N, N, N, 0.5, w.D, N, 0, w.T1, N, 0, 0.0, w.W, N, 0, 1, 0, 0, st));
-    // gamma = L^{-1} d and c = L^{-T} gamma = A^{-1} d
-    HIPC(ri::gamma_only(Bc, pairs, n_pairs, na, no, C, w.dpair, w.gamma, st));
-    HIPC(ri::gemm_f64(true, false, na, 1, na, 1.0, Linv, na, 0, w.gamma, 1, 0, 0.0, w.c, 1, 0, 1, 2, 0, st));
+    const int GB = ri::GRAD_BLOCKS;
+    const int64_t rowlen = 3 * (int64_t)nc;
+    // On the side stream, beside X and the exchange products (they share no
+    // buffers): gamma = L^{-1} d, c = L^{-T} gamma = A^{-1} d and the
+    // one-electron term.  Without a side stream they run here in turn.
+    Fork fk;
+    hipStream_t ss = fk.open(st) ? fk.side : st;
+    HIPC(ri::gamma_only(Bc, pairs, n_pairs, na, no, C, w.dpair, w.gamma, ss));
+    HIPC(ri::gemm_f64(true, false, na, 1, na, 1.0, Linv, na, 0, w.gamma, 1, 0, 0.0, w.c, 1, 0, 1, 2, 0, ss));
+    HIPC(ri::grad_one_electron(sys, w.D, w.W, w.part, ss));
     // B_ij^P = (C^T B^P C)_ij from X^P = B^P C
     if (prec == RI_FP32) {
         HIPC(x_any(B, prec, N, na, no, C, w.Cp, w.Xt32, Bc, pairs, n_pairs, w.sw, st));
@@ -840,9 +847,7 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     double* U = (double*)w.Xt;
     HIPC(ri::gemm_f64(false, false, N, no, no, 1.0, C, no, 0, w.Xi, no, o2, 0.0, U, no, (int64_t)N * no, na, 0, 0,
                       st));
-    const int GB = ri::GRAD_BLOCKS;
-    const int64_t rowlen = 3 * (int64_t)nc;
-    HIPC(ri::grad_one_electron(sys, w.D, w.W, w.part, st));
+    HIPC(fk.close());   // c and the one-electron rows are ready on st from here
     HIPC(ri::grad_metric(sys, w.Zx, w.c, w.part + GB * rowlen, st));
     HIPC(ri::grad_three_centre(sys, pairs, n_pairs, U, C, no, w.D, w.c, w.WY, w.part + 2 * GB * rowlen, st));
     HIPC(ri::grad_nuclear(sys, w.part + 3 * GB * rowlen, st));

@@ -376,8 +376,9 @@ hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n
         // WY[p] = U^{P0+p} C^T on the tiles holding mu >= nu
         RI_TRY(gemm_f64(false, true, N, N, n_occ, 1.0, U + (int64_t)P0 * N * n_occ, n_occ, (int64_t)N * n_occ, C,
                         n_occ, 0, 0.0, WY, N, (int64_t)N * N, np, 0, 1, st));
-        g3c_kernel<<<GRAD_BLOCKS, 256, 3 * s->n_centres * sizeof(double), st>>>(s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, P0, np,
-                                                s->n_centres, pairs, n_pairs, WY, D, N, c, part);
+        g3c_kernel<<<GRAD_BLOCKS, 256, 3 * s->n_centres * sizeof(double), st>>>(
+            s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, P0, np, s->n_centres, pairs, n_pairs, WY, D,
+            N, c, part);
         RI_TRY(hipGetLastError());
     }
     return hipSuccess;

@@ -144,7 +144,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* __restrict__ C,
     int64_t ldc, int64_t sC, int tri, int lowerC) {
     const int gx = gridDim.x, gy = gridDim.y;
-    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int L = tri != 0 ? lin : xcd_remap(lin, gx * gy * gridDim.z);   // as in the 128-wide form
     const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
     const int m0 = by * BM, n0 = bx * BN;
     if (lowerC && n0 > m0 + BM - 1) return;
@@ -281,7 +282,13 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_128_kernel(
     int64_t ldc, int64_t sC, int tri, int lowerC) {
     constexpr int TM = 128, TN = 128;
     const int gx = gridDim.x, gy = gridDim.y;
-    const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    // Contiguous runs of tiles per XCD keep shared operands in one L2, but with
+    // a triangular operand the work per tile changes along the rows (or
+    // columns), and with lowerC the number of live tiles per row does, so the
+    // XCD holding one end would carry most of the work: there the tiles go
+    // round-robin over the XCDs in launch order instead.
+    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int L = (tri != 0 || lowerC) ? lin : xcd_remap(lin, gx * gy * gridDim.z);
     const int bx = L % gx, by = (L / gx) % gy, bz = L / (gx * gy);
     const int m0 = by * TM, n0 = bx * TN;
     if (lowerC && n0 > m0 + TM - 1) return;

@@ -35,7 +35,9 @@ __device__ void flush_add(double* g, int nc3, double* part) {
 // F1(t) = sum_k (-t)^k / (k! (2k + 3)), 19 terms (the first omitted term is
 // below 3e-18), and F0 = 2t F1 + exp(-t) (the downward relation, all terms
 // positive); above, F0 = (sqrt(pi)/2) erf(sqrt t) / sqrt t and
-// F1 = (F0 - exp(-t)) / (2t).
+// F1 = (F0 - exp(-t)) / (2t).  From t = 40 on, erfc(sqrt t) < 1e-18 and
+// exp(-t) < 5e-18 relative to F0, so both drop out: F0 = (sqrt(pi)/2) / sqrt t
+// and F1 = F0 / (2t).
 struct BoysTaylor {
     double c[19];
     constexpr BoysTaylor() : c() {
@@ -47,18 +49,20 @@ struct BoysTaylor {
     }
 };
 __device__ __forceinline__ void boys_f01(double t, double& f0, double& f1) {
-    const double e = exp(-t);
     if (t < 1.0) {
         constexpr BoysTaylor B{};
         double s = B.c[18];
 #pragma unroll
         for (int k = 17; k >= 0; --k) s = fma(s, t, B.c[k]);
         f1 = s;
-        f0 = fma(2.0 * t, s, e);
-    } else {
+        f0 = fma(2.0 * t, s, exp(-t));
+    } else if (t < 40.0) {
         const double r = sqrt(t);
         f0 = 0.88622692545275801365 * erf(r) / r;
-        f1 = (f0 - e) / (2.0 * t);
+        f1 = (f0 - exp(-t)) / (2.0 * t);
+    } else {
+        f0 = 0.88622692545275801365 / sqrt(t);
+        f1 = f0 / (2.0 * t);
     }
 }
 

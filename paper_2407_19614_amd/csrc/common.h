@@ -43,6 +43,8 @@ __device__ __forceinline__ double boys_f0(double t) {
         return 1.0 + t * (-1.0 / 3.0 + t * (1.0 / 10.0 + t * (-1.0 / 42.0 + t * (1.0 / 216.0))));
     }
     double s = sqrt(t);
+    // from t = 40 on, erf(sqrt t) is 1 in double precision (erfc < 2e-19)
+    if (t >= 40.0) return 0.88622692545275801365 / s;
     return 0.88622692545275801365 * erf(s) / s;   // sqrt(pi)/2
 }
 

@@ -6,6 +6,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace {
 
@@ -264,6 +265,84 @@ __global__ __launch_bounds__(256) void g3c_kernel(const double* xyz, const int32
     flush_add(g, 3 * nc, part);
 }
 
+// WY[p][mu][nu] = sum_i U[p][mu][i] C[nu][i] on the lower 64 x 64 tiles
+// (mu, nu < N) for p in [0, np); U [np][N][K], C [N][K] row-major, K <= 8 KU.
+// One workgroup per (lower tile (I, J), group of WY_PB auxiliaries); each of
+// the 4 waves owns 32 x 32 of the tile as 2 x 2 FP64 MFMA blocks.  The tile
+// column's 64 rows of C stay in registers as B operands for the whole group;
+// U's rows stream from memory 16 B per lane.  MFMA step 2u + h of a lane in
+// group g (lanes 16 g ..) takes reduction index 8u + 2g + h, the same order
+// on both operands; indices >= K are zeroed in registers (a row's tail would
+// read the next row), and rows >= N read as zero through the buffer range.
+constexpr int WY_PB = 8;
+
+template <int KU>
+__global__ __launch_bounds__(256, 2) void wy_kernel(const double* __restrict__ U, const double* __restrict__ C,
+                                                    int N, int K, int np, double* __restrict__ WY) {
+    const int t = blockIdx.x;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    const int p0 = blockIdx.y * WY_PB, p1 = min(np, p0 + WY_PB);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int rowbytes = K * 8;
+    const __amdgpu_buffer_rsrc_t cr =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(C), (short)0, N * rowbytes, 0x00020000);
+    d2_t b[2][KU];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int nu = 64 * J + wn + 16 * j + li;
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int k0 = 8 * u + 2 * g;
+            d2_t v = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(cr, nu * rowbytes + k0 * 8, 0, 0));
+            if (k0 >= K) v[0] = 0.0;
+            if (k0 + 1 >= K) v[1] = 0.0;
+            b[j][u] = v;
+        }
+    }
+    for (int p = p0; p < p1; ++p) {
+        const __amdgpu_buffer_rsrc_t ur = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double*>(U + (int64_t)p * N * K), (short)0, N * rowbytes, 0x00020000);
+        d4_t acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        const int r0 = (64 * I + wm + li) * rowbytes, r1 = r0 + 16 * rowbytes;
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int k0 = 8 * u + 2 * g;
+            d2_t a0 = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(ur, r0 + k0 * 8, 0, 0));
+            d2_t a1 = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(ur, r1 + k0 * 8, 0, 0));
+            if (k0 >= K) { a0[0] = 0.0; a1[0] = 0.0; }
+            if (k0 + 1 >= K) { a0[1] = 0.0; a1[1] = 0.0; }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[0][j] = mfma_f64(a0[h], b[j][u][h], acc[0][j]);
+                    acc[1][j] = mfma_f64(a1[h], b[j][u][h], acc[1][j]);
+                }
+            }
+        }
+        double* out = WY + (int64_t)p * N * N;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = 64 * J + wn + 16 * j + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 64 * I + wm + 16 * i + 4 * r + g;
+                    if (row < N && col < N) out[(int64_t)row * N + col] = acc[i][j][r];
+                }
+            }
+    }
+}
+
 __global__ __launch_bounds__(256) void gnuc_kernel(const double* xyz, const double* Z, int nc, double* part) {
     for (int A = threadIdx.x; A < nc; A += 256) {
         double gx = 0, gy = 0, gz = 0;
@@ -368,6 +447,22 @@ int grad_slab(int N, int n_aux) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(n_aux, (int64_t(1) << 30) / per));
 }
 
+// WY[p] = U^p C^T on the lower 64 x 64 tiles for p < np (U [np][N][K]).
+hipError_t wy_products(const double* U, const double* C, int N, int K, int np, double* WY, hipStream_t st) {
+    const int ku = (K + 7) / 8, nt = (N + 63) / 64;
+    if (ku > 16 || (int64_t)N * K * 8 > INT_MAX)
+        return gemm_f64(false, true, N, N, K, 1.0, U, K, (int64_t)N * K, C, K, 0, 0.0, WY, N, (int64_t)N * N, np, 0, 1,
+                        st);
+    const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)((np + WY_PB - 1) / WY_PB));
+    switch (ku) {
+#define WYK(n) case n: wy_kernel<n><<<grid, 256, 0, st>>>(U, C, N, K, np, WY); break;
+        WYK(1) WYK(2) WYK(3) WYK(4) WYK(5) WYK(6) WYK(7) WYK(8)
+        WYK(9) WYK(10) WYK(11) WYK(12) WYK(13) WYK(14) WYK(15) WYK(16)
+#undef WYK
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n_pairs, const double* U,
                              const double* C, int n_occ, const double* D, const double* c, double* WY,
                              double* part, hipStream_t st) {
@@ -378,8 +473,7 @@ hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n
     for (int P0 = 0; P0 < na; P0 += ns) {
         const int np = std::min(ns, na - P0);
         // WY[p] = U^{P0+p} C^T on the tiles holding mu >= nu
-        RI_TRY(gemm_f64(false, true, N, N, n_occ, 1.0, U + (int64_t)P0 * N * n_occ, n_occ, (int64_t)N * n_occ, C,
-                        n_occ, 0, 0.0, WY, N, (int64_t)N * N, np, 0, 1, st));
+        RI_TRY(wy_products(U + (int64_t)P0 * N * n_occ, C, N, n_occ, np, WY, st));
         g3c_kernel<<<GRAD_BLOCKS, 256, 3 * s->n_centres * sizeof(double), st>>>(
             s->xyz, s->fn_centre, s->fn_exp, s->aux_centre, s->aux_exp, P0, np, s->n_centres, pairs, n_pairs, WY, D,
             N, c, part);

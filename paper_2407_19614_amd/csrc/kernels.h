@@ -120,7 +120,8 @@ hipError_t grad_metric_z(const double* Xi, int n_aux, int64_t K, double* tmp, in
 // Three-centre term.  (U^P C^T)_mu_nu (U^P = C Xi^P, [n_aux][N][n_occ]) is formed
 // on MFMA for the lower 64 x 64 tiles, grad_slab(N, n_aux) auxiliary indices at
 // a time, into WY (workspace of grad_slab * N * N doubles), and the derivative
-// kernel reads it at the significant pairs.
+// kernel reads it at the significant pairs.  For n_occ <= 128 the products run
+// in a kernel that keeps C's tile rows in registers across 8 auxiliaries.
 int grad_slab(int N, int n_aux);
 hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n_pairs, const double* U,
                              const double* C, int n_occ, const double* D, const double* c, double* WY,

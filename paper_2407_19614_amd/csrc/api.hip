@@ -845,8 +845,7 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     HIPC(ri::grad_metric_z(w.Xi, na, o2, w.WY, (int64_t)ri::grad_slab(N, na) * N * N, w.Zx, st));
     // U^P = C Xi^P  (stored over the X buffer)
     double* U = (double*)w.Xt;
-    HIPC(ri::gemm_f64(false, false, N, no, no, 1.0, C, no, 0, w.Xi, no, o2, 0.0, U, no, (int64_t)N * no, na, 0, 0,
-                      st));
+    HIPC(ri::u_products(C, w.Xi, N, no, na, U, st));
     HIPC(fk.close());   // c and the one-electron rows are ready on st from here
     HIPC(ri::grad_metric(sys, w.Zx, w.c, w.part + GB * rowlen, st));
     HIPC(ri::grad_three_centre(sys, pairs, n_pairs, U, C, no, w.D, w.c, w.WY, w.part + 2 * GB * rowlen, st));

@@ -343,6 +343,77 @@ __global__ __launch_bounds__(256, 2) void wy_kernel(const double* __restrict__ U
     }
 }
 
+// U[p][mu][i] = sum_j C[mu][j] Xi^p[i][j] for p in [0, np): C [N][K], Xi^p the
+// K x K block p of Xi [np][K][K].  Xi^p is symmetric (Xi = L^{-T} B_ij, and
+// each B_ij^P = C^T B^P C is), so this is C Xi^p read along its rows.  The
+// structure of wy_kernel with the roles swapped: C's 64 rows of the row tile
+// stay in registers as A operands for a group of WY_PB auxiliaries, and
+// Xi^p's rows stream in as B operands.  Grid: (row tile, column tile of the
+// n_occ columns) x groups of auxiliaries.
+template <int KU>
+__global__ __launch_bounds__(256, 2) void u_kernel(const double* __restrict__ C, const double* __restrict__ Xi,
+                                                   int N, int K, int np, double* __restrict__ U) {
+    const int nct = (K + 63) / 64;
+    const int I = blockIdx.x / nct, Jc = blockIdx.x % nct;
+    const int p0 = blockIdx.y * WY_PB, p1 = min(np, p0 + WY_PB);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g = lane >> 4;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int rowbytes = K * 8;
+    const __amdgpu_buffer_rsrc_t cr =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(C), (short)0, N * rowbytes, 0x00020000);
+    d2_t a[2][KU];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int mu = 64 * I + wm + 16 * i + li;
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int k0 = 8 * u + 2 * g;
+            d2_t v = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(cr, mu * rowbytes + k0 * 8, 0, 0));
+            if (k0 >= K) v[0] = 0.0;
+            if (k0 + 1 >= K) v[1] = 0.0;
+            a[i][u] = v;
+        }
+    }
+    for (int p = p0; p < p1; ++p) {
+        const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double*>(Xi + (int64_t)p * K * K), (short)0, K * rowbytes, 0x00020000);
+        d4_t acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        const int r0 = (64 * Jc + wn + li) * rowbytes, r1 = r0 + 16 * rowbytes;
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int k0 = 8 * u + 2 * g;
+            d2_t b0 = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(xr, r0 + k0 * 8, 0, 0));
+            d2_t b1 = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(xr, r1 + k0 * 8, 0, 0));
+            if (k0 >= K) { b0[0] = 0.0; b1[0] = 0.0; }
+            if (k0 + 1 >= K) { b0[1] = 0.0; b1[1] = 0.0; }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    acc[i][0] = mfma_f64(a[i][u][h], b0[h], acc[i][0]);
+                    acc[i][1] = mfma_f64(a[i][u][h], b1[h], acc[i][1]);
+                }
+            }
+        }
+        double* out = U + (int64_t)p * N * K;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = 64 * Jc + wn + 16 * j + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 64 * I + wm + 16 * i + 4 * r + g;
+                    if (row < N && col < K) out[(int64_t)row * K + col] = acc[i][j][r];
+                }
+            }
+    }
+}
+
 __global__ __launch_bounds__(256) void gnuc_kernel(const double* xyz, const double* Z, int nc, double* part) {
     for (int A = threadIdx.x; A < nc; A += 256) {
         double gx = 0, gy = 0, gz = 0;
@@ -459,6 +530,22 @@ hipError_t wy_products(const double* U, const double* C, int N, int K, int np, d
         WYK(1) WYK(2) WYK(3) WYK(4) WYK(5) WYK(6) WYK(7) WYK(8)
         WYK(9) WYK(10) WYK(11) WYK(12) WYK(13) WYK(14) WYK(15) WYK(16)
 #undef WYK
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+// U[p] = C Xi^p for p < np (Xi [np][K][K], each block symmetric; U [np][N][K]).
+hipError_t u_products(const double* C, const double* Xi, int N, int K, int np, double* U, hipStream_t st) {
+    const int ku = (K + 7) / 8;
+    if (ku > 16 || (int64_t)N * K * 8 > INT_MAX)
+        return gemm_f64(false, false, N, K, K, 1.0, C, K, 0, Xi, K, (int64_t)K * K, 0.0, U, K, (int64_t)N * K, np, 0,
+                        0, st);
+    const dim3 grid((unsigned)(((N + 63) / 64) * ((K + 63) / 64)), (unsigned)((np + WY_PB - 1) / WY_PB));
+    switch (ku) {
+#define UK(n) case n: u_kernel<n><<<grid, 256, 0, st>>>(C, Xi, N, K, np, U); break;
+        UK(1) UK(2) UK(3) UK(4) UK(5) UK(6) UK(7) UK(8)
+        UK(9) UK(10) UK(11) UK(12) UK(13) UK(14) UK(15) UK(16)
+#undef UK
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

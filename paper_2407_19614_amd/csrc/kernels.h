@@ -123,6 +123,9 @@ hipError_t grad_metric_z(const double* Xi, int n_aux, int64_t K, double* tmp, in
 // kernel reads it at the significant pairs.  For n_occ <= 128 the products run
 // in a kernel that keeps C's tile rows in registers across 8 auxiliaries.
 int grad_slab(int N, int n_aux);
+// U[p] = C Xi^p for p < np: C [N][K], Xi [np][K][K] with symmetric blocks,
+// U [np][N][K].
+hipError_t u_products(const double* C, const double* Xi, int N, int K, int np, double* U, hipStream_t st);
 hipError_t grad_three_centre(const ri_system* s, const int32_t* pairs, int64_t n_pairs, const double* U,
                              const double* C, int n_occ, const double* D, const double* c, double* WY,
                              double* part, hipStream_t st);

@@ -838,7 +838,7 @@ int32_t ri_gradient(const ri_system* sys, const int32_t* pairs, int64_t n_pairs,
     }
     // one GEMM over all (P, i) rows: the rows of X^T are stacked P-major, as B_ij's
     HIPC(ri::gemm_f64(false, false, na * no, no, N, 1.0, (const double*)w.Xt, Npad, 0, C, no, 0, 0.0, w.Bij, no, 0,
-                      1, 0, 0, st));
+                      1, 0, 0, st, 128));
     // Xi = L^{-T} B_ij  (columns ij)
     HIPC(ri::gemm_f64(true, false, na, (int)o2, na, 1.0, Linv, na, 0, w.Bij, o2, 0, 0.0, w.Xi, o2, 0, 1, 2, 0, st));
     // Zx = -2 sum_ij Xi_ij Xi_ij^T (lower tiles); Z = c c^T + Zx inside the contraction
